@@ -1,0 +1,476 @@
+"""CPU oracle of EVIS's per-frame event-generation path.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it.  The HIP library and its
+Python binding never import, call or link anything here, and this file uses
+nothing from them.
+
+Paper: "EVIS: Real-Time Event Camera Simulation with Multimodal Supervision
+in NVIDIA Isaac Sim".  Steps, in the paper's order:
+
+  a1  log_luminance          Sec. "HDR Event Formation Model", Eq. 3 and the
+                             log-intensity definition that follows it
+  a2  adaptive_k             Sec. "Bidirectional Motion Vector Warping": K-1
+                             intermediate frames per keyframe gap, K chosen so
+                             that no pixel moves more than one px per substep
+  a3  endpoint_depth         Eq. 7, depth at the B-side endpoint of A's motion
+  a4  splat_forward          Eq. 5 (q_A), the bilinear footprint, Eq. 6 z-buffer,
+                             Eq. 7 intermediate depth
+  a5  resolve_gather_blend   Eq. 5 (q_B) evaluated as a backward gather, the
+                             hole-aware blend of A and B
+  a6  emit_events            Eq. 4 (crossing count, polarity, residual-keeping
+                             reference update), Eq. 8 threshold mismatch, the
+                             refractory period of Sec. "Sensor Calibration and
+                             Non-idealities"
+  a7  pack_events            the (x, y, t, p) event tuple of Sec. "Problem
+                             Formulation" as an 8-byte record
+      step / interpolate     the whole per-pair path
+
+Precision.  Everything from the log intensity onwards is float32, every
+operation rounded to nearest in the order written: numpy float32 ufuncs and
+float32 scalars do exactly that and never fuse a multiply with an add.  The
+splat winner, the footprint corners and the crossing count are discrete
+decisions taken on those float32 values; the crossing count is the exact
+floor of the real quotient of the two float32 numbers (``fractions``).
+a1 is the one float64 step: it holds a transcendental and sits upstream of
+the exact part, so it is compared within a tolerance.
+
+Readings of the paper taken here (each is restated where it is used):
+  R1  B is warped by a backward bilinear gather at s = q - (1-f) m_B(q);
+      A by the depth-tested forward splat of Eq. 6.
+  R2  blend: L = lerp(A^, B^, alpha) where both are valid, the valid one
+      where only one is, lerp(L_A(q), L_B(q), alpha) where neither is;
+      alpha = f (BLEND_TIME) or alpha = 1 (BLEND_B_PRIMARY: B primary,
+      A only fills B's holes).
+  R3  the splat value is the winner's own intensity (winner-take-all).
+  R4  the footprint of a target position holds only the corners of its
+      containing cell whose bilinear weight is strictly positive.
+  R5  equal depths: the smaller source index wins.
+  R6  Eq. 7 endpoints: p_A = p, p_B = p - m_A(p); Z_B is sampled bilinearly
+      with the position clamped into the image.
+  R7  a source is invisible unless its intermediate depth is > 0 (NaN too).
+  R8  crossing count n = floor(|dL| / C) exactly, capped at N_MAX.
+  R9  the reference moves by fl(n * C) after all n crossings, also for
+      crossings the refractory period suppresses.
+  R10 crossing k of a substep is timed by linear interpolation of L between
+      the previous and the current sample; integer microseconds, floor.
+  R11 lerp(a, b, w) = a + w * (b - a); bilinear = two lerps along x, one
+      along y; x1 = min(x0 + 1, W - 1).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from fractions import Fraction
+from typing import Iterable, Optional
+
+import numpy as np
+
+F32 = np.float32
+EMPTY_KEY = np.uint64(0xFFFF_FFFF_FFFF_FFFF)
+N_MAX = 65535                 # R8: crossings per pixel-substep are capped here
+T_LAST_INIT = -(2 ** 30)      # "never fired": far enough back for any refractory period
+BLEND_TIME = 0
+BLEND_B_PRIMARY = 1
+REC709 = (0.2126, 0.7152, 0.0722)
+
+
+# ---------------------------------------------------------------------------
+# Small float32 building blocks (R11)
+# ---------------------------------------------------------------------------
+
+def lerp(a, b, w):
+    """a + w * (b - a), three float32 roundings."""
+    return a + w * (b - a)
+
+
+def pixel_coords(H: int, W: int):
+    """Float32 x (column) and y (row) of every pixel centre, shape [H][W]."""
+    yy, xx = np.mgrid[0:H, 0:W]
+    return xx.astype(F32), yy.astype(F32)
+
+
+def bilinear(img: np.ndarray, sx: np.ndarray, sy: np.ndarray) -> np.ndarray:
+    """Bilinear sample of float32 ``img`` at positions inside [0,W-1]x[0,H-1]."""
+    H, W = img.shape
+    fx0 = np.floor(sx)
+    fy0 = np.floor(sy)
+    wx = sx - fx0
+    wy = sy - fy0
+    x0 = fx0.astype(np.int64)
+    y0 = fy0.astype(np.int64)
+    x1 = np.minimum(x0 + 1, W - 1)
+    y1 = np.minimum(y0 + 1, H - 1)
+    top = lerp(img[y0, x0], img[y0, x1], wx)
+    bot = lerp(img[y1, x0], img[y1, x1], wx)
+    return lerp(top, bot, wy)
+
+
+def clamp_into(v: np.ndarray, hi: int) -> np.ndarray:
+    """Clamp into [0, hi]; NaN becomes 0."""
+    v = np.where(v > 0, v, F32(0))
+    return np.where(v < hi, v, F32(hi)).astype(F32)
+
+
+# ---------------------------------------------------------------------------
+# a1: log luminance (float64)
+# ---------------------------------------------------------------------------
+
+def log_luminance(x, eps: float = 1e-3) -> np.ndarray:
+    """Eq. 3 Rec.709 luminance of [..., 3] colour (a single channel is taken
+    as luminance already), then L = ln(Y + eps).  float64."""
+    x = np.asarray(x, np.float64)
+    if x.ndim >= 1 and x.shape[-1] == 3:
+        Y = REC709[0] * x[..., 0] + REC709[1] * x[..., 1] + REC709[2] * x[..., 2]
+    else:
+        Y = x
+    return np.log(Y + eps)
+
+
+# ---------------------------------------------------------------------------
+# a2: adaptive substep count
+# ---------------------------------------------------------------------------
+
+def adaptive_k(m_A: np.ndarray, m_B: np.ndarray, K_max: int) -> int:
+    """Smallest K >= 1 with K^2 >= max |m|^2 over both motion fields, at most K_max.
+
+    |m|^2 = dx^2 + dy^2 in float64 (both squares exact, one rounding in the
+    sum).  Pixels whose |m|^2 is not finite are left out.  With K so chosen,
+    no motion vector moves a pixel by more than one pixel per substep.
+    """
+    best = 0.0
+    for m in (m_A, m_B):
+        dx = m[..., 0].astype(np.float64)
+        dy = m[..., 1].astype(np.float64)
+        msq = dx * dx + dy * dy
+        msq = msq[np.isfinite(msq)]
+        if msq.size:
+            best = max(best, float(msq.max()))
+    need = math.ceil(Fraction(best))          # K^2 >= best  <=>  K^2 >= ceil(best)
+    K = math.isqrt(need)
+    if K * K < need:
+        K += 1
+    return int(min(max(K, 1), K_max))
+
+
+# ---------------------------------------------------------------------------
+# a3: endpoint depth (Eq. 7)
+# ---------------------------------------------------------------------------
+
+def endpoint_depth(Z_B: np.ndarray, m_A: np.ndarray) -> np.ndarray:
+    """Z_B at p_B = p - m_A(p), position clamped into the image (R6)."""
+    H, W = Z_B.shape
+    px, py = pixel_coords(H, W)
+    sx = clamp_into(px - m_A[..., 0], W - 1)
+    sy = clamp_into(py - m_A[..., 1], H - 1)
+    return bilinear(Z_B, sx, sy)
+
+
+# ---------------------------------------------------------------------------
+# a4: forward depth-tested splat of A (Eq. 5, Eq. 6, Eq. 7)
+# ---------------------------------------------------------------------------
+
+def substep_fraction(j: int, K: int):
+    """f = j / K in float32 (one rounding)."""
+    return F32(j) / F32(K)
+
+
+def splat_keys(m_A, Z_A, Zend, f):
+    """Per source: target q_A = p - f m_A(p), intermediate depth and the
+    packed key (float32 depth bits << 32 | source index)."""
+    H, W = Z_A.shape
+    px, py = pixel_coords(H, W)
+    qx = px - f * m_A[..., 0]
+    qy = py - f * m_A[..., 1]
+    zt = lerp(Z_A, Zend, f)
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (np.ascontiguousarray(zt).view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def footprint(qx, qy):
+    """Corners of the cell holding (qx, qy) with strictly positive bilinear
+    weight (R4): list of (cx, cy, selected) int64 arrays."""
+    x0f = np.floor(qx)
+    y0f = np.floor(qy)
+    fx = qx - x0f
+    fy = qy - y0f
+    x0 = x0f.astype(np.int64)
+    y0 = y0f.astype(np.int64)
+    allv = np.ones(qx.shape, bool)
+    return [(x0, y0, allv), (x0 + 1, y0, fx > 0), (x0, y0 + 1, fy > 0),
+            (x0 + 1, y0 + 1, (fx > 0) & (fy > 0))]
+
+
+def splat_forward(m_A, Z_A, Zend, f) -> np.ndarray:
+    """Eq. 6 z-buffer of A splatted to fraction f: uint64 key per target
+    pixel, EMPTY_KEY where nothing lands.  min over keys = nearest depth,
+    then smallest source index (R5)."""
+    H, W = Z_A.shape
+    qx, qy, zt, key = splat_keys(m_A, Z_A, Zend, f)
+    # R7 plus finiteness; positions far outside the image cannot reach it.
+    live = (zt > 0) & (np.abs(qx) < 2.0 ** 24) & (np.abs(qy) < 2.0 ** 24)
+    qx = np.where(live, qx, F32(-8))
+    qy = np.where(live, qy, F32(-8))
+    zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
+    for cx, cy, sel in footprint(qx, qy):
+        sel = sel & live & (cx >= 0) & (cx < W) & (cy >= 0) & (cy < H)
+        np.minimum.at(zbuf, (cy * W + cx)[sel], key[sel])
+    return zbuf.reshape(H, W)
+
+
+# ---------------------------------------------------------------------------
+# a5: resolve, backward gather of B, hole-aware blend
+# ---------------------------------------------------------------------------
+
+def resolve_gather_blend(zbuf, L_A, L_B, m_B, f, alpha):
+    """Intermediate log frame at fraction f.
+
+    A^ = L_A at the z-buffer winner (valid where something landed);
+    B^ = bilinear L_B at s = q - (1 - f) m_B(q) (valid where s is inside the
+    image); blend per R2.  Returns (L_f, validA, validB).
+    """
+    H, W = L_A.shape
+    g = F32(1) - f
+    ux, uy = pixel_coords(H, W)
+    key = zbuf.reshape(-1)
+    vA = key != EMPTY_KEY
+    src = np.where(vA, key & np.uint64(0xFFFF_FFFF), np.uint64(0)).astype(np.int64)
+    Ah = np.where(vA, L_A.reshape(-1)[src], F32(0)).reshape(H, W)
+    vA = vA.reshape(H, W)
+    sx = ux - g * m_B[..., 0]
+    sy = uy - g * m_B[..., 1]
+    vB = (sx >= 0) & (sx <= W - 1) & (sy >= 0) & (sy <= H - 1)
+    Bh = np.zeros((H, W), F32)
+    Bh[vB] = bilinear(L_B, sx[vB], sy[vB])
+    both = lerp(Ah, Bh, alpha)
+    hole = lerp(L_A, L_B, alpha)
+    out = np.where(vA & vB, both, np.where(vA, Ah, np.where(vB, Bh, hole)))
+    return out.astype(F32), vA, vB
+
+
+def blend_alpha(f, blend_mode: int):
+    return f if blend_mode == BLEND_TIME else F32(1)
+
+
+@dataclass
+class Pair:
+    """One keyframe pair A (t0_us) -> B (t1_us) of one environment."""
+    L_A: np.ndarray
+    L_B: np.ndarray
+    m_A: np.ndarray
+    m_B: np.ndarray
+    Z_A: np.ndarray
+    Z_B: np.ndarray
+    t0_us: int = 0
+    t1_us: int = 16667
+
+    @property
+    def shape(self):
+        return self.L_A.shape
+
+
+def substep_frames(pair: Pair, K: int, js: Iterable[int], blend_mode: int = BLEND_TIME):
+    """Yields (j, L_j, hole) for j in js; L_0 = L_A and L_K = L_B exactly;
+    hole bit0 = A invalid, bit1 = B invalid (0 at j = 0 and j = K)."""
+    Zend = None
+    H, W = pair.shape
+    for j in js:
+        if j == 0 or j == K:
+            yield j, (pair.L_A if j == 0 else pair.L_B).astype(F32), np.zeros((H, W), np.uint8)
+            continue
+        if Zend is None:
+            Zend = endpoint_depth(pair.Z_B, pair.m_A)
+        f = substep_fraction(j, K)
+        zbuf = splat_forward(pair.m_A, pair.Z_A, Zend, f)
+        L, vA, vB = resolve_gather_blend(zbuf, pair.L_A, pair.L_B, pair.m_B, f,
+                                         blend_alpha(f, blend_mode))
+        hole = ((~vA).astype(np.uint8) | ((~vB).astype(np.uint8) << 1))
+        yield j, L, hole
+
+
+def interpolate(pair: Pair, K: int, j_begin: int, j_end: int, blend_mode: int = BLEND_TIME):
+    """Stacked L_j for j in [j_begin, j_end) and their hole masks."""
+    Ls, holes = [], []
+    for _, L, h in substep_frames(pair, K, range(j_begin, j_end), blend_mode):
+        Ls.append(L)
+        holes.append(h)
+    return np.stack(Ls), np.stack(holes)
+
+
+# ---------------------------------------------------------------------------
+# a6: event emission (Eq. 4, Eq. 8, refractory period)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Sensor:
+    C_on: float = 0.2
+    C_off: float = 0.2
+    theta_on: Optional[np.ndarray] = None     # [H][W] float32, Eq. 8
+    theta_off: Optional[np.ndarray] = None
+    refractory_us: int = 0
+    K: int = 8                                # > 0 fixed, <= 0 adaptive
+    K_max: int = 64
+    blend_mode: int = BLEND_TIME
+
+    def thresholds(self, H, W):
+        on = self.theta_on if self.theta_on is not None else np.full((H, W), F32(self.C_on))
+        off = self.theta_off if self.theta_off is not None else np.full((H, W), F32(self.C_off))
+        return on.astype(F32), off.astype(F32)
+
+
+def crossing_count(a, c) -> int:
+    """Eq. 4: n = floor(a / c) of the exact real quotient of float32 a >= c > 0,
+    capped at N_MAX (R8); an infinite a gives N_MAX."""
+    if not math.isfinite(float(a)):
+        return N_MAX
+    n = Fraction(float(a)) // Fraction(float(c))
+    return int(min(n, N_MAX))
+
+
+def crossing_time_offset(j, k, R, c, positive, prev, cur, Dt, span) -> int:
+    """R10: integer-microsecond offset from t0 of crossing k in substep j.
+
+    The k-th crossing level is R +- k*c; its position between the previous
+    sample ``prev`` and the current ``cur`` is phi = (level - prev) / (cur - prev),
+    clamped to [0, 1] (1 when cur == prev, NaN -> 0); the offset is
+    floor((j - 1 + phi) * Dt), at most ``span``.
+    """
+    kc = F32(k) * c
+    lam = R + kc if positive else R - kc
+    den = cur - prev
+    if den == 0:
+        phi = F32(1)
+    else:
+        phi = (lam - prev) / den
+    if not phi >= 0:
+        phi = F32(0)
+    if phi > 1:
+        phi = F32(1)
+    v = (F32(j - 1) + phi) * Dt
+    return min(int(np.floor(v)), span)
+
+
+def substep_dt(t0_us: int, t1_us: int, K: int):
+    """Dt = fl32(fl32(t1 - t0) / fl32(K)), microseconds per substep."""
+    return F32(F32(t1_us - t0_us) / F32(K))
+
+
+class EventLog:
+    """Collects (x, y, t_us, p, env) tuples."""
+
+    def __init__(self):
+        self.rows = []
+
+    def add(self, x, y, t, p, env):
+        self.rows.append((x, y, t, p, env))
+
+    def array(self) -> np.ndarray:
+        if not self.rows:
+            return np.zeros((0, 5), np.int64)
+        return np.asarray(self.rows, np.int64)
+
+
+def emit_substep(j, prev, cur, R, tl, on, off, refractory_us, t0_us, Dt, span,
+                 env_id, log: EventLog, track_t_last: bool = True):
+    """Eq. 4 at substep j for every pixel; R and tl are updated in place."""
+    H, W = cur.shape
+    d = cur - R
+    positive = d > 0
+    c = np.where(positive, on, off)
+    a = np.abs(d)
+    hit = (a >= c) & (c > 0)              # n = 0 otherwise (NaN never hits)
+    for flat in np.flatnonzero(hit):
+        y, x = divmod(int(flat), W)
+        pos = bool(positive[y, x])
+        cc = c[y, x]
+        n = crossing_count(a[y, x], cc)
+        r0 = R[y, x]
+        for k in range(1, n + 1):
+            t = t0_us + crossing_time_offset(j, k, r0, cc, pos, prev[y, x], cur[y, x], Dt, span)
+            if refractory_us == 0 or t - int(tl[y, x]) >= refractory_us:
+                log.add(x, y, t, 1 if pos else 0, env_id)
+                if track_t_last:
+                    tl[y, x] = t
+        nc = F32(n) * cc
+        R[y, x] = r0 + nc if pos else r0 - nc
+
+
+def emit_events(S_seq, t0_us, t1_us, sensor: Sensor, L_ref, t_last=None, env_id=0):
+    """Events from caller-supplied frames S_seq[0..K] (S_seq[0] is the
+    previous sample; events come from j = 1..K).  Returns (events[N,5] as
+    x, y, t, p, env; L_ref'; t_last')."""
+    S_seq = [np.asarray(s, F32) for s in S_seq]
+    K = len(S_seq) - 1
+    H, W = S_seq[0].shape
+    on, off = sensor.thresholds(H, W)
+    R = np.array(L_ref, F32, copy=True)
+    track = t_last is not None
+    tl = np.array(t_last, np.int64, copy=True) if track else np.full((H, W), T_LAST_INIT, np.int64)
+    Dt = substep_dt(t0_us, t1_us, K)
+    span = t1_us - t0_us
+    log = EventLog()
+    for j in range(1, K + 1):
+        emit_substep(j, S_seq[j - 1], S_seq[j], R, tl, on, off, sensor.refractory_us,
+                     t0_us, Dt, span, env_id, log, track)
+    return log.array(), R, (tl.astype(np.int32) if track else None)
+
+
+# ---------------------------------------------------------------------------
+# The whole per-pair path
+# ---------------------------------------------------------------------------
+
+def choose_k(pair: Pair, sensor: Sensor) -> int:
+    if sensor.K > 0:
+        return int(sensor.K)
+    return adaptive_k(pair.m_A, pair.m_B, sensor.K_max)
+
+
+def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0):
+    """One keyframe pair: K, sub-frames (a3-a5) and events (a6), streaming
+    over j.  Returns (events[N,5], L_ref', t_last', K)."""
+    K = choose_k(pair, sensor)
+    H, W = pair.shape
+    on, off = sensor.thresholds(H, W)
+    R = np.array(L_ref, F32, copy=True)
+    track = t_last is not None
+    tl = np.array(t_last, np.int64, copy=True) if track else np.full((H, W), T_LAST_INIT, np.int64)
+    Dt = substep_dt(pair.t0_us, pair.t1_us, K)
+    span = pair.t1_us - pair.t0_us
+    log = EventLog()
+    prev = pair.L_A.astype(F32)
+    for j, L, _ in substep_frames(pair, K, range(1, K + 1), sensor.blend_mode):
+        emit_substep(j, prev, L, R, tl, on, off, sensor.refractory_us, pair.t0_us, Dt,
+                     span, env_id, log, track)
+        prev = L
+    return log.array(), R, (tl.astype(np.int32) if track else None), K
+
+
+# ---------------------------------------------------------------------------
+# a7: event record
+# ---------------------------------------------------------------------------
+
+def pack_events(ev: np.ndarray) -> np.ndarray:
+    """[N,5] (x, y, t, p, env) -> [N,2] int64 of (x | y<<11 | p<<22 | env<<23, t)."""
+    ev = np.asarray(ev, np.int64).reshape(-1, 5)
+    word = ev[:, 0] | (ev[:, 1] << 11) | (ev[:, 3] << 22) | (ev[:, 4] << 23)
+    return np.stack([word, ev[:, 2]], axis=1)
+
+
+def unpack_events(rec: np.ndarray) -> np.ndarray:
+    """Inverse of pack_events; accepts uint32/int32 words."""
+    rec = np.asarray(rec).reshape(-1, 2)
+    word = rec[:, 0].astype(np.int64) & 0xFFFF_FFFF
+    t = rec[:, 1].astype(np.int64)
+    x = word & 0x7FF
+    y = (word >> 11) & 0x7FF
+    p = (word >> 22) & 1
+    env = (word >> 23) & 0x1FF
+    return np.stack([x, y, t, p, env], axis=1)
+
+
+def canonical(ev: np.ndarray) -> np.ndarray:
+    """Events sorted by (env, t, y, x, p): the multiset in a fixed order."""
+    ev = np.asarray(ev, np.int64).reshape(-1, 5)
+    order = np.lexsort((ev[:, 3], ev[:, 0], ev[:, 1], ev[:, 2], ev[:, 4]))
+    return ev[order]

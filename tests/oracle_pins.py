@@ -1,0 +1,483 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+Each ``pin_*`` takes the oracle module and raises AssertionError when the
+oracle disagrees with a closed form, an invariant, a brute-force enumeration
+or a hand-worked golden case.  ``test_oracle_pins.py`` runs them on the real
+oracle; ``test_oracle_mutations.py`` runs them on copies of the oracle with
+one plausible mistake planted, and requires some pin to fail.
+"""
+from __future__ import annotations
+
+import math
+import os
+from decimal import Decimal, getcontext
+
+import numpy as np
+
+F32 = np.float32
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ---------------------------------------------------------------------------
+# helpers (inputs only; no oracle arithmetic)
+# ---------------------------------------------------------------------------
+
+def zero_motion_pair(o, L_A, L_B, Z=1.0, t0=0, t1=1000):
+    L_A = np.asarray(L_A, F32)
+    L_B = np.asarray(L_B, F32)
+    H, W = L_A.shape
+    m = np.zeros((H, W, 2), F32)
+    z = np.full((H, W), F32(Z))
+    return o.Pair(L_A, L_B, m, m.copy(), z, z.copy(), t0, t1)
+
+
+def read_golden(name):
+    kv, events = {}, []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            k, v = [s.strip() for s in line.split("=", 1)]
+            if k == "event":
+                events.append([int(t) for t in v.split()])
+            else:
+                kv[k] = v
+    return kv, events
+
+
+# ---------------------------------------------------------------------------
+# a1
+# ---------------------------------------------------------------------------
+
+def pin_log_luminance(o):
+    for v in (0.0, 1.0, 100.0, 1e3):
+        got = float(o.log_luminance(np.array([v, v, v])))
+        assert abs(got - math.log(v + 1e-3)) < 1e-12, (v, got)
+    v = math.exp(2.0) - 1e-3
+    assert abs(float(o.log_luminance(np.array([v, v, v]))) - 2.0) < 1e-12
+    w = (0.2126, 0.7152, 0.0722)
+    for ch in range(3):
+        x = np.zeros(3)
+        x[ch] = 1.0
+        assert abs(float(o.log_luminance(x)) - math.log(w[ch] + 1e-3)) < 1e-12
+    y = np.array([[0.5, 7.0]])
+    assert np.allclose(o.log_luminance(y), np.log(y + 1e-3), rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# a2
+# ---------------------------------------------------------------------------
+
+def _field(H, W, vec=None):
+    m = np.zeros((H, W, 2), F32)
+    if vec is not None:
+        m[1, 2] = vec
+    return m
+
+
+def pin_adaptive_k(o):
+    cases = [((0, 0), 1), ((0.5, 0), 1), ((1, 0), 1), ((1.0001, 0), 2), ((3, 4), 5),
+             ((3, 4.0001), 6), ((2.5, 0), 3), ((-7, 0), 7), ((0, -7.5), 8), ((100, 0), 64)]
+    for vec, want in cases:
+        got = o.adaptive_k(_field(4, 5, vec), _field(4, 5), 64)
+        assert got == want, (vec, got, want)
+    # the second field counts as much as the first
+    assert o.adaptive_k(_field(4, 5, (0.25, 0)), _field(4, 5, (6, 8)), 64) == 10
+    # non-finite vectors are left out
+    m = _field(4, 5, (3, 4))
+    m[0, 0] = (np.nan, 0)
+    m[2, 2] = (np.inf, 1)
+    assert o.adaptive_k(m, _field(4, 5), 64) == 5
+    # brute force: the smallest k with k*k >= the largest squared length
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        mA = rng.normal(0, rng.uniform(0.1, 20), size=(3, 4, 2)).astype(F32)
+        mB = rng.normal(0, rng.uniform(0.1, 20), size=(3, 4, 2)).astype(F32)
+        big = max(float(v[0]) ** 2 + float(v[1]) ** 2 for v in
+                  list(mA.reshape(-1, 2)) + list(mB.reshape(-1, 2)))
+        want = next(k for k in range(1, 10_000) if k * k >= big)
+        assert o.adaptive_k(mA, mB, 128) == min(want, 128)
+
+
+# ---------------------------------------------------------------------------
+# a3
+# ---------------------------------------------------------------------------
+
+def pin_endpoint_depth_affine(o):
+    H, W = 8, 9
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    Z_B = (1.0 + 0.5 * xx + 0.25 * yy).astype(F32)
+    m_A = np.zeros((H, W, 2), F32)
+    m_A[..., 0] = -1.5
+    m_A[..., 1] = 0.75
+    got = o.endpoint_depth(Z_B, m_A).astype(np.float64)
+    sx = np.minimum(xx + 1.5, W - 1)
+    sy = np.maximum(yy - 0.75, 0.0)
+    want = 1.0 + 0.5 * sx + 0.25 * sy
+    assert np.array_equal(got, want), np.abs(got - want).max()
+
+
+# ---------------------------------------------------------------------------
+# a4
+# ---------------------------------------------------------------------------
+
+def pin_splat_bruteforce(o):
+    """Scatter z-buffer == per-target enumeration of every covering source."""
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        H, W = 8, 8
+        if trial % 2 == 0:
+            m = (np.round(rng.uniform(-3, 3, size=(H, W, 2)) * 4) / 4).astype(F32)
+        else:
+            m = rng.uniform(-3, 3, size=(H, W, 2)).astype(F32)
+        Z_A = rng.choice(np.array([1.0, 2.0, 3.0, -1.0], F32), size=(H, W))
+        Z_B = rng.choice(np.array([1.0, 2.0, 3.0], F32), size=(H, W))
+        Zend = o.endpoint_depth(Z_B, m)
+        for K, j in ((8, 3), (4, 2), (7, 5)):
+            f = F32(j) / F32(K)
+            zbuf = o.splat_forward(m, Z_A, Zend, f)
+            for ty in range(H):
+                for tx in range(W):
+                    best = None
+                    for py in range(H):
+                        for px in range(W):
+                            qx = F32(px) - f * m[py, px, 0]
+                            qy = F32(py) - f * m[py, px, 1]
+                            zt = Z_A[py, px] + f * (Zend[py, px] - Z_A[py, px])
+                            if not zt > 0:
+                                continue
+                            x0, y0 = math.floor(qx), math.floor(qy)
+                            okx = tx == x0 or (qx - x0 > 0 and tx == x0 + 1)
+                            oky = ty == y0 or (qy - y0 > 0 and ty == y0 + 1)
+                            if okx and oky:
+                                cand = (float(zt), py * W + px)
+                                if best is None or cand < best:
+                                    best = cand
+                    key = int(zbuf[ty, tx])
+                    if best is None:
+                        assert key == 0xFFFF_FFFF_FFFF_FFFF, (trial, tx, ty)
+                    else:
+                        depth = float(np.uint32(key >> 32).view(F32))
+                        assert (depth, key & 0xFFFF_FFFF) == best, (trial, tx, ty, best)
+
+
+def pin_integer_translation(o):
+    """Content moving by an integer u per substep (K a power of two):
+    every sub-frame is an exact shift of L_A where both ends are in view."""
+    rng = np.random.default_rng(3)
+    H, W, K = 16, 20, 4
+    for u in ((1, 2), (-2, 1), (0, -1)):
+        L_A = rng.normal(0, 2, size=(H, W)).astype(F32)
+        L_B = rng.normal(0, 2, size=(H, W)).astype(F32)
+        ux, uy = u
+        for y in range(H):
+            for x in range(W):
+                sx, sy = x - K * ux, y - K * uy
+                if 0 <= sx < W and 0 <= sy < H:
+                    L_B[y, x] = L_A[sy, sx]
+        m = np.zeros((H, W, 2), F32)
+        m[..., 0] = -K * ux
+        m[..., 1] = -K * uy
+        Z = np.full((H, W), F32(2.0))
+        pair = o.Pair(L_A, L_B, m, m.copy(), Z, Z.copy())
+        Ls, _ = o.interpolate(pair, K, 1, K)
+        for j in range(1, K):
+            Lj = Ls[j - 1]
+            for y in range(H):
+                for x in range(W):
+                    ax, ay = x - j * ux, y - j * uy            # A source
+                    bx, by = x + (K - j) * ux, y + (K - j) * uy  # B sample
+                    a_in = 0 <= ax < W and 0 <= ay < H
+                    b_in = 0 <= bx < W and 0 <= by < H
+                    if a_in:
+                        assert Lj[y, x] == L_A[ay, ax], (u, j, x, y)
+                    elif b_in:
+                        assert Lj[y, x] == L_B[by, bx], (u, j, x, y)
+
+
+def pin_static_scene(o):
+    rng = np.random.default_rng(5)
+    H, W, K = 12, 10, 7
+    L = rng.normal(0, 3, size=(H, W)).astype(F32)
+    m = np.zeros((H, W, 2), F32)
+    Z_A = rng.uniform(0.5, 5, size=(H, W)).astype(F32)
+    Z_A[2:5, 3:6] = -1.0                      # some A sources invisible
+    Z_B = rng.uniform(0.5, 5, size=(H, W)).astype(F32)
+    pair = o.Pair(L, L.copy(), m, m.copy(), Z_A, Z_B)
+    for mode in (o.BLEND_TIME, o.BLEND_B_PRIMARY):
+        Ls, _ = o.interpolate(pair, K, 0, K + 1, mode)
+        for j in range(K + 1):
+            assert np.array_equal(Ls[j], L), (mode, j)
+
+
+def _square_scene(u=(2, 1), K=4):
+    H, W = 24, 24
+    ux, uy = u
+    Z_A = np.full((H, W), F32(5.0))
+    Z_B = np.full((H, W), F32(5.0))
+    m_A = np.zeros((H, W, 2), F32)
+    sq = (slice(4, 10), slice(4, 10))
+    Z_A[sq] = 1.0
+    m_A[sq + (0,)] = -K * ux
+    m_A[sq + (1,)] = -K * uy
+    Z_B[4 + K * uy:10 + K * uy, 4 + K * ux:10 + K * ux] = 1.0
+    return H, W, Z_A, Z_B, m_A
+
+
+def pin_occlusion(o):
+    """A near square moving over a static far background: it wins wherever
+    it lands, and the background it uncovers is a hole of the A splat."""
+    K, u = 4, (2, 1)
+    H, W, Z_A, Z_B, m_A = _square_scene(u, K)
+    Zend = o.endpoint_depth(Z_B, m_A)
+    for j in (1, 2, 3):
+        zbuf = o.splat_forward(m_A, Z_A, Zend, F32(j) / F32(K))
+        idx = (zbuf & np.uint64(0xFFFF_FFFF)).astype(np.int64)
+        for y in range(H):
+            for x in range(W):
+                sx, sy = x - j * u[0], y - j * u[1]
+                if 4 <= sx < 10 and 4 <= sy < 10:
+                    assert idx[y, x] == sy * W + sx, (j, x, y)
+                elif 4 <= x < 10 and 4 <= y < 10:
+                    assert zbuf[y, x] == o.EMPTY_KEY, (j, x, y)
+                else:
+                    assert idx[y, x] == y * W + x, (j, x, y)
+
+
+def pin_depth_interp(o):
+    """Eq. 7 on one static source: Z~ = (1-f) Z_A + f Z_B, exact here."""
+    H, W = 3, 3
+    m = np.zeros((H, W, 2), F32)
+    Z_A = np.full((H, W), F32(2.0))
+    Z_B = np.full((H, W), F32(4.0))
+    Zend = o.endpoint_depth(Z_B, m)
+    for K, j, want in ((4, 1, 2.5), (4, 3, 3.5), (8, 1, 2.25)):
+        zbuf = o.splat_forward(m, Z_A, Zend, F32(j) / F32(K))
+        depth = (zbuf >> np.uint64(32)).astype(np.uint32).view(F32)
+        assert np.all(depth == F32(want)), (K, j, depth)
+
+
+def pin_tie_break(o):
+    """Equal depths: the smaller source index wins; a nearer one beats both."""
+    H, W, K = 1, 4, 2
+    m = np.zeros((H, W, 2), F32)
+    m[0, 0, 0] = -2.0      # lands on x = 1 at f = 1/2
+    m[0, 2, 0] = 2.0       # lands on x = 1 at f = 1/2
+    Z = np.full((H, W), F32(3.0))
+    Zend = o.endpoint_depth(Z, m)
+    zbuf = o.splat_forward(m, Z, Zend, F32(1) / F32(K))
+    assert int(zbuf[0, 1]) & 0xFFFF_FFFF == 0
+    Z2 = Z.copy()
+    Z2[0, 2] = 2.5                            # Z~ = 2.5 + (3 - 2.5) / 2 = 2.75 < 3
+    zbuf = o.splat_forward(m, Z2, o.endpoint_depth(Z, m), F32(1) / F32(K))
+    assert int(zbuf[0, 1]) & 0xFFFF_FFFF == 2
+    assert zbuf[0, 0] == o.EMPTY_KEY and int(zbuf[0, 3]) & 0xFFFF_FFFF == 3
+
+
+# ---------------------------------------------------------------------------
+# a5
+# ---------------------------------------------------------------------------
+
+def pin_gather_affine(o):
+    """Bilinear sampling reproduces an affine L_B exactly at dyadic points."""
+    H, W, K = 12, 12, 4
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    L_B = (0.5 + 0.25 * xx - 0.125 * yy).astype(F32)
+    L_A = np.zeros((H, W), F32)
+    m_A = np.zeros((H, W, 2), F32)
+    m_B = np.zeros((H, W, 2), F32)
+    m_B[..., 0] = 1.5
+    m_B[..., 1] = -0.75
+    Z = np.full((H, W), F32(-1.0))           # no A source is visible
+    pair = o.Pair(L_A, L_B, m_A, m_B, Z, Z.copy())
+    Ls, holes = o.interpolate(pair, K, 1, K)
+    for j in range(1, K):
+        g = 1.0 - j / K
+        sx, sy = xx - g * 1.5, yy + g * 0.75
+        inside = (sx >= 0) & (sx <= W - 1) & (sy >= 0) & (sy <= H - 1)
+        want = np.where(inside, 0.5 + 0.25 * sx - 0.125 * sy, (j / K) * L_B)
+        assert np.array_equal(Ls[j - 1].astype(np.float64), want), j
+        assert np.array_equal(holes[j - 1], np.where(inside, 1, 3)), j
+
+
+def pin_blend_modes(o):
+    H, W, K = 2, 3, 4
+    L_A = np.full((H, W), F32(0.5))
+    L_B = np.full((H, W), F32(1.5))
+    m = np.zeros((H, W, 2), F32)
+    far = np.zeros((H, W, 2), F32)
+    far[..., 0] = 100.0                      # B sample always outside the image
+    Zok = np.full((H, W), F32(1.0))
+    Zbad = np.full((H, W), F32(-1.0))
+    cases = [  # (m_B, Z, TIME value at j=1, B_PRIMARY value at j=1)
+        (m, Zok, 0.75, 1.5),                 # both valid
+        (far, Zok, 0.5, 0.5),                # only A valid
+        (m, Zbad, 1.5, 1.5),                 # only B valid
+        (far, Zbad, 0.75, 1.5),              # neither: lerp(L_A(q), L_B(q), alpha)
+    ]
+    for m_B, Z, want_t, want_b in cases:
+        pair = o.Pair(L_A, L_B, m, m_B, Z, Z.copy())
+        lt, _ = o.interpolate(pair, K, 1, 2, o.BLEND_TIME)
+        lb, _ = o.interpolate(pair, K, 1, 2, o.BLEND_B_PRIMARY)
+        assert np.all(lt == F32(want_t)) and np.all(lb == F32(want_b)), (want_t, want_b)
+
+
+# ---------------------------------------------------------------------------
+# a6
+# ---------------------------------------------------------------------------
+
+def pin_goldens(o):
+    for name in ("ramp_refractory.txt", "multi_crossing.txt", "exact_floor_off.txt"):
+        kv, want = read_golden(name)
+        H, W = int(kv["H"]), int(kv["W"])
+        pair = zero_motion_pair(o, np.full((H, W), float(kv["L_A"])),
+                                np.full((H, W), float(kv["L_B"])),
+                                t0=int(kv["t0"]), t1=int(kv["t1"]))
+        C = float(kv["C"])
+        sensor = o.Sensor(C_on=C, C_off=C, refractory_us=int(kv["refractory"]),
+                          K=int(kv["K"]))
+        L_ref = np.zeros((H, W), F32)
+        t_last = np.full((H, W), o.T_LAST_INIT, np.int32)
+        ev, R, _, K = o.step(pair, sensor, L_ref, t_last)
+        got = sorted((int(e[0]), int(e[1]), int(e[2]), int(e[3])) for e in ev)
+        assert got == sorted(tuple(e) for e in want), (name, got)
+        assert float(R[0, 0]) == float(Decimal(kv["L_ref_end"])), (name, float(R[0, 0]))
+
+
+def pin_uniform_ramp(o):
+    """A uniform log ramp dL with zero motion gives floor(dL / C) events per
+    pixel, evenly spaced in time (interpolation is exact for a ramp)."""
+    rng = np.random.default_rng(9)
+    H, W, K, C = 6, 7, 8, 0.2
+    t0, t1 = 1000, 1000 + 16667
+    L_A = rng.uniform(-2, 2, size=(H, W)).astype(F32)
+    L_B = (L_A + F32(1.1)).astype(F32)
+    pair = zero_motion_pair(o, L_A, L_B, t0=t0, t1=t1)
+    ev, R, _, _ = o.step(pair, o.Sensor(C_on=C, C_off=C, K=K), L_A.copy())
+    for y in range(H):
+        for x in range(W):
+            sel = ev[(ev[:, 0] == x) & (ev[:, 1] == y)]
+            dL = float(L_B[y, x]) - float(L_A[y, x])
+            n = math.floor(dL / float(F32(C)))
+            assert len(sel) == n == 5, (x, y, len(sel))
+            assert np.all(sel[:, 3] == 1)
+            ts = np.sort(sel[:, 2])
+            want = [t0 + k * float(F32(C)) / dL * (t1 - t0) for k in range(1, n + 1)]
+            assert np.all(np.abs(ts - np.array(want)) <= 2.0), (ts, want)
+
+
+def pin_constant_frame_no_events(o):
+    rng = np.random.default_rng(13)
+    H, W = 10, 11
+    for L0 in (0.0, 1.7):
+        L = np.full((H, W), F32(L0))
+        pair = zero_motion_pair(o, L, L.copy())
+        ev, _, _, _ = o.step(pair, o.Sensor(K=8), L.copy())
+        assert len(ev) == 0
+        # any motion over a constant image still gives constant sub-frames
+        m = rng.uniform(-4, 4, size=(H, W, 2)).astype(F32)
+        Z = rng.uniform(0.5, 5, size=(H, W)).astype(F32)
+        pair = o.Pair(L, L.copy(), m, m.copy(), Z, Z.copy())
+        ev, _, _, _ = o.step(pair, o.Sensor(K=5), L.copy())
+        assert len(ev) == 0
+
+
+def _random_pair(o, seed, H=20, W=24, amp=3.0):
+    rng = np.random.default_rng(seed)
+    L_A = rng.normal(0, amp, size=(H, W)).astype(F32)
+    m = rng.normal(0, 2.0, size=(H, W, 2)).astype(F32)
+    L_B = (L_A + rng.normal(0, 0.5, size=(H, W))).astype(F32)
+    Z_A = rng.uniform(0.5, 5, size=(H, W)).astype(F32)
+    Z_B = rng.uniform(0.5, 5, size=(H, W)).astype(F32)
+    return o.Pair(L_A, L_B, m, (m + F32(0.25)).astype(F32), Z_A, Z_B, 0, 16667)
+
+
+def pin_polarity_symmetry(o):
+    pair = _random_pair(o, 17)
+    sensor = o.Sensor(C_on=0.2, C_off=0.2, K=6)
+    ev, R, _, _ = o.step(pair, sensor, pair.L_A.copy())
+    neg = o.Pair(-pair.L_A, -pair.L_B, pair.m_A, pair.m_B, pair.Z_A, pair.Z_B, 0, 16667)
+    ev2, R2, _, _ = o.step(neg, sensor, -pair.L_A)
+    assert len(ev) > 50
+    flipped = ev2.copy()
+    flipped[:, 3] = 1 - flipped[:, 3]
+    assert np.array_equal(o.canonical(ev), o.canonical(flipped))
+    assert np.array_equal(R, -R2)
+
+
+def pin_residual_and_sum(o):
+    """After a pair: |L_B - L_ref| < C, and the reference moved by exactly
+    the signed sum of C over the emitted crossings (no refractory period)."""
+    C = 0.2
+    pair = _random_pair(o, 19)
+    L0 = pair.L_A.copy()
+    ev, R, _, _ = o.step(pair, o.Sensor(C_on=C, C_off=C, K=5), L0)
+    c = float(F32(C))
+    assert np.all(np.abs(pair.L_B.astype(np.float64) - R) < c * (1 + 1e-5))
+    H, W = pair.shape
+    moved = np.zeros((H, W))
+    np.add.at(moved, (ev[:, 1], ev[:, 0]), np.where(ev[:, 3] == 1, c, -c))
+    assert np.allclose(R.astype(np.float64) - L0, moved, rtol=0, atol=1e-4)
+
+
+def pin_timestamps(o):
+    pair = _random_pair(o, 23)
+    t_last = np.full(pair.shape, o.T_LAST_INIT, np.int32)
+    ev, _, _, _ = o.step(pair, o.Sensor(K=7, refractory_us=150), pair.L_A.copy(), t_last)
+    assert len(ev) > 20
+    assert ev[:, 2].min() >= pair.t0_us and ev[:, 2].max() <= pair.t1_us
+    H, W = pair.shape
+    for flat in range(H * W):
+        y, x = divmod(flat, W)
+        ts = ev[(ev[:, 0] == x) & (ev[:, 1] == y), 2]       # emission order
+        assert np.all(np.diff(ts) >= 150), (x, y, ts)
+
+
+def pin_mismatch(o):
+    """Eq. 8: rising pixels use theta_on, falling pixels theta_off."""
+    L_A = np.zeros((1, 2), F32)
+    L_B = np.array([[1.1, -1.1]], F32)
+    pair = zero_motion_pair(o, L_A, L_B)
+    on = np.array([[0.25, 0.25]], F32)
+    off = np.array([[0.5, 0.5]], F32)
+    s = o.Sensor(theta_on=on, theta_off=off, K=4)
+    ev, _, _, _ = o.step(pair, s, L_A.copy())
+    p0 = ev[ev[:, 0] == 0]
+    p1 = ev[ev[:, 0] == 1]
+    assert len(p0) == 4 and np.all(p0[:, 3] == 1)
+    assert len(p1) == 2 and np.all(p1[:, 3] == 0)
+
+
+def pin_crossing_count_exact(o):
+    getcontext().prec = 80
+    rng = np.random.default_rng(29)
+    cases = [(F32(1.0), F32(0.2)), (F32(0.6), F32(0.2)), (F32(1.1), F32(0.2)),
+             (F32(0.75), F32(0.25)), (F32(3.0), F32(0.1))]
+    for _ in range(300):
+        c = F32(rng.uniform(0.01, 1.0))
+        a = F32(c * rng.integers(1, 40) * (1 + rng.choice([-1, 0, 1]) * 1e-7))
+        if a >= c:
+            cases.append((a, c))
+    for a, c in cases:
+        want = int((Decimal(float(a)) / Decimal(float(c))).to_integral_value(rounding="ROUND_FLOOR"))
+        assert o.crossing_count(a, c) == want, (float(a), float(c))
+    assert o.crossing_count(F32(np.inf), F32(0.2)) == o.N_MAX
+    assert o.crossing_count(F32(1e6), F32(0.01)) == o.N_MAX
+
+
+# ---------------------------------------------------------------------------
+# a7
+# ---------------------------------------------------------------------------
+
+def pin_event_record(o):
+    rec = o.pack_events(np.array([[5, 3, 77, 1, 2]]))
+    assert int(rec[0, 0]) == 5 + 3 * 2048 + 1 * 4194304 + 2 * 8388608 and int(rec[0, 1]) == 77
+    rng = np.random.default_rng(31)
+    ev = np.stack([rng.integers(0, 2048, 100), rng.integers(0, 2048, 100),
+                   rng.integers(0, 2 ** 31 - 1, 100), rng.integers(0, 2, 100),
+                   rng.integers(0, 512, 100)], axis=1)
+    assert np.array_equal(o.unpack_events(o.pack_events(ev).astype(np.uint32)), ev)
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

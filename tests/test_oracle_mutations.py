@@ -1,0 +1,178 @@
+"""Plant one plausible mistake at a time into the CPU oracle and require the
+pins to notice.  This shows the pins constrain every step of the oracle,
+not only its overall shape.  CPU only; the mistakes live in patched copies
+of oracle functions and never leave this process."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import evis_oracle as o
+import oracle_pins as P
+
+F32 = np.float32
+
+
+def m_splat_sign(m_A, Z_A, Zend, f):
+    H, W = Z_A.shape
+    px, py = o.pixel_coords(H, W)
+    qx = px + f * m_A[..., 0]                      # planted: wrong sign of Eq. 5
+    qy = py + f * m_A[..., 1]
+    zt = o.lerp(Z_A, Zend, f)
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (zt.view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def m_depth_swapped(m_A, Z_A, Zend, f):
+    H, W = Z_A.shape
+    px, py = o.pixel_coords(H, W)
+    qx = px - f * m_A[..., 0]
+    qy = py - f * m_A[..., 1]
+    zt = o.lerp(Zend, Z_A, f)                      # planted: Eq. 7 weights swapped
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (np.ascontiguousarray(zt).view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def m_zbuffer_max(m_A, Z_A, Zend, f):
+    H, W = Z_A.shape
+    qx, qy, zt, key = o.splat_keys(m_A, Z_A, Zend, f)
+    live = (zt > 0) & (np.abs(qx) < 2.0 ** 24) & (np.abs(qy) < 2.0 ** 24)
+    zbuf = np.zeros(H * W, dtype=np.uint64)        # planted: farthest surface wins
+    for cx, cy, sel in o.footprint(np.where(live, qx, F32(-8)), np.where(live, qy, F32(-8))):
+        sel = sel & live & (cx >= 0) & (cx < W) & (cy >= 0) & (cy < H)
+        np.maximum.at(zbuf, (cy * W + cx)[sel], key[sel])
+    zbuf[zbuf == 0] = o.EMPTY_KEY
+    return zbuf.reshape(H, W)
+
+
+def m_zero_weight_corners(qx, qy):
+    x0f, y0f = np.floor(qx), np.floor(qy)
+    x0, y0 = x0f.astype(np.int64), y0f.astype(np.int64)
+    allv = np.ones(qx.shape, bool)
+    return [(x0, y0, allv), (x0 + 1, y0, allv), (x0, y0 + 1, allv), (x0 + 1, y0 + 1, allv)]
+
+
+def m_gather_sign(zbuf, L_A, L_B, m_B, f, alpha):
+    return o.__dict__["_orig_rgb"](zbuf, L_A, L_B, -m_B, f, alpha)   # planted: s = q + g m_B
+
+
+def m_blend_swap(zbuf, L_A, L_B, m_B, f, alpha):
+    H, W = L_A.shape
+    out, vA, vB = o.__dict__["_orig_rgb"](zbuf, L_A, L_B, m_B, f, alpha)
+    g = F32(1) - f
+    ux, uy = o.pixel_coords(H, W)
+    key = zbuf.reshape(-1)
+    src = np.where(key != o.EMPTY_KEY, key & np.uint64(0xFFFF_FFFF), 0).astype(np.int64)
+    Ah = L_A.reshape(-1)[src].reshape(H, W)
+    sx, sy = ux - g * m_B[..., 0], uy - g * m_B[..., 1]
+    Bh = np.zeros((H, W), F32)
+    Bh[vB] = o.bilinear(L_B, sx[vB], sy[vB])
+    swapped = o.lerp(Bh, Ah, alpha)                # planted: blend weights swapped
+    return np.where(vA & vB, swapped, out).astype(F32), vA, vB
+
+
+def m_bilinear_transposed(img, sx, sy):
+    H, W = img.shape
+    x0 = np.floor(sx).astype(np.int64)
+    y0 = np.floor(sy).astype(np.int64)
+    wx, wy = sx - np.floor(sx), sy - np.floor(sy)
+    x1, y1 = np.minimum(x0 + 1, W - 1), np.minimum(y0 + 1, H - 1)
+    t = img.T                                      # planted: rows and columns swapped
+    top = o.lerp(t[np.minimum(y0, W - 1), np.minimum(x0, H - 1)],
+                 t[np.minimum(y0, W - 1), np.minimum(x1, H - 1)], wx)
+    bot = o.lerp(t[np.minimum(y1, W - 1), np.minimum(x0, H - 1)],
+                 t[np.minimum(y1, W - 1), np.minimum(x1, H - 1)], wx)
+    return o.lerp(top, bot, wy)
+
+
+def m_adaptive_floor(m_A, m_B, K_max):
+    best = 0.0
+    for m in (m_A, m_B):
+        msq = m[..., 0].astype(np.float64) ** 2 + m[..., 1].astype(np.float64) ** 2
+        msq = msq[np.isfinite(msq)]
+        best = max(best, float(msq.max()) if msq.size else 0.0)
+    return int(min(max(int(math.floor(math.sqrt(best))), 1), K_max))   # planted: floor
+
+
+def m_rounded_quotient(a, c):
+    return int(min(math.floor(F32(a) / F32(c)), o.N_MAX))   # planted: floor of fl32(a/c)
+
+
+def m_time_shift(j, k, R, c, positive, prev, cur, Dt, span):
+    return o.__dict__["_orig_cto"](j + 1, k, R, c, positive, prev, cur, Dt, span)  # planted: j, not j-1
+
+
+def _emit_variant(drop_residual=False, flip=False, refr_keeps_ref=False):
+    def emit(j, prev, cur, R, tl, on, off, refractory_us, t0_us, Dt, span, env_id, log,
+             track_t_last=True):
+        H, W = cur.shape
+        d = cur - R
+        positive = d > 0
+        c = np.where(positive, on, off)
+        a = np.abs(d)
+        hit = (a >= c) & (c > 0)
+        for flat in np.flatnonzero(hit):
+            y, x = divmod(int(flat), W)
+            pos = bool(positive[y, x])
+            cc = c[y, x]
+            n = o.crossing_count(a[y, x], cc)
+            r0 = R[y, x]
+            kept = 0
+            for k in range(1, n + 1):
+                t = t0_us + o.crossing_time_offset(j, k, r0, cc, pos, prev[y, x], cur[y, x], Dt, span)
+                if refractory_us == 0 or t - int(tl[y, x]) >= refractory_us:
+                    p = 1 if pos else 0
+                    log.add(x, y, t, (1 - p) if flip else p, env_id)
+                    kept += 1
+                    if track_t_last:
+                        tl[y, x] = t
+            if drop_residual:
+                R[y, x] = cur[y, x]
+            else:
+                nn = kept if refr_keeps_ref else n
+                nc = F32(nn) * cc
+                R[y, x] = r0 + nc if pos else r0 - nc
+    return emit
+
+
+def m_pack_shift(ev):
+    ev = np.asarray(ev, np.int64).reshape(-1, 5)
+    word = ev[:, 0] | (ev[:, 1] << 12) | (ev[:, 3] << 22) | (ev[:, 4] << 23)   # planted
+    return np.stack([word, ev[:, 2]], axis=1)
+
+
+MUTANTS = [
+    ("splat_sign", "splat_keys", m_splat_sign, P.pin_integer_translation),
+    ("depth_weights_swapped", "splat_keys", m_depth_swapped, P.pin_depth_interp),
+    ("zbuffer_keeps_farthest", "splat_forward", m_zbuffer_max, P.pin_occlusion),
+    ("zero_weight_corners", "footprint", m_zero_weight_corners, P.pin_integer_translation),
+    ("gather_sign", "resolve_gather_blend", m_gather_sign, P.pin_gather_affine),
+    ("blend_swapped", "resolve_gather_blend", m_blend_swap, P.pin_blend_modes),
+    ("bilinear_transposed", "bilinear", m_bilinear_transposed, P.pin_endpoint_depth_affine),
+    ("adaptive_k_floor", "adaptive_k", m_adaptive_floor, P.pin_adaptive_k),
+    ("rounded_quotient", "crossing_count", m_rounded_quotient, P.pin_goldens),
+    ("time_offset_shift", "crossing_time_offset", m_time_shift, P.pin_goldens),
+    ("residual_dropped", "emit_substep", _emit_variant(drop_residual=True), P.pin_goldens),
+    ("polarity_flipped", "emit_substep", _emit_variant(flip=True), P.pin_goldens),
+    ("suppressed_keep_reference", "emit_substep", _emit_variant(refr_keeps_ref=True), P.pin_goldens),
+    ("pack_bit_position", "pack_events", m_pack_shift, P.pin_event_record),
+]
+
+
+def test_unmutated_variant_passes(monkeypatch):
+    """The harness's own copy of emit_substep, without a mistake, passes."""
+    monkeypatch.setattr(o, "emit_substep", _emit_variant())
+    P.pin_goldens(o)
+    P.pin_residual_and_sum(o)
+
+
+@pytest.mark.parametrize("name,attr,mutant,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_catches_mutant(monkeypatch, name, attr, mutant, pin):
+    monkeypatch.setitem(o.__dict__, "_orig_rgb", o.resolve_gather_blend)
+    monkeypatch.setitem(o.__dict__, "_orig_cto", o.crossing_time_offset)
+    monkeypatch.setattr(o, attr, mutant)
+    with pytest.raises((AssertionError, IndexError, ValueError)):
+        pin(o)

@@ -1,0 +1,213 @@
+/* evis.h -- C ABI of the EVIS event-generation path on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: "EVIS: Real-Time Event Camera Simulation with Multimodal Supervision
+ * in NVIDIA Isaac Sim".  For each environment and keyframe pair A (t0) -> B
+ * (t1) the library takes log intensity, backward motion vectors and depth,
+ * synthesises K-1 intermediate log frames by bidirectional warping with a
+ * depth-tested forward splat (Sec. "Bidirectional Motion Vector Warping",
+ * Eq. 5-7) and emits contrast-threshold crossings as (x, y, t, p) events
+ * (Sec. "HDR Event Formation Model", Eq. 4; non-idealities Eq. 8 and the
+ * refractory period of Sec. "Sensor Calibration and Non-idealities").
+ *
+ * Conventions shared by every call
+ *  - Array arguments are DEVICE pointers owned by the caller; the library
+ *    never frees them.  The library owns only the scratch inside evis_ctx.
+ *    Float arrays need 4-byte alignment, motion-vector arrays and event
+ *    buffers 8-byte alignment.
+ *  - Images are row-major [H][W]; pixel centres sit at integer (x, y);
+ *    1 <= H, W <= EVIS_MAX_DIM.
+ *  - Motion vectors are [H][W][2] float32 (dx, dy) in pixels and point
+ *    backward: pixel p of keyframe B sits at p + m_B(p) in keyframe A;
+ *    keyframe A's own backward field m_A is reused as its forward velocity.
+ *  - Depth is float32 metres; a source whose intermediate depth is not > 0
+ *    (NaN included) is invisible to the splat.
+ *  - Times are integer microseconds, 0 <= t0 < t1 <= 2^31 - 1 and
+ *    t1 - t0 <= EVIS_MAX_SPAN_US.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream); the caller synchronises before reading results.
+ *  - An argument error returns a negative status, enqueues nothing and
+ *    sets evis_last_error().  One evis_ctx per host thread and stream.
+ *  - Event streams are multisets: the order of events in `out` is
+ *    unspecified.  `n_total` is a device int64 cursor: events are appended
+ *    at out[*n_total ...] and *n_total grows by the number of events of the
+ *    call, also past `capacity`; only the events whose index is below
+ *    `capacity` are stored (which ones is unspecified) and the state still
+ *    advances.  Pass EVIS_FLAG_RESET_CURSOR to start the cursor at 0.
+ *  - Non-finite log intensities or motion vectors give unspecified events
+ *    but never an access outside the arrays described here.
+ */
+#ifndef EVIS_H
+#define EVIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EVIS_ABI_VERSION 1
+
+#define EVIS_MAX_DIM 2047
+#define EVIS_MAX_ENVS 512
+#define EVIS_MAX_K 128
+#define EVIS_MAX_CROSSINGS 65535       /* crossings per pixel and substep (cap) */
+#define EVIS_MAX_SPAN_US (1 << 24)
+#define EVIS_T_LAST_INIT (-1073741824) /* "never fired" refractory state */
+
+enum {
+  EVIS_OK = 0,
+  EVIS_ERR_INVALID = -1,     /* a bad argument; nothing was enqueued */
+  EVIS_ERR_UNSUPPORTED = -2, /* valid but outside the supported range */
+  EVIS_ERR_HIP = -3,         /* the HIP runtime reported an error */
+  EVIS_ERR_NOMEM = -4        /* scratch allocation failed */
+};
+
+/* Blend of the two warped keyframes at fraction f (Sec. "Bidirectional
+ * Motion Vector Warping", last paragraph): where both are valid the
+ * sub-frame is A^ + alpha (B^ - A^). */
+enum {
+  EVIS_BLEND_TIME = 0,      /* alpha = f */
+  EVIS_BLEND_B_PRIMARY = 1  /* alpha = 1: backward-warped B is the result, A fills B's holes */
+};
+
+enum { EVIS_FLAG_RESET_CURSOR = 1 };
+
+/* One event: x in bits 0..10, y in 11..21, polarity in 22 (1 = ON), env id
+ * in 23..31; t_us is the absolute time in microseconds. */
+typedef struct {
+  uint32_t xyp;
+  int32_t t_us;
+} evis_event;
+
+/* One environment's keyframe pair A -> B (Sec. "Bidirectional Motion Vector
+ * Warping").  L_* are log intensities (the output of evis_log_luminance). */
+typedef struct {
+  int32_t H, W;
+  const float *L_A, *L_B;   /* [H*W] */
+  const float *m_A, *m_B;   /* [H*W*2] backward motion vectors, px */
+  const float *Z_A, *Z_B;   /* [H*W] depth */
+  int64_t t0_us, t1_us;
+} evis_pair;
+
+/* Per-camera sensor model. */
+typedef struct {
+  float C_on, C_off;                  /* contrast thresholds (> 0) used where theta_* is NULL */
+  const float *theta_on, *theta_off;  /* [H*W] per-pixel thresholds (Eq. 8) or NULL */
+  int32_t refractory_us;              /* >= 0; 0 = off */
+  int32_t K;                          /* > 0: fixed substep count; <= 0: adaptive */
+  int32_t K_max;                      /* 1..EVIS_MAX_K, cap of the adaptive count */
+  int32_t blend_mode;                 /* EVIS_BLEND_* */
+} evis_sensor;
+
+/* Per-pixel state carried from pair to pair (caller-owned device arrays). */
+typedef struct {
+  float *L_ref;     /* [H*W] reference log level of each pixel (Eq. 4) */
+  int32_t *t_last;  /* [H*W] time of the last emitted event; may be NULL when refractory_us == 0 */
+} evis_state;
+
+typedef struct {
+  evis_pair pair;
+  evis_sensor sensor;
+  evis_state state;
+  int32_t env_id;     /* 0..EVIS_MAX_ENVS-1, written into each event */
+  int32_t reserved;
+} evis_env;
+
+typedef struct evis_ctx evis_ctx;
+
+/* Lifetime.  evis_create binds the context to HIP device `device` and
+ * allocates nothing else until a call needs scratch.  Returns EVIS_OK or a
+ * negative status (ctx is then NULL). */
+int evis_create(evis_ctx **ctx, int device);
+void evis_destroy(evis_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *evis_last_error(const evis_ctx *ctx);
+int evis_abi_version(void);
+
+/* a1 -- Eq. 3 Rec.709 luminance and the log intensity below it:
+ * L = ln(Y + eps).  x is [n] luminance (channels == 1) or [n][3] linear RGB
+ * (channels == 3); L_out is [n].  float32 arithmetic with the library's own
+ * logarithm.  eps > 0. */
+int evis_log_luminance(evis_ctx *ctx, const float *x, int32_t channels, int64_t n, float eps,
+                       float *L_out, void *stream);
+
+/* Initialise a pixel state from the first log frame: L_ref = L_first and,
+ * when t_last is non-NULL, t_last = EVIS_T_LAST_INIT. */
+int evis_state_init(evis_ctx *ctx, const float *L_first, int32_t H, int32_t W,
+                    const evis_state *state, void *stream);
+
+/* a2 -- substep count of one pair: the smallest K >= 1 with K^2 >= the
+ * largest finite |m|^2 over m_A and m_B (float64), at most K_max; so no
+ * motion vector moves a pixel by more than one pixel per substep.
+ * K_out is a device int32. */
+int evis_substep_count(evis_ctx *ctx, const evis_pair *pair, int32_t K_max, int32_t *K_out,
+                       void *stream);
+
+/* a3-a5 -- intermediate log frames j in [j_begin, j_end) of K (0 <= j_begin <
+ * j_end <= K + 1, 1 <= K <= EVIS_MAX_K).  j = 0 and j = K return L_A and
+ * L_B verbatim.  For 0 < j < K, f = j/K: keyframe A is splatted forward to
+ * q = p - f m_A(p) over the bilinear footprint (corners with positive
+ * weight), a 64-bit (depth bits << 32 | source index) z-buffer keeps the
+ * nearest source (Eq. 6; depth from Eq. 7 with p_B = p - m_A(p), Z_B
+ * sampled with edge clamping); keyframe B is gathered bilinearly at
+ * s = q - (1 - f) m_B(q); the two are blended per blend_mode, each side
+ * alone where the other is missing, and lerp(L_A(q), L_B(q), alpha) where
+ * both are missing.  L_out is [(j_end - j_begin)][H*W]; hole_mask (nullable) is
+ * the same shape in bytes: bit 0 = no A source landed, bit 1 = s outside
+ * the image. */
+int evis_interpolate(evis_ctx *ctx, const evis_pair *pair, int32_t K, int32_t j_begin,
+                     int32_t j_end, int32_t blend_mode, float *L_out, uint8_t *hole_mask,
+                     void *stream);
+
+/* a6-a7 -- events from caller-supplied log frames L_seq[0..K] ([K+1][H*W];
+ * L_seq[0] is the previous sample, events come from j = 1..K) between
+ * t0_us and t1_us.  Per pixel and substep j: d = L_j - L_ref, polarity
+ * sgn d, threshold c = theta_on/C_on or theta_off/C_off, n = floor(|d|/c)
+ * exactly (Eq. 4), each crossing timed by linear interpolation of L between
+ * L_{j-1} and L_j and floored to whole microseconds, dropped when the
+ * refractory period has not elapsed since the last emitted event; then
+ * L_ref moves by n*c (suppressed crossings included).  `state` is updated
+ * in place.  The sensor's K, K_max and blend_mode are ignored here. */
+int evis_generate_events(evis_ctx *ctx, const float *L_seq, int32_t H, int32_t W, int32_t K,
+                         int64_t t0_us, int64_t t1_us, const evis_sensor *sensor,
+                         const evis_state *state, int32_t env_id, evis_event *out,
+                         int64_t capacity, int64_t *n_total, int32_t flags, void *stream);
+
+/* a1-a8 fused -- one keyframe pair for each of n_envs environments
+ * (1..EVIS_MAX_ENVS; envs is a HOST array of descriptors) in one
+ * persistent launch: substep count, sub-frames and events of every env,
+ * all events appended to one stream.  K_used (device [n_envs], nullable)
+ * receives each env's K.  States are updated in place.  The launch
+ * sequence is captured once into a HIP graph per (n_envs, out, cursor,
+ * K_used, tuning) and replayed. */
+int evis_step_batch(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_event *out,
+                    int64_t capacity, int64_t *n_total, int32_t *K_used, int32_t flags,
+                    void *stream);
+
+/* Tuning of the fused launch: target tile shape and persistent grid size.
+ * tile_w x tile_h in {16x16, 32x16, 32x32, 64x16, 64x32}; grid_mult >= 1
+ * workgroups per compute unit (0 = occupancy limit); list_cap in 1..1024
+ * caps the per-tile candidate list (smaller values force the window-scan
+ * fallback; 0 = the maximum); use_graph 0/1. */
+typedef struct {
+  int32_t tile_w, tile_h;
+  int32_t grid_mult;
+  int32_t list_cap;
+  int32_t use_graph;
+  int32_t static_tiles;   /* 1 = skip warping of provably static tiles */
+} evis_tuning;
+
+int evis_get_tuning(const evis_ctx *ctx, evis_tuning *out);
+int evis_set_tuning(evis_ctx *ctx, const evis_tuning *tuning);
+
+/* Time every tile shape on this batch (reps launches each, states are
+ * restored afterwards from a private copy) and keep the fastest in ctx.
+ * best (host, nullable) receives it, best_ms (host, nullable) its time. */
+int evis_autotune(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_event *out,
+                  int64_t capacity, int64_t *n_total, int32_t reps, evis_tuning *best,
+                  float *best_ms, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EVIS_H */

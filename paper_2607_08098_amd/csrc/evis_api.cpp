@@ -1,0 +1,686 @@
+// C ABI of libevis: argument validation, per-context scratch, descriptor
+// upload, HIP graph capture/replay of the fused launch, tuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "evis.h"
+#include "evis_internal.h"
+
+using namespace evis;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+constexpr int kStageSlots = 4;
+
+}  // namespace
+
+struct evis_ctx {
+  int device = 0;
+  int n_cu = 256;
+  std::string err;
+  hipStream_t capture_stream = nullptr;
+  // device scratch
+  DevBuf meta;        // EnvDesc[n] followed by int32 src_prefix[n + 1]
+  DevBuf dyn;         // EnvDyn[n]
+  DevBuf sched;       // rank_begin[n + 1], env_order[n], n_items, queue counter
+  DevBuf dz;          // float[sum H*W]
+  DevBuf tb;          // float4[sum source tiles]
+  DevBuf msq;         // one u64 for evis_substep_count
+  // host staging of the descriptor block (pinned ring)
+  void* stage[kStageSlots] = {};
+  size_t stage_bytes = 0;
+  hipEvent_t stage_ev[kStageSlots] = {};
+  int stage_next = 0;
+  std::vector<unsigned char> shadow;   // what d_meta currently holds
+  // graphs
+  std::map<std::string, GraphEntry> graphs;
+  evis_tuning tuning{32, 32, 0, kListCapMax, 1, 1};
+};
+
+namespace {
+
+int fail(evis_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(evis_ctx* c, hipError_t e, const char* where) {
+  return fail(c, EVIS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define EVIS_HIP(call, where)                      \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int ensure(evis_ctx* ctx, DevBuf& b, size_t bytes, bool* grew = nullptr) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return EVIS_OK;
+  if (b.p) {
+    hipDeviceSynchronize();
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)4096);
+  want = (want + 255) & ~(size_t)255;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(ctx, EVIS_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  b.bytes = want;
+  if (grew) *grew = true;
+  return EVIS_OK;
+}
+
+void drop_graphs(evis_ctx* ctx) {
+  for (auto& kv : ctx->graphs) {
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+  }
+  ctx->graphs.clear();
+}
+
+int ensure_stage(evis_ctx* ctx, size_t bytes) {
+  if (ctx->stage_bytes >= bytes) return EVIS_OK;
+  for (int i = 0; i < kStageSlots; ++i) {
+    if (ctx->stage_ev[i]) hipEventSynchronize(ctx->stage_ev[i]);
+    if (ctx->stage[i]) hipHostFree(ctx->stage[i]);
+    ctx->stage[i] = nullptr;
+  }
+  size_t want = std::max(bytes, (size_t)65536);
+  for (int i = 0; i < kStageSlots; ++i) {
+    hipError_t e = hipHostMalloc(&ctx->stage[i], want, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(ctx, EVIS_ERR_NOMEM, "hipHostMalloc of descriptor staging");
+    if (!ctx->stage_ev[i]) {
+      e = hipEventCreateWithFlags(&ctx->stage_ev[i], hipEventDisableTiming);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipEventCreate");
+    }
+  }
+  ctx->stage_bytes = want;
+  return EVIS_OK;
+}
+
+// Copy the descriptor block to device memory unless it already holds it.
+int upload_meta(evis_ctx* ctx, const std::vector<unsigned char>& blob, hipStream_t s) {
+  bool grew = false;
+  int rc = ensure(ctx, ctx->meta, blob.size(), &grew);
+  if (rc) return rc;
+  if (grew) {
+    drop_graphs(ctx);
+    ctx->shadow.clear();
+  }
+  if (ctx->shadow == blob) return EVIS_OK;
+  rc = ensure_stage(ctx, blob.size());
+  if (rc) return rc;
+  const int slot = ctx->stage_next;
+  ctx->stage_next = (slot + 1) % kStageSlots;
+  EVIS_HIP(hipEventSynchronize(ctx->stage_ev[slot]), "hipEventSynchronize");
+  std::memcpy(ctx->stage[slot], blob.data(), blob.size());
+  EVIS_HIP(hipMemcpyAsync(ctx->meta.p, ctx->stage[slot], blob.size(), hipMemcpyHostToDevice, s),
+           "hipMemcpyAsync(descriptors)");
+  EVIS_HIP(hipEventRecord(ctx->stage_ev[slot], s), "hipEventRecord");
+  ctx->shadow = blob;
+  return EVIS_OK;
+}
+
+int check_pair(evis_ctx* ctx, const evis_pair& p, const char* who) {
+  if (p.H < 1 || p.W < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": H and W must be >= 1");
+  if (p.H > EVIS_MAX_DIM || p.W > EVIS_MAX_DIM)
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": H and W must be <= 2047");
+  const void* ptrs[6] = {p.L_A, p.L_B, p.m_A, p.m_B, p.Z_A, p.Z_B};
+  for (int i = 0; i < 6; ++i)
+    if (!ptrs[i]) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": null frame pointer");
+  if (!aligned(p.L_A, 4) || !aligned(p.L_B, 4) || !aligned(p.Z_A, 4) || !aligned(p.Z_B, 4) ||
+      !aligned(p.m_A, 8) || !aligned(p.m_B, 8))
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": misaligned frame pointer");
+  return EVIS_OK;
+}
+
+int check_times(evis_ctx* ctx, int64_t t0, int64_t t1, const char* who) {
+  if (t0 < 0 || t1 <= t0 || t1 > 2147483647LL || t1 - t0 > EVIS_MAX_SPAN_US)
+    return fail(ctx, EVIS_ERR_INVALID,
+                std::string(who) + ": need 0 <= t0 < t1 <= 2^31-1 and t1 - t0 <= 2^24 us");
+  return EVIS_OK;
+}
+
+int check_sensor(evis_ctx* ctx, const evis_sensor& s, const char* who, bool need_k) {
+  const bool on_ok = s.theta_on ? aligned(s.theta_on, 4) : (s.C_on > 0.0f && std::isfinite(s.C_on));
+  const bool off_ok = s.theta_off ? aligned(s.theta_off, 4) : (s.C_off > 0.0f && std::isfinite(s.C_off));
+  if (!on_ok || !off_ok)
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": thresholds must be > 0 and finite");
+  if (s.refractory_us < 0) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": refractory_us < 0");
+  if (need_k) {
+    if (s.K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": K > 128");
+    if (s.K <= 0 && (s.K_max < 1 || s.K_max > EVIS_MAX_K))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": K_max must be in 1..128");
+    if (s.blend_mode != EVIS_BLEND_TIME && s.blend_mode != EVIS_BLEND_B_PRIMARY)
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown blend_mode");
+  }
+  return EVIS_OK;
+}
+
+int check_events_out(evis_ctx* ctx, const evis_event* out, int64_t capacity, const int64_t* n_total,
+                     const char* who) {
+  if (!n_total || !aligned(n_total, 8)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": n_total");
+  if (capacity < 0) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": capacity < 0");
+  if (capacity > 0 && (!out || !aligned(out, 8)))
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": event buffer");
+  return EVIS_OK;
+}
+
+EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st, int env_id) {
+  EnvDesc d{};
+  d.LA = p.L_A;
+  d.LB = p.L_B;
+  d.mA = reinterpret_cast<const float2*>(p.m_A);
+  d.mB = reinterpret_cast<const float2*>(p.m_B);
+  d.ZA = p.Z_A;
+  d.ZB = p.Z_B;
+  d.Lref = st.L_ref;
+  d.tlast = st.t_last;
+  d.th_on = s.theta_on;
+  d.th_off = s.theta_off;
+  d.H = p.H;
+  d.W = p.W;
+  d.ntx_src = (p.W + kSrcTile - 1) / kSrcTile;
+  d.nty_src = (p.H + kSrcTile - 1) / kSrcTile;
+  d.K_fixed = s.K > 0 ? s.K : 0;
+  d.K_max = s.K_max;
+  d.blend = s.blend_mode;
+  d.C_on = s.C_on;
+  d.C_off = s.C_off;
+  d.refr = s.refractory_us;
+  d.env_bits = (uint32_t)env_id << 23;
+  d.t0 = p.t0_us;
+  d.span = (int32_t)(p.t1_us - p.t0_us);
+  return d;
+}
+
+struct Plan {
+  std::vector<EnvDesc> desc;
+  std::vector<int32_t> src_prefix;   // n + 1
+  long long px_total = 0;
+  int src_total = 0;
+  int items = 0;
+};
+
+// Lay out per-env scratch (dZ, tile bounds) and the descriptor block.
+int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
+  const int n = (int)pl.desc.size();
+  long long px = 0;
+  int src = 0, items = 0;
+  pl.src_prefix.assign(n + 1, 0);
+  for (int e = 0; e < n; ++e) {
+    pl.src_prefix[e] = src;
+    px += (long long)pl.desc[e].H * pl.desc[e].W;
+    src += pl.desc[e].ntx_src * pl.desc[e].nty_src;
+    items += ((pl.desc[e].W + tw - 1) / tw) * ((pl.desc[e].H + th - 1) / th);
+  }
+  pl.src_prefix[n] = src;
+  pl.px_total = px;
+  pl.src_total = src;
+  pl.items = items;
+  bool grew = false;
+  int rc = ensure(ctx, ctx->dz, (size_t)px * sizeof(float), &grew);
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->tb, (size_t)src * sizeof(float4), &grew);
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->dyn, (size_t)n * sizeof(EnvDyn), &grew);
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->sched, (size_t)(3 * n + 8) * sizeof(int32_t), &grew);
+  if (rc) return rc;
+  if (grew) {
+    drop_graphs(ctx);
+    ctx->shadow.clear();
+  }
+  long long off_px = 0;
+  for (int e = 0; e < n; ++e) {
+    pl.desc[e].dZ = static_cast<float*>(ctx->dz.p) + off_px;
+    pl.desc[e].tb = static_cast<float4*>(ctx->tb.p) + pl.src_prefix[e];
+    pl.desc[e].src_tile_base = pl.src_prefix[e];
+    off_px += (long long)pl.desc[e].H * pl.desc[e].W;
+  }
+  return EVIS_OK;
+}
+
+std::vector<unsigned char> meta_blob(const Plan& pl) {
+  const size_t n = pl.desc.size();
+  std::vector<unsigned char> blob(n * sizeof(EnvDesc) + (n + 1) * sizeof(int32_t));
+  std::memcpy(blob.data(), pl.desc.data(), n * sizeof(EnvDesc));
+  std::memcpy(blob.data() + n * sizeof(EnvDesc), pl.src_prefix.data(), (n + 1) * sizeof(int32_t));
+  return blob;
+}
+
+struct Sched {
+  int32_t* rank_begin;
+  int32_t* env_order;
+  int32_t* n_items;
+  unsigned int* queue;
+};
+
+Sched sched_ptrs(evis_ctx* ctx, int n) {
+  int32_t* base = static_cast<int32_t*>(ctx->sched.p);
+  Sched s;
+  s.rank_begin = base;                 // n + 1
+  s.env_order = base + (n + 1);        // n
+  s.n_items = base + (2 * n + 1);      // 1
+  s.queue = reinterpret_cast<unsigned int*>(base + (2 * n + 2));
+  return s;
+}
+
+// Enqueue reset, prep, queue and the tile kernel for the uploaded plan.
+int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileArgs ta,
+                  int32_t* K_used, unsigned long long* reset_cursor, hipStream_t s) {
+  const int n = (int)pl.desc.size();
+  const EnvDesc* d_desc = static_cast<const EnvDesc*>(ctx->meta.p);
+  const int32_t* d_prefix = reinterpret_cast<const int32_t*>(
+      static_cast<const unsigned char*>(ctx->meta.p) + n * sizeof(EnvDesc));
+  EnvDyn* d_dyn = static_cast<EnvDyn*>(ctx->dyn.p);
+  Sched sc = sched_ptrs(ctx, n);
+  EVIS_HIP(launch_reset(d_dyn, n, sc.queue, reset_cursor, s), "k_reset");
+  EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n, pl.src_total, s), "k_prep");
+  EVIS_HIP(launch_queue(d_desc, d_dyn, n, tw, th, sc.rank_begin, sc.env_order, sc.n_items, K_used, s),
+           "k_queue");
+  ta.envs = d_desc;
+  ta.dyn = d_dyn;
+  ta.rank_begin = sc.rank_begin;
+  ta.env_order = sc.env_order;
+  ta.n_envs = n;
+  ta.queue = sc.queue;
+  ta.n_items = sc.n_items;
+  int occ = tile_occupancy(tw, th, mode);
+  int per_cu = ctx->tuning.grid_mult > 0 ? std::min(ctx->tuning.grid_mult, occ) : occ;
+  int grid = std::max(1, std::min(pl.items, per_cu * ctx->n_cu));
+  EVIS_HIP(launch_tile(tw, th, mode, ta, grid, s), "k_tile");
+  return EVIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int evis_abi_version(void) { return EVIS_ABI_VERSION; }
+
+int evis_create(evis_ctx** out, int device) {
+  if (!out) return EVIS_ERR_INVALID;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return EVIS_ERR_INVALID;
+  if (hipSetDevice(device) != hipSuccess) return EVIS_ERR_HIP;
+  evis_ctx* ctx = new evis_ctx();
+  ctx->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->n_cu = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return EVIS_ERR_HIP;
+  }
+  *out = ctx;
+  return EVIS_OK;
+}
+
+void evis_destroy(evis_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  drop_graphs(ctx);
+  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->dz, &ctx->tb, &ctx->msq};
+  for (DevBuf* b : bufs)
+    if (b->p) hipFree(b->p);
+  for (int i = 0; i < kStageSlots; ++i) {
+    if (ctx->stage[i]) hipHostFree(ctx->stage[i]);
+    if (ctx->stage_ev[i]) hipEventDestroy(ctx->stage_ev[i]);
+  }
+  if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+  delete ctx;
+}
+
+const char* evis_last_error(const evis_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int evis_log_luminance(evis_ctx* ctx, const float* x, int32_t channels, int64_t n, float eps,
+                       float* L_out, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!x || !L_out || !aligned(x, 4) || !aligned(L_out, 4))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_log_luminance: null or misaligned pointer");
+  if (channels != 1 && channels != 3)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_log_luminance: channels must be 1 or 3");
+  if (n < 0) return fail(ctx, EVIS_ERR_INVALID, "evis_log_luminance: n < 0");
+  if (!(eps > 0.0f) || !std::isfinite(eps))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_log_luminance: eps must be > 0");
+  if (n == 0) return EVIS_OK;
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  EVIS_HIP(launch_log_luminance(x, channels, n, eps, L_out, (hipStream_t)stream), "k_log_luminance");
+  return EVIS_OK;
+}
+
+int evis_state_init(evis_ctx* ctx, const float* L_first, int32_t H, int32_t W,
+                    const evis_state* state, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!state || !L_first || !state->L_ref || !aligned(L_first, 4) || !aligned(state->L_ref, 4) ||
+      (state->t_last && !aligned(state->t_last, 4)))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_state_init: null or misaligned pointer");
+  if (H < 1 || W < 1 || H > EVIS_MAX_DIM || W > EVIS_MAX_DIM)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_state_init: bad H, W");
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  EVIS_HIP(launch_state_init(L_first, (long long)H * W, state->L_ref, state->t_last, (hipStream_t)stream),
+           "k_state_init");
+  return EVIS_OK;
+}
+
+int evis_substep_count(evis_ctx* ctx, const evis_pair* pair, int32_t K_max, int32_t* K_out,
+                       void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!pair) return fail(ctx, EVIS_ERR_INVALID, "evis_substep_count: null pair");
+  int rc = check_pair(ctx, *pair, "evis_substep_count");
+  if (rc) return rc;
+  if (K_max < 1 || K_max > EVIS_MAX_K) return fail(ctx, EVIS_ERR_INVALID, "evis_substep_count: K_max");
+  if (!K_out || !aligned(K_out, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_substep_count: K_out");
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  rc = ensure(ctx, ctx->msq, sizeof(unsigned long long));
+  if (rc) return rc;
+  EVIS_HIP(launch_substep_count(reinterpret_cast<const float2*>(pair->m_A),
+                                reinterpret_cast<const float2*>(pair->m_B),
+                                (long long)pair->H * pair->W, K_max,
+                                static_cast<unsigned long long*>(ctx->msq.p), K_out,
+                                (hipStream_t)stream),
+           "k_msq");
+  return EVIS_OK;
+}
+
+int evis_interpolate(evis_ctx* ctx, const evis_pair* pair, int32_t K, int32_t j_begin,
+                     int32_t j_end, int32_t blend_mode, float* L_out, uint8_t* hole_mask,
+                     void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!pair) return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: null pair");
+  int rc = check_pair(ctx, *pair, "evis_interpolate");
+  if (rc) return rc;
+  if (K < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: K must be >= 1");
+  if (K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_interpolate: K > 128");
+  if (j_begin < 0 || j_end <= j_begin || j_end > K + 1)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: need 0 <= j_begin < j_end <= K + 1");
+  if (blend_mode != EVIS_BLEND_TIME && blend_mode != EVIS_BLEND_B_PRIMARY)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: unknown blend_mode");
+  if (!L_out || !aligned(L_out, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: L_out");
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  evis_sensor s{};
+  s.C_on = s.C_off = 1.0f;
+  s.K = K;
+  s.K_max = K;
+  s.blend_mode = blend_mode;
+  evis_state st{};
+  Plan pl;
+  evis_pair p = *pair;
+  p.t0_us = 0;
+  p.t1_us = 1;
+  pl.desc.push_back(make_desc(p, s, st, 0));
+  const int tw = 32, th = 32;
+  rc = plan_envs(ctx, pl, tw, th);
+  if (rc) return rc;
+  rc = upload_meta(ctx, meta_blob(pl), (hipStream_t)stream);
+  if (rc) return rc;
+  TileArgs ta{};
+  ta.list_cap = std::min(std::max(ctx->tuning.list_cap, 1), kListCapMax);
+  ta.static_tiles = 0;
+  ta.L_out = L_out;
+  ta.hole = hole_mask;
+  ta.j_begin = j_begin;
+  ta.j_end = j_end;
+  return enqueue_batch(ctx, pl, MODE_INTERP, tw, th, ta, nullptr, nullptr, (hipStream_t)stream);
+}
+
+int evis_generate_events(evis_ctx* ctx, const float* L_seq, int32_t H, int32_t W, int32_t K,
+                         int64_t t0_us, int64_t t1_us, const evis_sensor* sensor,
+                         const evis_state* state, int32_t env_id, evis_event* out,
+                         int64_t capacity, int64_t* n_total, int32_t flags, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!L_seq || !aligned(L_seq, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: L_seq");
+  if (H < 1 || W < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: H, W");
+  if (H > EVIS_MAX_DIM || W > EVIS_MAX_DIM)
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_generate_events: H, W > 2047");
+  if (K < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: K must be >= 1");
+  if (K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_generate_events: K > 128");
+  int rc = check_times(ctx, t0_us, t1_us, "evis_generate_events");
+  if (rc) return rc;
+  if (!sensor || !state) return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: sensor/state");
+  rc = check_sensor(ctx, *sensor, "evis_generate_events", false);
+  if (rc) return rc;
+  if (!state->L_ref || !aligned(state->L_ref, 4))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: state.L_ref");
+  if (sensor->refractory_us > 0 && !state->t_last)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: refractory period needs state.t_last");
+  if (state->t_last && !aligned(state->t_last, 4))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: state.t_last");
+  if (env_id < 0 || env_id >= EVIS_MAX_ENVS)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: env_id");
+  rc = check_events_out(ctx, out, capacity, n_total, "evis_generate_events");
+  if (rc) return rc;
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const int span = (int)(t1_us - t0_us);
+  const float Dt = (float)span / (float)K;
+  EVIS_HIP(launch_events(L_seq, H, W, K, t0_us, span, Dt, sensor->C_on, sensor->C_off,
+                         sensor->theta_on, sensor->theta_off, sensor->refractory_us,
+                         (uint32_t)env_id << 23, state->L_ref, state->t_last, out, capacity,
+                         reinterpret_cast<unsigned long long*>(n_total),
+                         (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0, (hipStream_t)stream),
+           "k_events");
+  return EVIS_OK;
+}
+
+static int validate_envs(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, Plan& pl,
+                         const char* who) {
+  if (!envs) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": null envs");
+  if (n_envs < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": n_envs must be >= 1");
+  if (n_envs > EVIS_MAX_ENVS) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": n_envs > 512");
+  pl.desc.clear();
+  pl.desc.reserve(n_envs);
+  for (int e = 0; e < n_envs; ++e) {
+    const evis_env& v = envs[e];
+    int rc = check_pair(ctx, v.pair, who);
+    if (rc) return rc;
+    rc = check_times(ctx, v.pair.t0_us, v.pair.t1_us, who);
+    if (rc) return rc;
+    rc = check_sensor(ctx, v.sensor, who, true);
+    if (rc) return rc;
+    if (!v.state.L_ref || !aligned(v.state.L_ref, 4))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": state.L_ref");
+    if (v.sensor.refractory_us > 0 && !v.state.t_last)
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": refractory period needs state.t_last");
+    if (v.state.t_last && !aligned(v.state.t_last, 4))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": state.t_last");
+    if (v.env_id < 0 || v.env_id >= EVIS_MAX_ENVS)
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": env_id");
+    pl.desc.push_back(make_desc(v.pair, v.sensor, v.state, v.env_id));
+  }
+  return EVIS_OK;
+}
+
+static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, int64_t* n_total,
+                    int32_t* K_used, int32_t flags, hipStream_t s) {
+  const evis_tuning tu = ctx->tuning;
+  int rc = plan_envs(ctx, pl, tu.tile_w, tu.tile_h);
+  if (rc) return rc;
+  rc = upload_meta(ctx, meta_blob(pl), s);
+  if (rc) return rc;
+  TileArgs ta{};
+  ta.list_cap = std::min(std::max(tu.list_cap, 1), kListCapMax);
+  ta.static_tiles = tu.static_tiles ? 1 : 0;
+  ta.out = out;
+  ta.capacity = capacity;
+  ta.cursor = reinterpret_cast<unsigned long long*>(n_total);
+  unsigned long long* reset = (flags & EVIS_FLAG_RESET_CURSOR) ? ta.cursor : nullptr;
+  if (!tu.use_graph) return enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
+
+  char key[256];
+  std::snprintf(key, sizeof(key), "%d|%d|%d|%p|%lld|%p|%p|%d|%d|%d|%d|%d|%d|%d", (int)pl.desc.size(),
+                pl.src_total, pl.items, (void*)out, (long long)capacity, (void*)n_total,
+                (void*)K_used, flags & EVIS_FLAG_RESET_CURSOR, tu.tile_w, tu.tile_h, tu.grid_mult,
+                ta.list_cap, ta.static_tiles, (int)ctx->meta.bytes);
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= 32) drop_graphs(ctx);
+    GraphEntry g;
+    hipStream_t cs = ctx->capture_stream;
+    EVIS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    rc = enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(graph);
+      return hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    g.graph = graph;
+    it = ctx->graphs.emplace(key, g).first;
+  }
+  EVIS_HIP(hipGraphLaunch(it->second.exec, s), "hipGraphLaunch");
+  return EVIS_OK;
+}
+
+int evis_step_batch(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_event* out,
+                    int64_t capacity, int64_t* n_total, int32_t* K_used, int32_t flags,
+                    void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  Plan pl;
+  int rc = validate_envs(ctx, envs, n_envs, pl, "evis_step_batch");
+  if (rc) return rc;
+  rc = check_events_out(ctx, out, capacity, n_total, "evis_step_batch");
+  if (rc) return rc;
+  if (K_used && !aligned(K_used, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_step_batch: K_used");
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  return run_step(ctx, pl, out, capacity, n_total, K_used, flags, (hipStream_t)stream);
+}
+
+int evis_get_tuning(const evis_ctx* ctx, evis_tuning* out) {
+  if (!ctx || !out) return EVIS_ERR_INVALID;
+  *out = ctx->tuning;
+  return EVIS_OK;
+}
+
+int evis_set_tuning(evis_ctx* ctx, const evis_tuning* t) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!t) return fail(ctx, EVIS_ERR_INVALID, "evis_set_tuning: null");
+  if (!tile_shape_supported(t->tile_w, t->tile_h))
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_set_tuning: unsupported tile shape");
+  if (t->grid_mult < 0 || t->list_cap < 0 || t->list_cap > kListCapMax)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_set_tuning: grid_mult / list_cap out of range");
+  ctx->tuning = *t;
+  if (ctx->tuning.list_cap == 0) ctx->tuning.list_cap = kListCapMax;
+  return EVIS_OK;
+}
+
+int evis_autotune(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_event* out,
+                  int64_t capacity, int64_t* n_total, int32_t reps, evis_tuning* best,
+                  float* best_ms, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  Plan pl;
+  int rc = validate_envs(ctx, envs, n_envs, pl, "evis_autotune");
+  if (rc) return rc;
+  rc = check_events_out(ctx, out, capacity, n_total, "evis_autotune");
+  if (rc) return rc;
+  if (reps < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_autotune: reps must be >= 1");
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  // Private copy of every state so that trial launches leave it untouched.
+  size_t bytes = 8;
+  for (int e = 0; e < n_envs; ++e) {
+    const size_t px = (size_t)envs[e].pair.H * envs[e].pair.W;
+    bytes += px * 4 * (envs[e].state.t_last ? 2 : 1);
+  }
+  void* saved = nullptr;
+  EVIS_HIP(hipMalloc(&saved, bytes), "hipMalloc(autotune state copy)");
+  auto copy_states = [&](bool save) -> hipError_t {
+    unsigned char* p = static_cast<unsigned char*>(saved);
+    hipError_t e = save ? hipMemcpyAsync(p, n_total, 8, hipMemcpyDeviceToDevice, s)
+                        : hipMemcpyAsync(n_total, p, 8, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    p += 8;
+    for (int k = 0; k < n_envs; ++k) {
+      const size_t px = (size_t)envs[k].pair.H * envs[k].pair.W;
+      e = save ? hipMemcpyAsync(p, envs[k].state.L_ref, px * 4, hipMemcpyDeviceToDevice, s)
+               : hipMemcpyAsync(envs[k].state.L_ref, p, px * 4, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return e;
+      p += px * 4;
+      if (envs[k].state.t_last) {
+        e = save ? hipMemcpyAsync(p, envs[k].state.t_last, px * 4, hipMemcpyDeviceToDevice, s)
+                 : hipMemcpyAsync(envs[k].state.t_last, p, px * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+        p += px * 4;
+      }
+    }
+    return hipSuccess;
+  };
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  const evis_tuning orig = ctx->tuning;
+  evis_tuning winner = orig;
+  float winner_ms = 1e30f;
+  const int shapes[5][2] = {{16, 16}, {32, 16}, {32, 32}, {64, 16}, {64, 32}};
+  hipError_t he = copy_states(true);
+  for (int i = 0; i < 5 && he == hipSuccess && rc == EVIS_OK; ++i) {
+    evis_tuning t = orig;
+    t.tile_w = shapes[i][0];
+    t.tile_h = shapes[i][1];
+    ctx->tuning = t;
+    float total = 0.0f;
+    for (int r = 0; r <= reps && rc == EVIS_OK; ++r) {
+      he = copy_states(false);
+      if (he != hipSuccess) break;
+      hipEventRecord(e0, s);
+      Plan p2 = pl;
+      rc = run_step(ctx, p2, out, capacity, n_total, nullptr, 0, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) total += ms;   // the first launch of a shape also captures its graph
+    }
+    const float avg = total / (float)reps;
+    if (rc == EVIS_OK && avg < winner_ms) {
+      winner_ms = avg;
+      winner = t;
+    }
+  }
+  if (he == hipSuccess) he = copy_states(false);
+  hipStreamSynchronize(s);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(saved);
+  ctx->tuning = (rc == EVIS_OK && he == hipSuccess) ? winner : orig;
+  if (he != hipSuccess) return hip_fail(ctx, he, "evis_autotune state copy");
+  if (rc) return rc;
+  if (best) *best = winner;
+  if (best_ms) *best_ms = winner_ms;
+  return EVIS_OK;
+}
+
+}  // extern "C"

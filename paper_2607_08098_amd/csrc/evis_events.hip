@@ -1,0 +1,185 @@
+// Elementwise front end, state initialisation, the substep count of one
+// pair, and the event model over caller-supplied frames (gfx950).
+#include "evis_internal.h"
+#include "evis_sink.h"
+
+namespace evis {
+
+// a1: Eq. 3 luminance, then ln(Y + eps).
+__global__ __launch_bounds__(kBlock) void k_log_luminance(const float* __restrict__ x, int channels,
+                                                          long long n, float eps,
+                                                          float* __restrict__ L) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    float Y;
+    if (channels == 3) {
+      const float r = x[3 * i], g = x[3 * i + 1], b = x[3 * i + 2];
+      Y = 0.2126f * r + 0.7152f * g + 0.0722f * b;
+    } else {
+      Y = x[i];
+    }
+    L[i] = logf(Y + eps);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_state_init(const float* __restrict__ L, long long n,
+                                                       float* __restrict__ Lref,
+                                                       int32_t* __restrict__ tlast) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    Lref[i] = L[i];
+    if (tlast) tlast[i] = EVIS_T_LAST_INIT;
+  }
+}
+
+// a2 for one pair: largest finite |m|^2 (float64) over both fields.
+__global__ __launch_bounds__(kBlock) void k_msq(const float2* __restrict__ mA,
+                                                const float2* __restrict__ mB, long long n,
+                                                unsigned long long* msq_bits) {
+  double best = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float2 a = mA[i], b = mB[i];
+    const double ma = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+    const double mb = (double)b.x * (double)b.x + (double)b.y * (double)b.y;
+    if (ma <= 1.7976931348623157e308 && ma > best) best = ma;
+    if (mb <= 1.7976931348623157e308 && mb > best) best = mb;
+  }
+  best = wave_max_d(best);
+  if ((threadIdx.x & (kWave - 1)) == 0 && best > 0.0)
+    atomicMax(msq_bits, (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ void k_k_from_msq(const unsigned long long* msq_bits, int K_max, int32_t* K_out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    *K_out = exact_k(__longlong_as_double((long long)*msq_bits), K_max);
+}
+
+__global__ void k_zero_u64(unsigned long long* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
+// a6-a7 over materialised frames: PPT pixels per thread, consecutive pixels
+// across the workgroup, one pass over the K+1 frames with the state in
+// registers and the next frame's values loaded ahead.
+struct EventArgs {
+  const float* L_seq;
+  int H, W, K;
+  long long t0;
+  int span;
+  float Dt;
+  float C_on, C_off;
+  const float* th_on;
+  const float* th_off;
+  int refr;
+  uint32_t env_bits;
+  float* Lref;
+  int32_t* tlast;
+  evis_event* out;
+  long long capacity;
+  unsigned long long* cursor;
+};
+
+template <int PPT>
+__global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
+  __shared__ uint2 evbuf[kEventBuf];
+  __shared__ int s_wtot[2][kWavesPerBlock];
+  __shared__ unsigned long long s_gbase;
+  const SinkShared sh{evbuf, s_wtot, &s_gbase, kEventBuf};
+  const SinkOut so{a.out, a.capacity, a.cursor};
+  const int tid = threadIdx.x;
+  const long long plane = (long long)a.H * a.W;
+  const long long base = (long long)blockIdx.x * (kBlock * PPT);
+  float R[PPT], Lp[PPT], Lj[PPT], Ln[PPT], con[PPT], coff[PPT];
+  int tl[PPT];
+  uint32_t xy[PPT];
+  long long qi[PPT];
+  uint32_t okbits = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const long long q = base + tid + (long long)k * kBlock;
+    const bool ok = q < plane;
+    okbits |= (ok ? 1u : 0u) << k;
+    qi[k] = ok ? q : 0;
+    const int x = (int)(qi[k] % a.W), y = (int)(qi[k] / a.W);
+    xy[k] = (uint32_t)x | ((uint32_t)y << 11);
+    R[k] = ok ? a.Lref[q] : 0.0f;
+    tl[k] = (ok && a.tlast) ? a.tlast[q] : EVIS_T_LAST_INIT;
+    con[k] = (ok && a.th_on) ? a.th_on[q] : a.C_on;
+    coff[k] = (ok && a.th_off) ? a.th_off[q] : a.C_off;
+    Lp[k] = ok ? a.L_seq[q] : 0.0f;
+    Ln[k] = ok ? a.L_seq[plane + q] : 0.0f;
+  }
+  int ev_count = 0, round = 0;
+  for (int j = 1; j <= a.K; ++j) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      Lj[k] = Ln[k];
+      if (j < a.K) Ln[k] = ((okbits >> k) & 1u) ? a.L_seq[(long long)(j + 1) * plane + qi[k]] : 0.0f;
+    }
+    emit_substep<PPT>(j, Lj, Lp, R, tl, con, coff, xy, okbits, a.t0, a.span, a.Dt, a.refr,
+                      a.env_bits, sh, so, ev_count, round);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) Lp[k] = Lj[k];
+  }
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    if ((okbits >> k) & 1u) {
+      a.Lref[qi[k]] = R[k];
+      if (a.tlast) a.tlast[qi[k]] = tl[k];
+    }
+  }
+  sink_flush(sh, so, ev_count);
+}
+
+static int grid_for(long long n, int per_block) {
+  long long g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > 65535LL * 16) g = 65535LL * 16;
+  return (int)g;
+}
+
+hipError_t launch_log_luminance(const float* x, int channels, long long n, float eps, float* L,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_log_luminance, dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, x,
+                     channels, n, eps, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(const float* L_first, long long n, float* L_ref, int32_t* t_last,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, L_first, n,
+                     L_ref, t_last);
+  return hipGetLastError();
+}
+
+hipError_t launch_substep_count(const float2* mA, const float2* mB, long long n, int K_max,
+                                unsigned long long* msq_scratch, int32_t* K_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, msq_scratch);
+  hipLaunchKernelGGL(k_msq, dim3(grid_for(n, kBlock * 8)), dim3(kBlock), 0, s, mA, mB, n,
+                     msq_scratch);
+  hipLaunchKernelGGL(k_k_from_msq, dim3(1), dim3(64), 0, s, msq_scratch, K_max, K_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, int span,
+                         float Dt, float C_on, float C_off, const float* th_on,
+                         const float* th_off, int refr, uint32_t env_bits, float* L_ref,
+                         int32_t* t_last, evis_event* out, long long capacity,
+                         unsigned long long* cursor, int reset_cursor, hipStream_t s) {
+  if (reset_cursor) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, cursor);
+  EventArgs a{L_seq, H, W, K, t0, span, Dt, C_on, C_off, th_on, th_off, refr, env_bits,
+              L_ref, t_last, out, capacity, cursor};
+  const long long n = (long long)H * W;
+  // Enough workgroups to cover the chip: 4 px per thread on large frames.
+  if (n >= 4LL * kBlock * 1024) {
+    hipLaunchKernelGGL((k_events<4>), dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, a);
+  } else if (n >= 2LL * kBlock * 512) {
+    hipLaunchKernelGGL((k_events<2>), dim3(grid_for(n, kBlock * 2)), dim3(kBlock), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_events<1>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace evis

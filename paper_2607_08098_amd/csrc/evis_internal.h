@@ -1,0 +1,74 @@
+// Host-side interface between the C ABI (evis_api.cpp) and the kernel
+// translation units.  Not installed; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "evis.h"
+#include "evis_common.h"
+
+namespace evis {
+
+enum Mode { MODE_STEP = 0, MODE_INTERP = 1, MODE_SOFT_FWD = 2, MODE_SOFT_BWD = 3 };
+
+constexpr int kListCapMax = 1024;   // per-tile candidate source tiles held in LDS
+constexpr int kEventBuf = 2048;     // events staged in LDS per workgroup
+
+// Arguments of the fused tile kernel (all device pointers).
+struct TileArgs {
+  const EnvDesc* envs;
+  EnvDyn* dyn;
+  const int32_t* rank_begin;   // [n_envs + 1] first item of the env of each rank
+  const int32_t* env_order;    // [n_envs] env index of each rank
+  int32_t n_envs;
+  int32_t list_cap;
+  unsigned int* queue;         // work-queue counter (zeroed before the launch)
+  const int32_t* n_items;      // device: total work items
+  int32_t static_tiles;
+  // MODE_STEP
+  evis_event* out;
+  long long capacity;
+  unsigned long long* cursor;
+  // MODE_INTERP
+  float* L_out;
+  uint8_t* hole;
+  int32_t j_begin, j_end;
+  // MODE_SOFT_*
+  const float* C_soft;         // [n_envs] per-env threshold of the surrogate
+  float inv_tau;
+  float* S_out;                // per env [H*W] via soft_ptrs
+  const float* const* soft_S;  // [n_envs] S (fwd out)
+  const float* const* soft_gS; // [n_envs] dLoss/dS (bwd in)
+  float* const* soft_gLA;      // [n_envs] dL/dL_A (bwd out, accumulated)
+  float* const* soft_gLB;
+  float* const* soft_gmB;      // [n_envs] [H*W*2]
+  float* gC;                   // [n_envs]
+};
+
+// Kernel launchers (defined in evis_tile.hip / evis_events.hip).
+hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
+                        unsigned long long* cursor, hipStream_t s);
+hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
+                       int total_src_tiles, hipStream_t s);
+hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,
+                        int32_t* rank_begin, int32_t* env_order, int32_t* n_items,
+                        int32_t* K_used, hipStream_t s);
+hipError_t launch_tile(int tile_w, int tile_h, int mode, const TileArgs& a, int grid,
+                       hipStream_t s);
+int tile_occupancy(int tile_w, int tile_h, int mode);
+bool tile_shape_supported(int tile_w, int tile_h);
+
+hipError_t launch_log_luminance(const float* x, int channels, long long n, float eps, float* L,
+                                hipStream_t s);
+hipError_t launch_state_init(const float* L_first, long long n, float* L_ref, int32_t* t_last,
+                             hipStream_t s);
+hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, int span,
+                         float Dt, float C_on, float C_off, const float* th_on,
+                         const float* th_off, int refr, uint32_t env_bits, float* L_ref,
+                         int32_t* t_last, evis_event* out, long long capacity,
+                         unsigned long long* cursor, int reset_cursor, hipStream_t s);
+hipError_t launch_substep_count(const float2* mA, const float2* mB, long long n, int K_max,
+                                unsigned long long* msq_scratch, int32_t* K_out, hipStream_t s);
+
+}  // namespace evis

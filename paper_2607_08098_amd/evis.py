@@ -1,0 +1,312 @@
+"""Python binding of libevis (ctypes): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and passes
+device pointers of torch tensors plus the current HIP stream; all
+arithmetic happens in the library's HIP kernels.  torch provides device
+memory and streams, nothing else.  The library must have been built
+(``python -m paper_2607_08098_amd.build``); without it every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libevis.so")
+
+EVIS_OK = 0
+EVIS_ERR_INVALID = -1
+EVIS_ERR_UNSUPPORTED = -2
+EVIS_ERR_HIP = -3
+EVIS_ERR_NOMEM = -4
+EVIS_BLEND_TIME = 0
+EVIS_BLEND_B_PRIMARY = 1
+EVIS_FLAG_RESET_CURSOR = 1
+EVIS_T_LAST_INIT = -(2 ** 30)
+EVIS_MAX_CROSSINGS = 65535
+
+_c_float_p = ctypes.POINTER(ctypes.c_float)
+
+
+class EvisPair(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("L_A", ctypes.c_void_p), ("L_B", ctypes.c_void_p),
+                ("m_A", ctypes.c_void_p), ("m_B", ctypes.c_void_p),
+                ("Z_A", ctypes.c_void_p), ("Z_B", ctypes.c_void_p),
+                ("t0_us", ctypes.c_int64), ("t1_us", ctypes.c_int64)]
+
+
+class EvisSensor(ctypes.Structure):
+    _fields_ = [("C_on", ctypes.c_float), ("C_off", ctypes.c_float),
+                ("theta_on", ctypes.c_void_p), ("theta_off", ctypes.c_void_p),
+                ("refractory_us", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("K_max", ctypes.c_int32), ("blend_mode", ctypes.c_int32)]
+
+
+class EvisState(ctypes.Structure):
+    _fields_ = [("L_ref", ctypes.c_void_p), ("t_last", ctypes.c_void_p)]
+
+
+class EvisEnv(ctypes.Structure):
+    _fields_ = [("pair", EvisPair), ("sensor", EvisSensor), ("state", EvisState),
+                ("env_id", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class EvisTuning(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("grid_mult", ctypes.c_int32), ("list_cap", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("static_tiles", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# Every symbol include/evis.h declares, with its ctypes signature.
+_VP = ctypes.c_void_p
+SIGNATURES = {
+    "evis_abi_version": (ctypes.c_int, []),
+    "evis_create": (ctypes.c_int, [ctypes.POINTER(_VP), ctypes.c_int]),
+    "evis_destroy": (None, [_VP]),
+    "evis_last_error": (ctypes.c_char_p, [_VP]),
+    "evis_log_luminance": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                                          _VP, _VP]),
+    "evis_state_init": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(EvisState), _VP]),
+    "evis_substep_count": (ctypes.c_int, [_VP, ctypes.POINTER(EvisPair), ctypes.c_int32, _VP, _VP]),
+    "evis_interpolate": (ctypes.c_int, [_VP, ctypes.POINTER(EvisPair), ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, _VP, _VP, _VP]),
+    "evis_generate_events": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(EvisSensor),
+                                            ctypes.POINTER(EvisState), ctypes.c_int32, _VP,
+                                            ctypes.c_int64, _VP, ctypes.c_int32, _VP]),
+    "evis_step_batch": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
+                                       _VP, _VP, ctypes.c_int32, _VP]),
+    "evis_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
+    "evis_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
+    "evis_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
+                                     _VP, ctypes.c_int32, ctypes.POINTER(EvisTuning),
+                                     ctypes.POINTER(ctypes.c_float), _VP]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libevis.so and bind every declared symbol; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libevis.so not built ({path}); run python -m paper_2607_08098_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class EvisError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"evis error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libevis takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libevis takes contiguous tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """Owns one evis_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        rc = lib.evis_create(ctypes.byref(h), int(device))
+        if rc != EVIS_OK:
+            raise EvisError(rc, "evis_create failed")
+        self.handle = h
+        self.device = device
+        self.lib = lib
+
+    def close(self):
+        if self.handle:
+            self.lib.evis_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc: int):
+        if rc != EVIS_OK:
+            raise EvisError(rc, self.lib.evis_last_error(self.handle).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return self.lib.evis_last_error(self.handle).decode()
+
+
+def make_pair(d: dict) -> EvisPair:
+    H, W = int(d["L_A"].shape[-2]), int(d["L_A"].shape[-1])
+    return EvisPair(H, W, _ptr(d["L_A"]), _ptr(d["L_B"]), _ptr(d["m_A"]), _ptr(d["m_B"]),
+                    _ptr(d["Z_A"]), _ptr(d["Z_B"]), int(d.get("t0", 0)), int(d.get("t1", 16667)))
+
+
+def make_sensor(d: dict) -> EvisSensor:
+    return EvisSensor(float(d.get("C_on", 0.2)), float(d.get("C_off", 0.2)),
+                      _ptr(d.get("theta_on")), _ptr(d.get("theta_off")),
+                      int(d.get("refractory_us", 0)), int(d.get("K", 0)), int(d.get("K_max", 64)),
+                      int(d.get("blend_mode", EVIS_BLEND_TIME)))
+
+
+def make_state(d: dict) -> EvisState:
+    return EvisState(_ptr(d["L_ref"]), _ptr(d.get("t_last")))
+
+
+def make_env(d: dict) -> EvisEnv:
+    return EvisEnv(make_pair(d), make_sensor(d), make_state(d), int(d.get("env_id", 0)), 0)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def evis_abi_version() -> int:
+    return load_library().evis_abi_version()
+
+
+def evis_log_luminance(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=None, stream=None):
+    channels = 3 if (x.dim() >= 1 and x.shape[-1] == 3) else 1
+    n = x.numel() // channels
+    shape = x.shape[:-1] if channels == 3 else x.shape
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=x.device)
+    ctx.check(ctx.lib.evis_log_luminance(ctx.handle, _ptr(x), channels, n, eps, _ptr(out), _stream(stream)))
+    return out
+
+
+def evis_state_init(ctx: Context, L_first: torch.Tensor, L_ref: torch.Tensor,
+                    t_last: Optional[torch.Tensor] = None, stream=None):
+    st = EvisState(_ptr(L_ref), _ptr(t_last))
+    H, W = L_first.shape[-2:]
+    ctx.check(ctx.lib.evis_state_init(ctx.handle, _ptr(L_first), H, W, ctypes.byref(st), _stream(stream)))
+
+
+def evis_substep_count(ctx: Context, pair: dict, K_max: int, K_out: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    if K_out is None:
+        K_out = torch.zeros(1, dtype=torch.int32, device=pair["L_A"].device)
+    p = make_pair(pair)
+    ctx.check(ctx.lib.evis_substep_count(ctx.handle, ctypes.byref(p), K_max, _ptr(K_out), _stream(stream)))
+    return K_out
+
+
+def evis_interpolate(ctx: Context, pair: dict, K: int, j_begin: int, j_end: int,
+                     blend_mode: int = EVIS_BLEND_TIME, L_out=None, hole_mask=None,
+                     want_holes: bool = True, stream=None):
+    H, W = pair["L_A"].shape[-2:]
+    dev = pair["L_A"].device
+    if L_out is None:
+        L_out = torch.empty((j_end - j_begin, H, W), dtype=torch.float32, device=dev)
+    if hole_mask is None and want_holes:
+        hole_mask = torch.empty((j_end - j_begin, H, W), dtype=torch.uint8, device=dev)
+    p = make_pair(pair)
+    ctx.check(ctx.lib.evis_interpolate(ctx.handle, ctypes.byref(p), K, j_begin, j_end, blend_mode,
+                                       _ptr(L_out), _ptr(hole_mask), _stream(stream)))
+    return L_out, hole_mask
+
+
+def evis_generate_events(ctx: Context, L_seq: torch.Tensor, t0: int, t1: int, sensor: dict,
+                         state: dict, env_id: int, out: torch.Tensor, n_total: torch.Tensor,
+                         flags: int = EVIS_FLAG_RESET_CURSOR, stream=None):
+    K = L_seq.shape[0] - 1
+    H, W = L_seq.shape[-2:]
+    s = make_sensor(sensor)
+    st = make_state(state)
+    ctx.check(ctx.lib.evis_generate_events(ctx.handle, _ptr(L_seq), H, W, K, int(t0), int(t1),
+                                           ctypes.byref(s), ctypes.byref(st), env_id, _ptr(out),
+                                           out.shape[0], _ptr(n_total), flags, _stream(stream)))
+    return n_total
+
+
+def env_array(envs: Sequence[dict]):
+    arr = (EvisEnv * len(envs))()
+    for i, d in enumerate(envs):
+        arr[i] = make_env(d)
+    return arr
+
+
+def evis_step_batch(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor,
+                    K_used: Optional[torch.Tensor] = None, flags: int = EVIS_FLAG_RESET_CURSOR,
+                    stream=None):
+    """envs: a sequence of env dicts or a prebuilt env_array()."""
+    arr = envs if isinstance(envs, ctypes.Array) else env_array(envs)
+    ctx.check(ctx.lib.evis_step_batch(ctx.handle, arr, len(arr), _ptr(out), out.shape[0],
+                                      _ptr(n_total), _ptr(K_used), flags, _stream(stream)))
+    return n_total
+
+
+def evis_get_tuning(ctx: Context) -> EvisTuning:
+    t = EvisTuning()
+    ctx.check(ctx.lib.evis_get_tuning(ctx.handle, ctypes.byref(t)))
+    return t
+
+
+def evis_set_tuning(ctx: Context, **kw) -> EvisTuning:
+    t = evis_get_tuning(ctx)
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    ctx.check(ctx.lib.evis_set_tuning(ctx.handle, ctypes.byref(t)))
+    return t
+
+
+def evis_autotune(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, reps: int = 3,
+                  stream=None):
+    arr = envs if isinstance(envs, ctypes.Array) else env_array(envs)
+    best = EvisTuning()
+    ms = ctypes.c_float()
+    ctx.check(ctx.lib.evis_autotune(ctx.handle, arr, len(arr), _ptr(out), out.shape[0], _ptr(n_total),
+                                    reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+    return best, ms.value
+
+
+# ---------------------------------------------------------------------------
+# event buffers
+# ---------------------------------------------------------------------------
+
+def event_buffer(capacity: int, device="cuda"):
+    """(events [capacity, 2] int32 of (xyp, t_us), n_total [1] int64)."""
+    return (torch.empty((capacity, 2), dtype=torch.int32, device=device),
+            torch.zeros(1, dtype=torch.int64, device=device))
+
+
+def decode_events(out: torch.Tensor, n_total: torch.Tensor):
+    """Host int64 [N, 5] of (x, y, t, p, env) from the first min(n, capacity) records."""
+    import numpy as np
+    n = int(n_total.item())
+    n = min(n, out.shape[0])
+    rec = out[:n].cpu().numpy()
+    word = rec[:, 0].astype(np.int64) & 0xFFFFFFFF
+    x = word & 0x7FF
+    y = (word >> 11) & 0x7FF
+    p = (word >> 22) & 1
+    env = (word >> 23) & 0x1FF
+    return np.stack([x, y, rec[:, 1].astype(np.int64), p, env], axis=1)

@@ -1,0 +1,54 @@
+"""The C ABI library loads and exports every symbol include/evis.h declares
+(CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "evis.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(evis_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("evis_interpolate", "evis_generate_events", "evis_step_batch", "evis_create",
+                 "evis_destroy", "evis_log_luminance", "evis_substep_count", "evis_autotune"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2607_08098_amd import evis
+    lib = evis.load_library()
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding knows the signature of each of them, and of nothing else
+    assert sorted(evis.SIGNATURES) == names
+
+
+def test_struct_layouts_match_the_header():
+    from paper_2607_08098_amd import evis
+    # evis_pair: 2 int32, 6 pointers, 2 int64
+    assert ctypes.sizeof(evis.EvisPair) == 8 + 6 * 8 + 16
+    assert ctypes.sizeof(evis.EvisSensor) == 8 + 16 + 16
+    assert ctypes.sizeof(evis.EvisState) == 16
+    assert ctypes.sizeof(evis.EvisEnv) == ctypes.sizeof(evis.EvisPair) + 40 + 16 + 8
+    assert ctypes.sizeof(evis.EvisTuning) == 24
+
+
+def test_null_context_is_rejected_without_touching_a_gpu():
+    from paper_2607_08098_amd import evis
+    lib = evis.load_library()
+    assert lib.evis_abi_version() == 1
+    assert lib.evis_step_batch(None, None, 0, None, 0, None, None, 0, None) == evis.EVIS_ERR_INVALID
+    assert lib.evis_interpolate(None, None, 1, 0, 1, 0, None, None, None) == evis.EVIS_ERR_INVALID
+    assert lib.evis_generate_events(None, None, 1, 1, 1, 0, 1, None, None, 0, None, 0, None, 0,
+                                    None) == evis.EVIS_ERR_INVALID
+    assert lib.evis_last_error(None) == b"no context"

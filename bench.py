@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Throughput of the fused event path on one MI355X.
+
+Workload: 64 environments of mixed resolution in one batch (24 x 346x260,
+24 x 640x480, 16 x 1280x720), each a rotating blob scene (omega U[0.5, 20]
+rad/s at 60 Hz, N(0, 0.3) px flow noise, depth U[0.5, 5] m), adaptive K
+(at most 64), C_on = C_off = 0.2.  Inputs are synthetic and resident in HBM
+before timing.  One step = the whole path for one keyframe pair of every
+env: log luminance of the new keyframe (one launch over all envs) and the
+fused, graph-replayed substep count + warp + emit launch, events appended
+to one device stream.
+
+Printed: one JSON line.  value = Mpix-substeps/s (sum over envs of H*W*K
+per step / step time); events/s beside it; the per-env-launch plain form
+(interpolate every sub-frame to HBM, then emit, env by env) and the per-env
+fused form on the same GPU; the roofline of the fused tile kernel, timed
+live with HIP events; the CPU oracle on a bounded sample of the same
+workload (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Algorithmic work of the fused path, per pixel and keyframe pair, from the
+# operation counts of the method's formulas (splat ~14, resolve ~2, bilinear
+# gather ~21, blend ~5, emission ~4 lane-ops per interior substep; emission
+# alone at j = K) and its compulsory traffic (6 input planes, 32 B, plus the
+# reference level read and written, 8 B) plus 8 B per event.
+OPS_INTERIOR = 46
+OPS_LAST = 4
+BYTES_PER_PX = 40
+BYTES_PER_EVENT = 8
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # plain VALU lane-ops: 39.3 T/s
+HBM_PEAK_GBS = 8000.0
+
+KERNEL_SOURCES = ["evis_common.h", "evis_sink.h", "evis_tile.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tile_step_mixed64.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2607_08098_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
+    ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(batch_specs, sample_envs):
+    """The CPU oracle, as it stands, on a bounded sample of the workload:
+    (pixel-substeps done, seconds in the oracle's step, sample names)."""
+    import numpy as np
+    from oracle import evis_oracle as o
+    from paper_2607_08098_amd import scenes
+    work, secs, names = 0.0, 0.0, []
+    for e in sample_envs:
+        H, W, seed = batch_specs[e]
+        sc = scenes.mixed_env(H, W, seed)
+        L_A = o.log_luminance(sc["I_A"]).astype(np.float32)
+        L_B = o.log_luminance(sc["I_B"]).astype(np.float32)
+        pair = o.Pair(L_A, L_B, sc["m_A"], sc["m_B"], sc["Z_A"], sc["Z_B"], 0, 16667)
+        t0 = time.perf_counter()
+        _, _, _, K = o.step(pair, o.Sensor(C_on=0.2, C_off=0.2, K=0, K_max=64), L_A.copy())
+        secs += time.perf_counter() - t0
+        work += H * W * K
+        names.append(f"env{e}:{W}x{H},K={K}")
+    return work, secs, names
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(environments shard by env across GPUs by design; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2607_08098_amd import evis, scenes, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    ctx = evis.Context(0)
+    t = time.time()
+    specs = scenes.mixed_batch_specs(3000)
+    batch = workloads.mixed_batch(ctx, specs=specs)
+    sensor = dict(C_on=0.2, C_off=0.2, K=0, K_max=64, refractory_us=0)
+    envs = batch.env_dicts(sensor)
+    arr = evis.env_array(envs)
+    n_envs = len(envs)
+    torch.cuda.synchronize()
+    log(f"workload ready in {time.time() - t:.1f}s: {n_envs} envs, {batch.n_px} px")
+
+    K_used = torch.zeros(n_envs, dtype=torch.int32, device="cuda")
+    out, n_total = evis.event_buffer(1 << 26)
+
+    def step(flags=0):
+        evis.evis_log_luminance(ctx, batch.I_B, 1e-3, out=batch.L_B)
+        evis.evis_step_batch(ctx, arr, out, n_total, K_used, flags)
+
+    tuning = None
+    if args.tile:
+        tw, th = (int(v) for v in args.tile.lower().split("x"))
+        evis.evis_set_tuning(ctx, tile_w=tw, tile_h=th)
+    elif not args.no_autotune:
+        best, ms = evis.evis_autotune(ctx, arr, out, n_total, reps=3)
+        evis.evis_set_tuning(ctx, **best.as_dict())
+        log(f"autotuned: tile {best.tile_w}x{best.tile_h} ({ms:.3f} ms)")
+    tuning = evis.evis_get_tuning(ctx).as_dict()
+
+    # warmup (the first step also captures the graph); size the event buffer
+    for _ in range(max(1, args.warmup)):
+        n_total.zero_()
+        step()
+    torch.cuda.synchronize()
+    per_step_events = int(n_total.item())
+    need = per_step_events * args.steps * 5 // 4 + 1024
+    if need > out.shape[0]:
+        out, n_total = evis.event_buffer(need)
+        for _ in range(2):
+            n_total.zero_()
+            step()
+    Ks = K_used.cpu().numpy().astype(np.int64)
+    shapes = np.array(batch.shapes, np.int64)
+    px = shapes[:, 0] * shapes[:, 1]
+    mpix_substeps = float((px * Ks).sum()) / 1e6
+
+    # timed region
+    n_total.zero_()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    events_total = int(n_total.item())
+    value = mpix_substeps / (ms_step / 1e3)
+    events_per_s = events_total / (ms_total / 1e3)
+    log(f"batched: {ms_step:.3f} ms/step, {value:.0f} Mpix-substeps/s, {events_per_s:.3e} events/s")
+    if args.quick:
+        print(json.dumps(dict(ms_per_step=ms_step, value=value)))
+        return
+
+    # the fused tile kernel alone, timed with HIP events on its own stream
+    evis.evis_profile_enable(ctx, True)
+    n_total.zero_()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    tile_ms, launches = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
+    evis.evis_profile_enable(ctx, False)
+    tile_ms_avg = tile_ms / max(launches, 1)
+    ev_per_launch = int(n_total.item()) / max(launches, 1)
+    ops = float((px * (OPS_INTERIOR * (Ks - 1) + OPS_LAST)).sum())
+    bytes_ = float(px.sum() * BYTES_PER_PX + BYTES_PER_EVENT * ev_per_launch)
+    t_alu = ops / (ALU_PEAK_TOPS * 1e12)
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("tuning") == [tuning["tile_w"], tuning["tile_h"]]:
+            traffic = tr.get("bytes_per_launch")
+    if t_alu >= t_hbm:
+        achieved = ops / (tile_ms_avg / 1e3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2),
+                    unit="Tops/s", frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=traffic)
+    else:
+        achieved = bytes_ / (tile_ms_avg / 1e3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
+    roof["kernel"] = "k_tile(step)"
+    roof["kernel_ms"] = round(tile_ms_avg, 4)
+    roof["hbm_algorithmic_GBps"] = round(bytes_ / (tile_ms_avg / 1e3) / 1e9, 1)
+    log(f"tile kernel {tile_ms_avg:.3f} ms; roofline {roof}")
+
+    # per-env-launch plain form: every sub-frame to HBM, then the event model
+    plain = None
+    fused_per_env = None
+    if args.plain_steps > 0:
+        Kmax = int(Ks.max())
+        Hmax_W = int(px.max())
+        L_seq = torch.empty((Kmax + 1) * Hmax_W, dtype=torch.float32, device="cuda")
+        pairs = [dict(L_A=d["L_A"], L_B=d["L_B"], m_A=d["m_A"], m_B=d["m_B"], Z_A=d["Z_A"],
+                      Z_B=d["Z_B"], t0=0, t1=16667) for d in envs]
+        st = [dict(L_ref=d["L_ref"]) for d in envs]
+
+        def plain_step():
+            evis.evis_log_luminance(ctx, batch.I_B, 1e-3, out=batch.L_B)
+            for e in range(n_envs):
+                H, W = batch.shapes[e]
+                K = int(Ks[e])
+                Ls = L_seq[: (K + 1) * H * W].view(K + 1, H, W)
+                evis.evis_interpolate(ctx, pairs[e], K, 0, K + 1, evis.EVIS_BLEND_TIME, L_out=Ls,
+                                      want_holes=False)
+                evis.evis_generate_events(ctx, Ls, 0, 16667, sensor, st[e], e, out, n_total, flags=0)
+
+        singles = [evis.env_array([d]) for d in envs]
+
+        def fused_single_step():
+            evis.evis_log_luminance(ctx, batch.I_B, 1e-3, out=batch.L_B)
+            for e in range(n_envs):
+                evis.evis_step_batch(ctx, singles[e], out, n_total, None, 0)
+
+        res = {}
+        for name, fn in (("plain", plain_step), ("fused_per_env", fused_single_step)):
+            fn()
+            n_total.zero_()
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.plain_steps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.plain_steps
+            res[name] = dict(ms_per_step=round(ms, 3), value=round(mpix_substeps / (ms / 1e3), 1))
+            log(f"{name}: {ms:.3f} ms/step")
+        plain, fused_per_env = res["plain"], res["fused_per_env"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        sample = [0, 24]
+        work, secs, names = cpu_baseline(specs, sample)
+        cpu = dict(value=round(work / 1e6 / secs, 4), unit="Mpix-substeps/s", cores=1, kind="oracle",
+                   sample=f"one pair of envs {names} of the 64, {secs:.1f}s in the oracle's step, "
+                          "single-threaded numpy")
+        log(f"cpu oracle: {cpu}")
+
+    rec = dict(
+        metric="Mpix-substeps/s (64 mixed-res envs, batched persistent launch)",
+        value=round(value, 1), unit="Mpix-substeps/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f32", data="synthetic",
+        config=dict(workload="mixed64: 24x346x260 + 24x640x480 + 16x1280x720 rotating blob scenes, "
+                             "adaptive K<=64, C=0.2", n_envs=n_envs, px_per_step=int(px.sum()),
+                    mean_K=round(float(Ks.mean()), 2), mpix_substeps_per_step=round(mpix_substeps, 2),
+                    tuning=tuning),
+        events_per_s=round(events_per_s, 1), events_per_step=round(events_total / args.steps, 1),
+        per_env_plain=plain, per_env_fused=fused_per_env,
+        batched_vs_plain=(round(value / plain["value"], 2) if plain else None),
+        roofline=roof, cpu_baseline=cpu,
+    )
+    print(json.dumps(rec))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -207,6 +207,17 @@ int evis_autotune(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_even
                   int64_t capacity, int64_t *n_total, int32_t reps, evis_tuning *best,
                   float *best_ms, void *stream);
 
+/* Kernel timing.  While profiling is enabled, each call records HIP events
+ * on its stream around its main kernel (the fused tile kernel of
+ * evis_step_batch, the tile kernel of evis_interpolate, the event kernel
+ * of evis_generate_events); evis_step_batch then launches directly
+ * instead of replaying its graph.  evis_profile_read waits for the
+ * recorded events of one kind, returns their summed duration and count,
+ * and forgets them. */
+enum { EVIS_KERNEL_STEP = 0, EVIS_KERNEL_INTERP = 1, EVIS_KERNEL_EVENTS = 2 };
+int evis_profile_enable(evis_ctx *ctx, int32_t enable);
+int evis_profile_read(evis_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,7 +39,7 @@ struct evis_ctx {
   // device scratch
   DevBuf meta;        // EnvDesc[n] followed by int32 src_prefix[n + 1]
   DevBuf dyn;         // EnvDyn[n]
-  DevBuf sched;       // rank_begin[n + 1], env_order[n], n_items, queue counter
+  DevBuf sched;       // xbegin[8][n + 1], env_order[n], n_items[8], queue counters[8]
   DevBuf dz;          // float[sum H*W]
   DevBuf tb;          // float4[sum source tiles]
   DevBuf msq;         // one u64 for evis_substep_count
@@ -52,9 +52,44 @@ struct evis_ctx {
   // graphs
   std::map<std::string, GraphEntry> graphs;
   evis_tuning tuning{32, 32, 0, kListCapMax, 1, 1};
+  // kernel timing
+  bool prof = false;
+  struct Rec { int kind; hipEvent_t e0, e1; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> ev_pool;
 };
 
 namespace {
+
+hipEvent_t pool_event(evis_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Start / stop a timed region around one kernel on stream s (profiling only).
+struct ProfScope {
+  evis_ctx* ctx;
+  int kind;
+  hipStream_t s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(evis_ctx* c, int k, hipStream_t st) : ctx(c), kind(k), s(st) {
+    if (!ctx->prof) return;
+    e0 = pool_event(ctx);
+    e1 = pool_event(ctx);
+    if (e0) hipEventRecord(e0, s);
+  }
+  ~ProfScope() {
+    if (!ctx->prof || !e0 || !e1) return;
+    hipEventRecord(e1, s);
+    ctx->recs.push_back({kind, e0, e1});
+  }
+};
 
 int fail(evis_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -218,6 +253,8 @@ EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st
   return d;
 }
 
+size_t sched_ints(int n) { return (size_t)kXcd * (n + 1) + n + 2 * kXcd; }
+
 struct Plan {
   std::vector<EnvDesc> desc;
   std::vector<int32_t> src_prefix;   // n + 1
@@ -249,7 +286,7 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   if (rc) return rc;
   rc = ensure(ctx, ctx->dyn, (size_t)n * sizeof(EnvDyn), &grew);
   if (rc) return rc;
-  rc = ensure(ctx, ctx->sched, (size_t)(3 * n + 8) * sizeof(int32_t), &grew);
+  rc = ensure(ctx, ctx->sched, sched_ints(n) * sizeof(int32_t), &grew);
   if (rc) return rc;
   if (grew) {
     drop_graphs(ctx);
@@ -274,7 +311,7 @@ std::vector<unsigned char> meta_blob(const Plan& pl) {
 }
 
 struct Sched {
-  int32_t* rank_begin;
+  int32_t* xbegin;
   int32_t* env_order;
   int32_t* n_items;
   unsigned int* queue;
@@ -283,10 +320,10 @@ struct Sched {
 Sched sched_ptrs(evis_ctx* ctx, int n) {
   int32_t* base = static_cast<int32_t*>(ctx->sched.p);
   Sched s;
-  s.rank_begin = base;                 // n + 1
-  s.env_order = base + (n + 1);        // n
-  s.n_items = base + (2 * n + 1);      // 1
-  s.queue = reinterpret_cast<unsigned int*>(base + (2 * n + 2));
+  s.xbegin = base;                               // kXcd * (n + 1)
+  s.env_order = base + kXcd * (n + 1);           // n
+  s.n_items = s.env_order + n;                   // kXcd
+  s.queue = reinterpret_cast<unsigned int*>(s.n_items + kXcd);   // kXcd
   return s;
 }
 
@@ -301,11 +338,11 @@ int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileA
   Sched sc = sched_ptrs(ctx, n);
   EVIS_HIP(launch_reset(d_dyn, n, sc.queue, reset_cursor, s), "k_reset");
   EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n, pl.src_total, s), "k_prep");
-  EVIS_HIP(launch_queue(d_desc, d_dyn, n, tw, th, sc.rank_begin, sc.env_order, sc.n_items, K_used, s),
+  EVIS_HIP(launch_queue(d_desc, d_dyn, n, tw, th, sc.xbegin, sc.env_order, sc.n_items, K_used, s),
            "k_queue");
   ta.envs = d_desc;
   ta.dyn = d_dyn;
-  ta.rank_begin = sc.rank_begin;
+  ta.xbegin = sc.xbegin;
   ta.env_order = sc.env_order;
   ta.n_envs = n;
   ta.queue = sc.queue;
@@ -313,7 +350,10 @@ int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileA
   int occ = tile_occupancy(tw, th, mode);
   int per_cu = ctx->tuning.grid_mult > 0 ? std::min(ctx->tuning.grid_mult, occ) : occ;
   int grid = std::max(1, std::min(pl.items, per_cu * ctx->n_cu));
-  EVIS_HIP(launch_tile(tw, th, mode, ta, grid, s), "k_tile");
+  {
+    ProfScope ps(ctx, mode == MODE_STEP ? EVIS_KERNEL_STEP : EVIS_KERNEL_INTERP, s);
+    EVIS_HIP(launch_tile(tw, th, mode, ta, grid, s), "k_tile");
+  }
   return EVIS_OK;
 }
 
@@ -348,6 +388,11 @@ void evis_destroy(evis_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
   drop_graphs(ctx);
+  for (auto& r : ctx->recs) {
+    hipEventDestroy(r.e0);
+    hipEventDestroy(r.e1);
+  }
+  for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->dz, &ctx->tb, &ctx->msq};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
@@ -481,6 +526,7 @@ int evis_generate_events(evis_ctx* ctx, const float* L_seq, int32_t H, int32_t W
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const int span = (int)(t1_us - t0_us);
   const float Dt = (float)span / (float)K;
+  ProfScope ps(ctx, EVIS_KERNEL_EVENTS, (hipStream_t)stream);
   EVIS_HIP(launch_events(L_seq, H, W, K, t0_us, span, Dt, sensor->C_on, sensor->C_off,
                          sensor->theta_on, sensor->theta_off, sensor->refractory_us,
                          (uint32_t)env_id << 23, state->L_ref, state->t_last, out, capacity,
@@ -532,7 +578,7 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
   ta.capacity = capacity;
   ta.cursor = reinterpret_cast<unsigned long long*>(n_total);
   unsigned long long* reset = (flags & EVIS_FLAG_RESET_CURSOR) ? ta.cursor : nullptr;
-  if (!tu.use_graph) return enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
+  if (!tu.use_graph || ctx->prof) return enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
 
   char key[256];
   std::snprintf(key, sizeof(key), "%d|%d|%d|%p|%lld|%p|%p|%d|%d|%d|%d|%d|%d|%d", (int)pl.desc.size(),
@@ -541,7 +587,7 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
                 ta.list_cap, ta.static_tiles, (int)ctx->meta.bytes);
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
-    if (ctx->graphs.size() >= 32) drop_graphs(ctx);
+    if (ctx->graphs.size() >= 512) drop_graphs(ctx);
     GraphEntry g;
     hipStream_t cs = ctx->capture_stream;
     EVIS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
@@ -577,6 +623,38 @@ int evis_step_batch(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_ev
   if (K_used && !aligned(K_used, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_step_batch: K_used");
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   return run_step(ctx, pl, out, capacity, n_total, K_used, flags, (hipStream_t)stream);
+}
+
+int evis_profile_enable(evis_ctx* ctx, int32_t enable) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  ctx->prof = enable != 0;
+  return EVIS_OK;
+}
+
+int evis_profile_read(evis_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (kernel < EVIS_KERNEL_STEP || kernel > EVIS_KERNEL_EVENTS)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_profile_read: unknown kernel");
+  double sum = 0.0;
+  int64_t cnt = 0;
+  std::vector<evis_ctx::Rec> keep;
+  for (auto& r : ctx->recs) {
+    if (r.kind != kernel) {
+      keep.push_back(r);
+      continue;
+    }
+    EVIS_HIP(hipEventSynchronize(r.e1), "hipEventSynchronize");
+    float ms = 0.0f;
+    EVIS_HIP(hipEventElapsedTime(&ms, r.e0, r.e1), "hipEventElapsedTime");
+    sum += ms;
+    ++cnt;
+    ctx->ev_pool.push_back(r.e0);
+    ctx->ev_pool.push_back(r.e1);
+  }
+  ctx->recs.swap(keep);
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = cnt;
+  return EVIS_OK;
 }
 
 int evis_get_tuning(const evis_ctx* ctx, evis_tuning* out) {

@@ -60,6 +60,30 @@ struct EnvDyn {
   int32_t pad;
 };
 
+// Loads and stores through a global-address-space pointer with a 32-bit
+// element index: the compiler then addresses with the pointer in scalar
+// registers plus a 32-bit offset (no 64-bit address arithmetic per access).
+// (The host compilation pass of this file only parses these device
+// functions; it gets a plain body.)
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, int idx) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(1))) char* gp;
+  return *(const __attribute__((address_space(1))) T*)((gp)p + (unsigned)idx * (unsigned)sizeof(T));
+#else
+  return p[idx];
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* p, int idx, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef __attribute__((address_space(1))) char* gp;
+  *(__attribute__((address_space(1))) T*)((gp)p + (unsigned)idx * (unsigned)sizeof(T)) = v;
+#else
+  p[idx] = v;
+#endif
+}
+
 __device__ __forceinline__ float lerp32(float a, float b, float w) {
   return a + w * (b - a);
 }
@@ -72,8 +96,8 @@ __device__ __forceinline__ float bilinear(const float* __restrict__ img, int H, 
   const float wx = sx - fx0, wy = sy - fy0;
   const int x0 = (int)fx0, y0 = (int)fy0;
   const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
-  const float a = img[y0 * W + x0], b = img[y0 * W + x1];
-  const float c = img[y1 * W + x0], d = img[y1 * W + x1];
+  const float a = ldg(img, y0 * W + x0), b = ldg(img, y0 * W + x1);
+  const float c = ldg(img, y1 * W + x0), d = ldg(img, y1 * W + x1);
   return lerp32(lerp32(a, b, wx), lerp32(c, d, wx), wy);
 }
 
@@ -97,16 +121,19 @@ __device__ __forceinline__ int exact_k(double M, int K_max) {
 }
 
 // Eq. 4 crossing count: floor of the exact quotient a / c for a >= c > 0,
-// capped at kMaxCross.  The float32 quotient gives a candidate; exact
-// float64 products n*c (n < 2^17, c has 24 significant bits) correct it.
+// capped at kMaxCross.  a * rcp(c) is within 0.02 of the quotient below the
+// cap, so one correction step against the exact comparisons n*c <= a <
+// (n+1)*c finishes the job.  fma(n, c, -a) rounds the exact n*c - a once,
+// and rounding never changes the sign of a nonzero value (every float is a
+// multiple of 2^-149, so a nonzero difference never rounds to zero), so the
+// sign of the fma is the sign of n*c - a.
 __device__ __forceinline__ int crossing_count(float a, float c) {
   if (!(a <= 3.402823466e38f)) return kMaxCross;   // a = +inf
-  const float q = a / c;
-  int n = (q > 65536.0f) ? 65536 : (int)floorf(q);
-  const double ad = (double)a, cd = (double)c;
-  if ((double)n * cd > ad)
+  const float q = a * __builtin_amdgcn_rcpf(c);
+  int n = (q >= 65536.0f) ? 65536 : (int)floorf(q);
+  if (fmaf((float)n, c, -a) > 0.0f)
     n -= 1;
-  else if ((double)(n + 1) * cd <= ad)
+  else if (fmaf((float)(n + 1), c, -a) <= 0.0f)
     n += 1;
   return min(n, kMaxCross);
 }
@@ -132,14 +159,17 @@ __device__ __forceinline__ int float_to_ordered(float f) {
   return (i >= 0) ? i : (i ^ 0x7FFFFFFF);
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
+// Inclusive prefix sum across the 64 lanes of a wave: shifts by 1, 2, 4, 8
+// within each row of 16 lanes, then the last lane of row 0 / rows 0-1 is
+// broadcast into the rows after it (DPP row_shr and row_bcast; a lane with
+// no source lane reads 0).
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const int t = __shfl_up(v, d, kWave);
-    if (lane >= d) v += t;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
   return v;
 }
 

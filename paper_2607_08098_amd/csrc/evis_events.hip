@@ -85,48 +85,50 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   __shared__ uint2 evbuf[kEventBuf];
   __shared__ int s_wtot[2][kWavesPerBlock];
   __shared__ unsigned long long s_gbase;
+  __shared__ float s_con[kBlock * PPT], s_coff[kBlock * PPT];
+  __shared__ int s_tl[kBlock * PPT];
   const SinkShared sh{evbuf, s_wtot, &s_gbase, kEventBuf};
   const SinkOut so{a.out, a.capacity, a.cursor};
   const int tid = threadIdx.x;
   const long long plane = (long long)a.H * a.W;
   const long long base = (long long)blockIdx.x * (kBlock * PPT);
-  float R[PPT], Lp[PPT], Lj[PPT], Ln[PPT], con[PPT], coff[PPT];
-  int tl[PPT];
-  uint32_t xy[PPT];
-  long long qi[PPT];
+  float R[PPT], Lp[PPT], Lj[PPT], Ln[PPT];
   uint32_t okbits = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
-    const long long q = base + tid + (long long)k * kBlock;
+    const int i = tid + k * kBlock;
+    const long long q = base + i;
     const bool ok = q < plane;
     okbits |= (ok ? 1u : 0u) << k;
-    qi[k] = ok ? q : 0;
-    const int x = (int)(qi[k] % a.W), y = (int)(qi[k] / a.W);
-    xy[k] = (uint32_t)x | ((uint32_t)y << 11);
     R[k] = ok ? a.Lref[q] : 0.0f;
-    tl[k] = (ok && a.tlast) ? a.tlast[q] : EVIS_T_LAST_INIT;
-    con[k] = (ok && a.th_on) ? a.th_on[q] : a.C_on;
-    coff[k] = (ok && a.th_off) ? a.th_off[q] : a.C_off;
+    s_tl[i] = (ok && a.tlast) ? a.tlast[q] : EVIS_T_LAST_INIT;
+    if (a.th_on) s_con[i] = ok ? a.th_on[q] : 1.0f;
+    if (a.th_off) s_coff[i] = ok ? a.th_off[q] : 1.0f;
     Lp[k] = ok ? a.L_seq[q] : 0.0f;
     Ln[k] = ok ? a.L_seq[plane + q] : 0.0f;
   }
+  const PixAux aux{a.th_on ? s_con : nullptr, a.th_off ? s_coff : nullptr, s_tl, a.C_on, a.C_off,
+                   0, 0, a.W, 0, base};
   int ev_count = 0, round = 0;
   for (int j = 1; j <= a.K; ++j) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       Lj[k] = Ln[k];
-      if (j < a.K) Ln[k] = ((okbits >> k) & 1u) ? a.L_seq[(long long)(j + 1) * plane + qi[k]] : 0.0f;
+      if (j < a.K)
+        Ln[k] = ((okbits >> k) & 1u) ? a.L_seq[(long long)(j + 1) * plane + base + tid + k * kBlock]
+                                     : 0.0f;
     }
-    emit_substep<PPT>(j, Lj, Lp, R, tl, con, coff, xy, okbits, a.t0, a.span, a.Dt, a.refr,
-                      a.env_bits, sh, so, ev_count, round);
+    emit_substep<PPT>(j, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.refr, a.env_bits, sh, so,
+                      ev_count, round);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) Lp[k] = Lj[k];
   }
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     if ((okbits >> k) & 1u) {
-      a.Lref[qi[k]] = R[k];
-      if (a.tlast) a.tlast[qi[k]] = tl[k];
+      const long long q = base + tid + k * kBlock;
+      a.Lref[q] = R[k];
+      if (a.tlast) a.tlast[q] = s_tl[tid + k * kBlock];
     }
   }
   sink_flush(sh, so, ev_count);

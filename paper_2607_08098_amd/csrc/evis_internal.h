@@ -14,17 +14,18 @@ enum Mode { MODE_STEP = 0, MODE_INTERP = 1, MODE_SOFT_FWD = 2, MODE_SOFT_BWD = 3
 
 constexpr int kListCapMax = 1024;   // per-tile candidate source tiles held in LDS
 constexpr int kEventBuf = 2048;     // events staged in LDS per workgroup
+constexpr int kXcd = 8;             // work queues: one per accelerator complex die
 
 // Arguments of the fused tile kernel (all device pointers).
 struct TileArgs {
   const EnvDesc* envs;
   EnvDyn* dyn;
-  const int32_t* rank_begin;   // [n_envs + 1] first item of the env of each rank
+  const int32_t* xbegin;       // [kXcd][n_envs + 1] first item of each rank in queue x
   const int32_t* env_order;    // [n_envs] env index of each rank
   int32_t n_envs;
   int32_t list_cap;
-  unsigned int* queue;         // work-queue counter (zeroed before the launch)
-  const int32_t* n_items;      // device: total work items
+  unsigned int* queue;         // [kXcd] work-queue counters (zeroed before the launch)
+  const int32_t* n_items;      // [kXcd] items of each queue
   int32_t static_tiles;
   // MODE_STEP
   evis_event* out;
@@ -48,11 +49,11 @@ struct TileArgs {
 
 // Kernel launchers (defined in evis_tile.hip / evis_events.hip).
 hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
-                        unsigned long long* cursor, hipStream_t s);
+                        unsigned long long* cursor, hipStream_t s);   // queue: kXcd counters
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
                        int total_src_tiles, hipStream_t s);
 hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,
-                        int32_t* rank_begin, int32_t* env_order, int32_t* n_items,
+                        int32_t* xbegin, int32_t* env_order, int32_t* n_items,
                         int32_t* K_used, hipStream_t s);
 hipError_t launch_tile(int tile_w, int tile_h, int mode, const TileArgs& a, int grid,
                        hipStream_t s);

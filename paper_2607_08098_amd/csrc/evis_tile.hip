@@ -32,10 +32,8 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
                         unsigned long long* cursor) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_envs) dyn[i].msq_bits = 0ull;
-  if (i == 0) {
-    queue[0] = 0u;
-    if (cursor) *cursor = 0ull;
-  }
+  if (i < kXcd) queue[i] = 0u;
+  if (i == 0 && cursor) *cursor = 0ull;
 }
 
 // One wave per 8x8 source tile: endpoint depth (Eq. 7, p_B = p - m_A(p),
@@ -44,17 +42,20 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
 __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ envs, EnvDyn* dyn,
                                                  const int32_t* __restrict__ src_prefix,
                                                  int n_envs, int total) {
+  __shared__ int s_prefix[EVIS_MAX_ENVS + 1];
+  for (int i = threadIdx.x; i <= n_envs; i += kBlock) s_prefix[i] = src_prefix[i];
+  __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
   const int gt = blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
   if (gt >= total) return;   // wave-uniform
   int lo = 0, hi = n_envs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (src_prefix[mid] <= gt) lo = mid; else hi = mid - 1;
+    if (s_prefix[mid] <= gt) lo = mid; else hi = mid - 1;
   }
   const int e = lo;
   const EnvDesc& d = envs[e];
-  const int t = gt - src_prefix[e];
+  const int t = gt - s_prefix[e];
   const int tx = t % d.ntx_src, ty = t / d.ntx_src;
   const int x = tx * kSrcTile + (lane & 7), y = ty * kSrcTile + (lane >> 3);
   const float inf = __int_as_float(0x7f800000);
@@ -62,12 +63,12 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
   double msq = 0.0;
   if (x < d.W && y < d.H) {
     const int p = y * d.W + x;
-    const float2 a = d.mA[p];
-    const float2 b = d.mB[p];
+    const float2 a = ldg(d.mA, p);
+    const float2 b = ldg(d.mB, p);
     const float sx = clamp_into((float)x - a.x, (float)(d.W - 1));
     const float sy = clamp_into((float)y - a.y, (float)(d.H - 1));
     const float zend = bilinear(d.ZB, d.H, d.W, sx, sy);
-    d.dZ[p] = zend - d.ZA[p];
+    stg(d.dZ, p, zend - ldg(d.ZA, p));
     if (finite32(a.x) && finite32(a.y)) {
       mnx = mxx = a.x;
       mny = mxy = a.y;
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
   mxy = wave_max(mxy);
   msq = wave_max_d(msq);
   if (lane == 0) {
-    d.tb[t] = make_float4(mnx, mxx, mny, mxy);
+    stg(d.tb, t, make_float4(mnx, mxx, mny, mxy));
     if (msq > 0.0) {
       unsigned long long* slot = &dyn[e].msq_bits;
       const unsigned long long bits = (unsigned long long)__double_as_longlong(msq);
@@ -93,15 +94,16 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
 }
 
 // Single workgroup: each env's K (fixed or the exact adaptive count), its
-// substep length Dt = fl(fl(t1 - t0) / K), its tile grid, and the work
-// queue order: envs by descending K (longest items first), items numbered
-// consecutively in that order.
+// substep length Dt = fl(fl(t1 - t0) / K) and tile grid, and the work
+// queues.  Envs are ranked by descending K (longest items first).  Queue x
+// holds horizontal band x of every env (tile rows [x*nty/8, (x+1)*nty/8)),
+// rank by rank, so that the workgroups of one XCD work on neighbouring
+// tiles and share their sources in that XCD's L2.
 __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restrict__ envs,
                                                           EnvDyn* dyn, int n_envs, int TW, int TH,
-                                                          int32_t* rank_begin, int32_t* env_order,
+                                                          int32_t* xbegin, int32_t* env_order,
                                                           int32_t* n_items, int32_t* K_used) {
   __shared__ int sK[EVIS_MAX_ENVS];
-  __shared__ int sN[EVIS_MAX_ENVS];
   __shared__ int sOrder[EVIS_MAX_ENVS];
   __shared__ int sScan[EVIS_MAX_ENVS];
   const int e = threadIdx.x;
@@ -111,14 +113,12 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
     const double M = __longlong_as_double((long long)dyn[e].msq_bits);
     K = (d.K_fixed > 0) ? d.K_fixed : exact_k(M, d.K_max);
     const float Dt = (float)d.span / (float)K;
-    const int ntx = (d.W + TW - 1) / TW, nty = (d.H + TH - 1) / TH;
     dyn[e].K = K;
     dyn[e].Dt = Dt;
-    dyn[e].ntx = ntx;
-    dyn[e].nty = nty;
+    dyn[e].ntx = (d.W + TW - 1) / TW;
+    dyn[e].nty = (d.H + TH - 1) / TH;
     if (K_used) K_used[e] = K;
     sK[e] = K;
-    sN[e] = ntx * nty;
   }
   __syncthreads();
   if (e < n_envs) {
@@ -130,24 +130,28 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
     sOrder[r] = e;
   }
   __syncthreads();
-  const int v = (e < n_envs) ? sN[sOrder[e]] : 0;
-  sScan[e] = v;
-  __syncthreads();
-  for (int dd = 1; dd < EVIS_MAX_ENVS; dd <<= 1) {
-    const int t = (e >= dd) ? sScan[e - dd] : 0;
+  if (e < n_envs) env_order[e] = sOrder[e];
+  for (int x = 0; x < kXcd; ++x) {
+    int v = 0;
+    if (e < n_envs) {
+      const int env = sOrder[e];
+      const int nty = (envs[env].H + TH - 1) / TH, ntx = (envs[env].W + TW - 1) / TW;
+      v = ntx * ((x + 1) * nty / kXcd - x * nty / kXcd);
+    }
+    sScan[e] = v;
     __syncthreads();
-    sScan[e] += t;
+    for (int dd = 1; dd < EVIS_MAX_ENVS; dd <<= 1) {
+      const int t = (e >= dd) ? sScan[e - dd] : 0;
+      __syncthreads();
+      sScan[e] += t;
+      __syncthreads();
+    }
+    if (e < n_envs) xbegin[x * (n_envs + 1) + e] = sScan[e] - v;
+    if (e == n_envs - 1) {
+      xbegin[x * (n_envs + 1) + n_envs] = sScan[e];
+      n_items[x] = sScan[e];
+    }
     __syncthreads();
-  }
-  if (e < n_envs) {
-    const int env = sOrder[e];
-    rank_begin[e] = sScan[e] - v;
-    env_order[e] = env;
-    dyn[env].item_begin = sScan[e] - v;
-  }
-  if (e == n_envs - 1) {
-    rank_begin[n_envs] = sScan[e];
-    *n_items = sScan[e];
   }
 }
 
@@ -161,155 +165,242 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
 // only if q_x = p_x - f m_x is in [Tx0 - 1, Tx1 + 1); over the tile q_x lies
 // in [Sx0 - f max m_x, Sx1 - f min m_x].  One pixel of slack covers
 // rounding; the substep range is widened by one on each side.
-__device__ __forceinline__ void lin_le(double a, double bnd, double& flo, double& fhi) {
-  if (a > 0.0) fhi = fmin(fhi, bnd / a);        // a f <= bnd
-  else if (a < 0.0) flo = fmax(flo, bnd / a);
-  else if (bnd < 0.0) flo = 2.0;
+__device__ __forceinline__ void lin_le(float a, float bnd, float& flo, float& fhi) {
+  if (a > 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));        // a f <= bnd
+  else if (a < 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));
+  else if (bnd < 0.0f) flo = 2.0f;
 }
-__device__ __forceinline__ void lin_ge(double a, double bnd, double& flo, double& fhi) {
-  if (a > 0.0) flo = fmax(flo, bnd / a);        // a f >= bnd
-  else if (a < 0.0) fhi = fmin(fhi, bnd / a);
-  else if (bnd > 0.0) flo = 2.0;
+__device__ __forceinline__ void lin_ge(float a, float bnd, float& flo, float& fhi) {
+  if (a > 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));        // a f >= bnd
+  else if (a < 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));
+  else if (bnd > 0.0f) flo = 2.0f;
 }
 
+// (the bounds are conservative by a pixel and the substep range is widened
+// by one substep each side, far beyond the error of the fast division)
 __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy0, int Sy1,
                                               int Tx0, int Tx1, int Ty0, int Ty1, int K,
                                               int& jlo, int& jhi) {
   if (!(b.x <= b.y) || !(b.z <= b.w)) return false;   // no finite source
-  double flo = 0.0, fhi = 1.0;
-  const double slack = 1.0;
-  lin_le((double)b.x, (double)(Sx1 - Tx0 + 1) + slack, flo, fhi);
-  lin_ge((double)b.y, (double)(Sx0 - Tx1 - 1) - slack, flo, fhi);
-  lin_le((double)b.z, (double)(Sy1 - Ty0 + 1) + slack, flo, fhi);
-  lin_ge((double)b.w, (double)(Sy0 - Ty1 - 1) - slack, flo, fhi);
+  float flo = 0.0f, fhi = 1.0f;
+  const float slack = 1.0f;
+  lin_le(b.x, (float)(Sx1 - Tx0 + 1) + slack, flo, fhi);
+  lin_ge(b.y, (float)(Sx0 - Tx1 - 1) - slack, flo, fhi);
+  lin_le(b.z, (float)(Sy1 - Ty0 + 1) + slack, flo, fhi);
+  lin_ge(b.w, (float)(Sy0 - Ty1 - 1) - slack, flo, fhi);
   if (!(flo <= fhi)) return false;
-  const int lo = max(1, (int)floor(flo * (double)K));
-  const int hi = min(K - 1, (int)ceil(fhi * (double)K));
+  const int lo = max(1, (int)floorf(flo * (float)K) - 1);
+  const int hi = min(K - 1, (int)ceilf(fhi * (float)K) + 1);
   if (lo > hi) return false;
   jlo = lo;
   jhi = hi;
   return true;
 }
 
-// Splat the 64 sources of source tile st (one per lane) at fraction f into
-// the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].
+// The LDS z-buffer of a TW x TH target tile has rows of ZS(TW) = TW + 8
+// keys: consecutive rows then start 64 bytes apart in the 32 banks, so the
+// 8 rows touched by one source tile's footprint spread over all banks.
 template <int TW>
-__device__ __forceinline__ void splat_src_tile(const EnvDesc& d, int st, float f, int Tx0, int Tx1,
-                                               int Ty0, int Ty1, unsigned long long* zbuf) {
+__device__ __forceinline__ constexpr int zrow() { return TW + 8; }
+
+// Splat up to kChunk source tiles (one source per lane and tile) at fraction
+// f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].  The loads of
+// all tiles of the chunk are issued before any of them is used.
+constexpr int kChunk = 4;
+
+template <int TW>
+__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kChunk], int nb,
+                                            float f, int Tx0, int Tx1, int Ty0, int Ty1,
+                                            unsigned long long* zbuf) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int sxt = st % d.ntx_src, syt = st / d.ntx_src;
-  const int sx = sxt * kSrcTile + (lane & 7), sy = syt * kSrcTile + (lane >> 3);
-  if (sx >= d.W || sy >= d.H) return;
-  const int p = sy * d.W + sx;
-  const float2 m = d.mA[p];
-  const float za = d.ZA[p];
-  const float dz = d.dZ[p];
-  const float qx = (float)sx - f * m.x;
-  const float qy = (float)sy - f * m.y;
-  const float zt = za + f * dz;
-  if (!(zt > 0.0f)) return;
-  if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
-        qy < (float)(Ty1 + 1)))
-    return;
-  const float fx0 = floorf(qx), fy0 = floorf(qy);
+  float2 m[kChunk];
+  float za[kChunk], dz[kChunk];
+  int sxs[kChunk], sys[kChunk];
+  bool ok[kChunk];
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c) {
+    ok[c] = false;
+    sxs[c] = 0;
+    sys[c] = 0;
+    if (c < nb) {
+      const int sxt = st[c] >> 8, syt = st[c] & 0xFF;   // wave-uniform
+      sxs[c] = sxt * kSrcTile + (lane & 7);
+      sys[c] = syt * kSrcTile + (lane >> 3);
+      ok[c] = (sxs[c] < d.W) && (sys[c] < d.H);
+    }
+    if (ok[c]) {
+      const int p = sys[c] * d.W + sxs[c];
+      m[c] = ldg(d.mA, p);
+      za[c] = ldg(d.ZA, p);
+      dz[c] = ldg(d.dZ, p);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c) {
+    if (!ok[c]) continue;
+    const float qx = (float)sxs[c] - f * m[c].x;
+    const float qy = (float)sys[c] - f * m[c].y;
+    const float zt = za[c] + f * dz[c];
+    if (!(zt > 0.0f)) continue;
+    if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
+          qy < (float)(Ty1 + 1)))
+      continue;
+    const float fx0 = floorf(qx), fy0 = floorf(qy);
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const bool bx = (qx - fx0) > 0.0f, by = (qy - fy0) > 0.0f;
+    const unsigned p = (unsigned)(sys[c] * d.W + sxs[c]);
+    const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | p;
+    const int lx = x0 - Tx0, ly = y0 - Ty0;
+    const bool in_x0 = x0 >= Tx0, in_x1 = bx && (x0 + 1 <= Tx1);
+    const bool in_y0 = y0 >= Ty0, in_y1 = by && (y0 + 1 <= Ty1);
+    constexpr int ZS = zrow<TW>();
+    unsigned long long* zr = zbuf + ly * ZS + lx;
+    if (in_x0 && in_y0) atomicMin(zr, key);
+    if (in_x1 && in_y0) atomicMin(zr + 1, key);
+    if (in_x0 && in_y1) atomicMin(zr + ZS, key);
+    if (in_x1 && in_y1) atomicMin(zr + ZS + 1, key);
+  }
+}
+
+// B gather at fraction g = 1 - f for one target pixel (x, y): the sample
+// position s = (x, y) - g m_B, its validity and the four taps of its cell.
+struct BTaps {
+  float a, b, c, d, wx, wy;
+  bool v;
+};
+
+__device__ __forceinline__ BTaps b_taps(const EnvDesc& d, int x, int y, float2 mB, float g,
+                                        bool pixel_ok) {
+  BTaps t;
+  const float sx = (float)x - g * mB.x;
+  const float sy = (float)y - g * mB.y;
+  t.v = pixel_ok && sx >= 0.0f && sx <= (float)(d.W - 1) && sy >= 0.0f && sy <= (float)(d.H - 1);
+  const float sxc = t.v ? sx : 0.0f, syc = t.v ? sy : 0.0f;
+  const float fx0 = floorf(sxc), fy0 = floorf(syc);
+  t.wx = sxc - fx0;
+  t.wy = syc - fy0;
   const int x0 = (int)fx0, y0 = (int)fy0;
-  const bool bx = (qx - fx0) > 0.0f, by = (qy - fy0) > 0.0f;
-  const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | (unsigned)p;
-  const int lx = x0 - Tx0, ly = y0 - Ty0;
-  const bool in_x0 = x0 >= Tx0, in_x1 = bx && (x0 + 1 <= Tx1);
-  const bool in_y0 = y0 >= Ty0, in_y1 = by && (y0 + 1 <= Ty1);
-  if (in_x0 && in_y0) atomicMin(&zbuf[ly * TW + lx], key);
-  if (in_x1 && in_y0) atomicMin(&zbuf[ly * TW + lx + 1], key);
-  if (in_x0 && in_y1) atomicMin(&zbuf[(ly + 1) * TW + lx], key);
-  if (in_x1 && in_y1) atomicMin(&zbuf[(ly + 1) * TW + lx + 1], key);
+  const int x1 = min(x0 + 1, d.W - 1), y1 = min(y0 + 1, d.H - 1);
+  t.a = t.b = t.c = t.d = 0.0f;
+  if (t.v) {
+    t.a = ldg(d.LB, y0 * d.W + x0);
+    t.b = ldg(d.LB, y0 * d.W + x1);
+    t.c = ldg(d.LB, y1 * d.W + x0);
+    t.d = ldg(d.LB, y1 * d.W + x1);
+  }
+  return t;
+}
+
+__device__ __forceinline__ float b_value(const BTaps& t) {
+  return lerp32(lerp32(t.a, t.b, t.wx), lerp32(t.c, t.d, t.wx), t.wy);
 }
 
 // ---------------------------------------------------------------------------
 // the persistent tile kernel
 // ---------------------------------------------------------------------------
 
+// Per substep j of an item: (1) issue the B-gather loads of j, (2) splat j
+// into the LDS z-buffer, (3) read the winners of j and issue the loads of
+// their L_A, (4) blend and emit substep j - 1, whose loads were issued one
+// substep earlier.  The z-buffer is cleared by its readers in (3); the
+// barrier of (4) orders that before the next splat.
 template <int TW, int TH, int MODE>
-__global__ __launch_bounds__(kBlock) void k_tile(const TileArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int NPX = TW * TH;
   constexpr int PPT = NPX / kBlock;
   static_assert(PPT * kBlock == NPX, "tile must be a multiple of the workgroup");
   constexpr int EVB = (MODE == MODE_STEP) ? kEventBuf : 1;
-  __shared__ unsigned long long zbuf[NPX];
+  constexpr int ZS = zrow<TW>();
+  __shared__ unsigned long long zbuf[ZS * TH];
   __shared__ uint32_t list[kListCapMax];
   __shared__ uint2 evbuf[EVB];
   __shared__ int s_wtot[2][kWavesPerBlock];
   __shared__ unsigned long long s_gbase;
-  __shared__ int s_item, s_rank, s_lcnt;
+  __shared__ int s_item, s_rank, s_q, s_lcnt;
+  constexpr int AUXN = (MODE == MODE_STEP) ? NPX : 1;
+  __shared__ float s_con[AUXN], s_coff[AUXN];
+  __shared__ int s_tl[AUXN];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) zbuf[tid + k * kBlock] = kEmptyKey;
+  for (int i = tid; i < ZS * TH; i += kBlock) zbuf[i] = kEmptyKey;
   const SinkShared sh{evbuf, s_wtot, &s_gbase, EVB};
   const SinkOut so{a.out, a.capacity, a.cursor};
   int ev_count = 0, round = 0;
-  const int n_items = *a.n_items;
+  const int home = (int)(blockIdx.x % kXcd);
+  int qsel = 0;   // 0..kXcd-1: queues tried so far (own queue first, then stealing)
+  int rcur = 0;   // rank of the last item taken from the current queue
 
   for (;;) {
     __syncthreads();
     if (tid == 0) {
-      const int item = (int)atomicAdd(a.queue, 1u);
-      int r = 0;
-      if (item < n_items) {
-        int lo = 0, hi = a.n_envs - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (a.rank_begin[mid] <= item) lo = mid; else hi = mid - 1;
+      int item = -1, r = 0, q = -1;
+      while (qsel < kXcd) {
+        const int qq = (home + qsel) % kXcd;
+        const int it = (int)atomicAdd(&a.queue[qq], 1u);
+        if (it < a.n_items[qq]) {
+          item = it;
+          q = qq;
+          break;
         }
-        r = lo;
+        ++qsel;
+        rcur = 0;
+      }
+      if (item >= 0) {
+        // items of a queue are taken in increasing order: walk ranks forward
+        const int32_t* xb = a.xbegin + q * (a.n_envs + 1);
+        r = rcur;
+        while (r + 1 < a.n_envs && xb[r + 1] <= item) ++r;
+        rcur = r;
       }
       s_item = item;
       s_rank = r;
+      s_q = q;
       s_lcnt = 0;
     }
     __syncthreads();
     const int item = __builtin_amdgcn_readfirstlane(s_item);
-    if (item >= n_items) break;
+    if (item < 0) break;
     const int rank = __builtin_amdgcn_readfirstlane(s_rank);
+    const int q = __builtin_amdgcn_readfirstlane(s_q);
     const int env = __builtin_amdgcn_readfirstlane(a.env_order[rank]);
     const EnvDesc d = a.envs[env];
     const EnvDyn dy = a.dyn[env];
-    const int tile = item - a.rank_begin[rank];
+    const int li = item - a.xbegin[q * (a.n_envs + 1) + rank];
     const int H = d.H, W = d.W, K = dy.K;
-    const int tx = tile % dy.ntx, ty = tile / dy.ntx;
+    const int row0 = q * dy.nty / kXcd;
+    const int tx = li % dy.ntx, ty = row0 + li / dy.ntx;
     const int Tx0 = tx * TW, Ty0 = ty * TH;
     const int Tx1 = min(Tx0 + TW, W) - 1, Ty1 = min(Ty0 + TH, H) - 1;
 
-    // per-pixel registers
-    float LAq[PPT], LBq[PPT], Lp[PPT], R[PPT], con[PPT], coff[PPT];
+    // per-pixel registers; pixel k of this thread is i = tid + k * kBlock,
+    // at (Tx0 + i % TW, Ty0 + i / TW)
+    float LAq[PPT], LBq[PPT], Lp[PPT], R[PPT];
     float2 mBq[PPT];
-    int tl[PPT];
-    uint32_t xy[PPT];
-    int qi[PPT];
     uint32_t okbits = 0;
+    auto pix_x = [&](int k) { return Tx0 + (tid + k * kBlock) % TW; };
+    auto pix_y = [&](int k) { return Ty0 + (tid + k * kBlock) / TW; };
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      const int i = tid + k * kBlock;
-      const int x = Tx0 + i % TW, y = Ty0 + i / TW;
+      const int x = pix_x(k), y = pix_y(k);
       const bool ok = (x <= Tx1) && (y <= Ty1);
-      const int q = ok ? (y * W + x) : 0;
+      const int qq = ok ? (y * W + x) : 0;
       okbits |= (ok ? 1u : 0u) << k;
-      qi[k] = q;
-      xy[k] = (uint32_t)x | ((uint32_t)y << 11);
-      LAq[k] = ok ? d.LA[q] : 0.0f;
-      LBq[k] = ok ? d.LB[q] : 0.0f;
-      mBq[k] = ok ? d.mB[q] : make_float2(0.0f, 0.0f);
+      LAq[k] = ok ? ldg(d.LA, qq) : 0.0f;
+      LBq[k] = ok ? ldg(d.LB, qq) : 0.0f;
+      mBq[k] = ok ? ldg(d.mB, qq) : make_float2(0.0f, 0.0f);
       Lp[k] = LAq[k];
       R[k] = 0.0f;
-      tl[k] = EVIS_T_LAST_INIT;
-      con[k] = d.C_on;
-      coff[k] = d.C_off;
       if (MODE == MODE_STEP) {
-        R[k] = ok ? d.Lref[q] : 0.0f;
-        if (ok && d.tlast) tl[k] = d.tlast[q];
-        if (ok && d.th_on) con[k] = d.th_on[q];
-        if (ok && d.th_off) coff[k] = d.th_off[q];
+        const int i = tid + k * kBlock;
+        R[k] = ok ? ldg(d.Lref, qq) : 0.0f;
+        s_tl[i] = (ok && d.tlast) ? ldg(d.tlast, qq) : EVIS_T_LAST_INIT;
+        if (d.th_on) s_con[i] = ok ? ldg(d.th_on, qq) : 1.0f;
+        if (d.th_off) s_coff[i] = ok ? ldg(d.th_off, qq) : 1.0f;
       }
     }
+    const PixAux aux{(MODE == MODE_STEP && d.th_on) ? s_con : nullptr,
+                     (MODE == MODE_STEP && d.th_off) ? s_coff : nullptr, s_tl, d.C_on, d.C_off,
+                     Tx0, Ty0, TW, __builtin_ctz(TW), -1};
 
     // Candidate source tiles and their substep intervals.
     int nlist = 0, wx0 = 0, wy0 = 0, nwx = 0, nwin = 0;
@@ -327,11 +418,12 @@ __global__ __launch_bounds__(kBlock) void k_tile(const TileArgs a) {
         const int sxt = wx0 + w % nwx, syt = wy0 + w / nwx;
         const int st = syt * d.ntx_src + sxt;
         int jlo, jhi;
-        if (substep_range(d.tb[st], sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
+        if (substep_range(ldg(d.tb, st), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
                           syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1,
                           K, jlo, jhi)) {
           const int slot = atomicAdd(&s_lcnt, 1);
-          if (slot < a.list_cap) list[slot] = ((uint32_t)st << 16) | ((uint32_t)jlo << 8) | (uint32_t)jhi;
+          if (slot < a.list_cap)
+            list[slot] = ((uint32_t)sxt << 24) | ((uint32_t)syt << 16) | ((uint32_t)jlo << 8) | (uint32_t)jhi;
         }
       }
       __syncthreads();
@@ -345,16 +437,17 @@ __global__ __launch_bounds__(kBlock) void k_tile(const TileArgs a) {
     if (MODE == MODE_STEP && a.static_tiles && K > 1 && !overflow) {
       bool okst = true;
       for (int e2 = tid; e2 < nlist; e2 += kBlock) {
-        const float4 b = d.tb[list[e2] >> 16];
+        const uint32_t ent = list[e2];
+        const float4 b = ldg(d.tb, (int)((ent >> 16) & 0xFFu) * d.ntx_src + (int)(ent >> 24));
         okst = okst && b.x == 0.0f && b.y == 0.0f && b.z == 0.0f && b.w == 0.0f;
       }
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if ((okbits >> k) & 1u) {
-          const int q = qi[k];
-          const int x = q % W, y = q / W;
+          const int x = pix_x(k), y = pix_y(k);
           const int x1 = min(x + 1, W - 1), y1 = min(y + 1, H - 1);
-          const float t1 = d.LB[y * W + x1], t2 = d.LB[y1 * W + x], t3 = d.LB[y1 * W + x1];
+          const float t1 = ldg(d.LB, y * W + x1), t2 = ldg(d.LB, y1 * W + x);
+          const float t3 = ldg(d.LB, y1 * W + x1);
           okst = okst && mBq[k].x == 0.0f && mBq[k].y == 0.0f && LAq[k] == LBq[k] &&
                  fabsf(LBq[k]) < 1e30f && fabsf(t1) < 1e30f && fabsf(t2) < 1e30f &&
                  fabsf(t3) < 1e30f;
@@ -369,8 +462,9 @@ __global__ __launch_bounds__(kBlock) void k_tile(const TileArgs a) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           if ((okbits >> k) & 1u) {
-            a.L_out[qi[k]] = LAq[k];
-            if (a.hole) a.hole[qi[k]] = 0;
+            const int qq = pix_y(k) * W + pix_x(k);
+            a.L_out[qq] = LAq[k];
+            if (a.hole) a.hole[qq] = 0;
           }
         }
       }
@@ -378,104 +472,166 @@ __global__ __launch_bounds__(kBlock) void k_tile(const TileArgs a) {
       j_last = min(K, a.j_end - 1);
     }
 
-    for (int j = j_first; j <= j_last; ++j) {
-      float Lj[PPT];
-      uint32_t hb[PPT];
-      if (j < K) {
-        const float f = (float)j / (float)K;
-        const float g = 1.0f - f;
-        const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
-        if (!is_static) {
-          if (!overflow) {
-            for (int base = 0; base < nlist; base += kBlock) {
-              const int e2 = base + lane * kWavesPerBlock + wave;
-              uint32_t ent = 0u;
-              bool act = false;
-              if (e2 < nlist) {
-                ent = list[e2];
-                const int jlo = (int)((ent >> 8) & 0xFFu), jhi = (int)(ent & 0xFFu);
-                act = (j >= jlo) && (j <= jhi);
-              }
-              unsigned long long mask = __ballot(act);
-              while (mask) {
-                const int b = __ffsll((long long)mask) - 1;
-                mask &= mask - 1ull;
-                const int st = (int)((uint32_t)__builtin_amdgcn_readlane((int)ent, b) >> 16);
-                splat_src_tile<TW>(d, st, f, Tx0, Tx1, Ty0, Ty1, zbuf);
-              }
-            }
-          } else {
-            // Window scan: the candidate list did not fit.
-            for (int w = wave; w < nwin; w += kWavesPerBlock) {
-              const int sxt = wx0 + w % nwx, syt = wy0 + w / nwx;
-              const int st = syt * d.ntx_src + sxt;
-              int jlo, jhi;
-              if (substep_range(d.tb[st], sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
-                                syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0,
-                                Ty1, K, jlo, jhi) &&
-                  j >= jlo && j <= jhi)
-                splat_src_tile<TW>(d, st, f, Tx0, Tx1, Ty0, Ty1, zbuf);
-            }
-          }
-          __syncthreads();
-        }
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          hb[k] = 0u;
-          Lj[k] = LAq[k];
-          if (((okbits >> k) & 1u) && !is_static) {
-            const int i = tid + k * kBlock;
-            const unsigned long long key = zbuf[i];
-            zbuf[i] = kEmptyKey;
-            const bool vA = key != kEmptyKey;
-            const float Ah = vA ? d.LA[(int)(key & 0xFFFFFFFFull)] : 0.0f;
-            const int q = qi[k];
-            const float sx = (float)(q % W) - g * mBq[k].x;
-            const float sy = (float)(q / W) - g * mBq[k].y;
-            const bool vB = sx >= 0.0f && sx <= (float)(W - 1) && sy >= 0.0f && sy <= (float)(H - 1);
-            const float Bh = vB ? bilinear(d.LB, H, W, sx, sy) : 0.0f;
-            float v;
-            if (vA && vB) v = lerp32(Ah, Bh, alpha);
-            else if (vA) v = Ah;
-            else if (vB) v = Bh;
-            else v = lerp32(LAq[k], LBq[k], alpha);
-            Lj[k] = v;
-            hb[k] = (vA ? 0u : 1u) | (vB ? 0u : 2u);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          Lj[k] = LBq[k];
-          hb[k] = 0u;
-        }
-      }
-
+    // Consumers of a finished sub-frame (substep jj, values Lj, holes hb).
+    auto consume = [&](int jj, const float (&Lj)[PPT], const uint32_t (&hb)[PPT]) {
       if (MODE == MODE_STEP) {
-        emit_substep<PPT>(j, Lj, Lp, R, tl, con, coff, xy, okbits, d.t0, d.span, dy.Dt, d.refr,
-                          d.env_bits, sh, so, ev_count, round);
+        emit_substep<PPT>(jj, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.refr, d.env_bits,
+                          sh, so, ev_count, round);
       } else if (MODE == MODE_INTERP) {
         const long long plane = (long long)H * W;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           if ((okbits >> k) & 1u) {
-            const long long o = (long long)(j - a.j_begin) * plane + qi[k];
+            const long long o = (long long)(jj - a.j_begin) * plane + (pix_y(k) * W + pix_x(k));
             a.L_out[o] = Lj[k];
             if (a.hole) a.hole[o] = (uint8_t)hb[k];
           }
         }
-        __syncthreads();
       }
 #pragma unroll
       for (int k = 0; k < PPT; ++k) Lp[k] = Lj[k];
+    };
+
+    // pending interior substep (values whose loads were issued last iteration)
+    float pAh[PPT], pBh[PPT];
+    uint32_t phb[PPT];
+    float palpha = 0.0f;
+    bool pending = false;
+    int pj = 0;
+
+    auto finish_pending = [&]() {
+      float Lj[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const bool vA = !(phb[k] & 1u), vB = !(phb[k] & 2u);
+        float v;
+        if (is_static) v = LAq[k];
+        else if (vA && vB) v = lerp32(pAh[k], pBh[k], palpha);
+        else if (vA) v = pAh[k];
+        else if (vB) v = pBh[k];
+        else v = lerp32(LAq[k], LBq[k], palpha);
+        Lj[k] = v;
+      }
+      consume(pj, Lj, phb);
+      pending = false;
+    };
+
+    const int j_int_last = min(j_last, K - 1);   // last interior substep to build
+    for (int j = j_first; j <= j_int_last; ++j) {
+      const float f = (float)j / (float)K;
+      const float g = 1.0f - f;
+      const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
+      float cAh[PPT], cBh[PPT];
+      uint32_t chb[PPT];
+      if (!is_static) {
+        // (1) B-gather loads of substep j
+        BTaps bt[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) bt[k] = b_taps(d, pix_x(k), pix_y(k), mBq[k], g, (okbits >> k) & 1u);
+        // (2) splat substep j
+        if (!overflow) {
+          for (int base = 0; base < nlist; base += kBlock) {
+            const int e2 = base + lane * kWavesPerBlock + wave;
+            uint32_t ent = 0u;
+            bool act = false;
+            if (e2 < nlist) {
+              ent = list[e2];
+              const int jlo = (int)((ent >> 8) & 0xFFu), jhi = (int)(ent & 0xFFu);
+              act = (j >= jlo) && (j <= jhi);
+            }
+            unsigned long long mask = __ballot(act);
+            while (mask) {
+              int st[kChunk];
+              int nb = 0;
+#pragma unroll
+              for (int c = 0; c < kChunk; ++c) {
+                st[c] = 0;
+                if (mask) {
+                  const int b = __ffsll((long long)mask) - 1;
+                  mask &= mask - 1ull;
+                  st[c] = (int)((uint32_t)__builtin_amdgcn_readlane((int)ent, b) >> 16);   // sxt<<8 | syt
+                  ++nb;
+                }
+              }
+              splat_chunk<TW>(d, st, nb, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+            }
+          }
+        } else {
+          // Window scan: the candidate list did not fit.
+          for (int w = wave; w < nwin; w += kWavesPerBlock) {
+            const int sxt = wx0 + w % nwx, syt = wy0 + w / nwx;
+            const int st0 = syt * d.ntx_src + sxt;
+            int jlo, jhi;
+            if (substep_range(ldg(d.tb, st0), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
+                              syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0,
+                              Ty1, K, jlo, jhi) &&
+                j >= jlo && j <= jhi) {
+              int st[kChunk] = {};
+              st[0] = (sxt << 8) | syt;
+              splat_chunk<TW>(d, st, 1, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+            }
+          }
+        }
+        __syncthreads();
+        // (3) winners of substep j: issue their L_A loads; B values
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          const int i = tid + k * kBlock;
+          const int zi = (i / TW) * ZS + (i % TW);
+          bool vA = false;
+          cAh[k] = 0.0f;
+          if ((okbits >> k) & 1u) {
+            const unsigned long long key = zbuf[zi];
+            zbuf[zi] = kEmptyKey;
+            vA = key != kEmptyKey;
+            if (vA) cAh[k] = ldg(d.LA, (int)(key & 0xFFFFFFFFull));
+          }
+          cBh[k] = bt[k].v ? b_value(bt[k]) : 0.0f;
+          chb[k] = (vA ? 0u : 1u) | (bt[k].v ? 0u : 2u);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          cAh[k] = 0.0f;
+          cBh[k] = 0.0f;
+          chb[k] = 0u;
+        }
+      }
+      // (4) substep j - 1.  In MODE_STEP its emission holds a barrier that
+      // orders (3) before the next splat; otherwise take one here.
+      const bool had_pending = pending;
+      if (pending) finish_pending();
+      if (!(MODE == MODE_STEP && had_pending)) __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        pAh[k] = cAh[k];
+        pBh[k] = cBh[k];
+        phb[k] = chb[k];
+      }
+      palpha = alpha;
+      pj = j;
+      pending = true;
     }
+    if (pending) finish_pending();
+    if (j_last == K) {
+      float Lj[PPT];
+      uint32_t hb[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        Lj[k] = LBq[k];
+        hb[k] = 0u;
+      }
+      consume(K, Lj, hb);
+    }
+    if (MODE == MODE_INTERP) __syncthreads();
 
     if (MODE == MODE_STEP) {
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if ((okbits >> k) & 1u) {
-          d.Lref[qi[k]] = R[k];
-          if (d.tlast) d.tlast[qi[k]] = tl[k];
+          const int qq = pix_y(k) * W + pix_x(k);
+          stg(d.Lref, qq, R[k]);
+          if (d.tlast) stg(d.tlast, qq, s_tl[tid + k * kBlock]);
         }
       }
     }
@@ -489,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(const TileArgs a) {
 
 hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue, unsigned long long* cursor,
                         hipStream_t s) {
-  const int n = max(n_envs, 1);
+  const int n = max(n_envs, kXcd);
   hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, dyn, n_envs, queue, cursor);
   return hipGetLastError();
 }
@@ -504,10 +660,10 @@ hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_pref
 }
 
 hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,
-                        int32_t* rank_begin, int32_t* env_order, int32_t* n_items,
+                        int32_t* xbegin, int32_t* env_order, int32_t* n_items,
                         int32_t* K_used, hipStream_t s) {
   hipLaunchKernelGGL(k_queue, dim3(1), dim3(EVIS_MAX_ENVS), 0, s, envs, dyn, n_envs, tile_w,
-                     tile_h, rank_begin, env_order, n_items, K_used);
+                     tile_h, xbegin, env_order, n_items, K_used);
   return hipGetLastError();
 }
 

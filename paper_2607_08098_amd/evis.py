@@ -86,6 +86,9 @@ SIGNATURES = {
                                        _VP, _VP, ctypes.c_int32, _VP]),
     "evis_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
     "evis_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
+    "evis_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "evis_profile_read": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int64)]),
     "evis_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
                                      _VP, ctypes.c_int32, ctypes.POINTER(EvisTuning),
                                      ctypes.POINTER(ctypes.c_float), _VP]),
@@ -286,6 +289,23 @@ def evis_autotune(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, 
     ctx.check(ctx.lib.evis_autotune(ctx.handle, arr, len(arr), _ptr(out), out.shape[0], _ptr(n_total),
                                     reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
     return best, ms.value
+
+
+EVIS_KERNEL_STEP = 0
+EVIS_KERNEL_INTERP = 1
+EVIS_KERNEL_EVENTS = 2
+
+
+def evis_profile_enable(ctx: Context, enable: bool = True):
+    ctx.check(ctx.lib.evis_profile_enable(ctx.handle, 1 if enable else 0))
+
+
+def evis_profile_read(ctx: Context, kernel: int):
+    """(summed milliseconds, launches) of the recorded launches of one kernel."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    ctx.check(ctx.lib.evis_profile_read(ctx.handle, kernel, ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,94 @@
+"""Device-resident synthetic workloads for the benchmark and the tests.
+
+Every environment's frames live in packed device buffers (one per field),
+so that the log front end runs as a single launch over all environments and
+each env's tensors are contiguous views.  Scene content comes from
+``scenes``; log intensity comes either from ``log_fn`` (a host function,
+used by tests so both sides see the same numbers) or from the library's own
+``evis_log_luminance`` on the device.
+"""
+from __future__ import annotations
+
+from typing import Callable, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import evis, scenes
+
+
+class Batch:
+    """Packed device frames of n environments plus their per-env views."""
+
+    def __init__(self, shapes: Sequence[Tuple[int, int]], device="cuda"):
+        self.shapes = list(shapes)
+        self.device = device
+        self.offsets = [0]
+        for H, W in self.shapes:
+            self.offsets.append(self.offsets[-1] + H * W)
+        n = self.offsets[-1]
+        f32 = dict(dtype=torch.float32, device=device)
+        self.I_A = torch.empty(n, **f32)
+        self.I_B = torch.empty(n, **f32)
+        self.L_A = torch.empty(n, **f32)
+        self.L_B = torch.empty(n, **f32)
+        self.m_A = torch.empty((n, 2), **f32)
+        self.m_B = torch.empty((n, 2), **f32)
+        self.Z_A = torch.empty(n, **f32)
+        self.Z_B = torch.empty(n, **f32)
+        self.L_ref = torch.empty(n, **f32)
+        self.t_last: Optional[torch.Tensor] = None
+        self.omega: List[float] = []
+
+    @property
+    def n_px(self) -> int:
+        return self.offsets[-1]
+
+    def view(self, buf: torch.Tensor, e: int) -> torch.Tensor:
+        H, W = self.shapes[e]
+        a, b = self.offsets[e], self.offsets[e + 1]
+        return buf[a:b].view(H, W, *buf.shape[1:])
+
+    def env_dicts(self, sensor: dict, t0: int = 0, t1: int = 16667, env_ids=None) -> List[dict]:
+        out = []
+        for e in range(len(self.shapes)):
+            d = dict(L_A=self.view(self.L_A, e), L_B=self.view(self.L_B, e),
+                     m_A=self.view(self.m_A, e), m_B=self.view(self.m_B, e),
+                     Z_A=self.view(self.Z_A, e), Z_B=self.view(self.Z_B, e),
+                     L_ref=self.view(self.L_ref, e), t0=t0, t1=t1,
+                     env_id=e if env_ids is None else env_ids[e])
+            if self.t_last is not None:
+                d["t_last"] = self.view(self.t_last, e)
+            d.update(sensor)
+            out.append(d)
+        return out
+
+
+def mixed_batch(ctx: evis.Context, seed_base: int = 3000, device="cuda",
+                log_fn: Optional[Callable[[np.ndarray], np.ndarray]] = None,
+                specs=None) -> Batch:
+    """The 64-environment mixed-resolution batch (24 x 346x260, 24 x 640x480,
+    16 x 1280x720) of rotating blob scenes, omega U[0.5, 20] rad/s at 60 Hz.
+    L_ref starts at L_A."""
+    specs = specs if specs is not None else scenes.mixed_batch_specs(seed_base)
+    b = Batch([(H, W) for H, W, _ in specs], device)
+    for e, (H, W, seed) in enumerate(specs):
+        sc = scenes.mixed_env(H, W, seed)
+        b.omega.append(float(sc["omega"]))
+        put = lambda buf, arr: b.view(buf, e).copy_(torch.from_numpy(np.ascontiguousarray(arr)))
+        put(b.I_A, sc["I_A"])
+        put(b.I_B, sc["I_B"])
+        put(b.m_A, sc["m_A"])
+        put(b.m_B, sc["m_B"])
+        put(b.Z_A, sc["Z_A"])
+        put(b.Z_B, sc["Z_B"])
+        if log_fn is not None:
+            put(b.L_A, log_fn(sc["I_A"]).astype(np.float32))
+            put(b.L_B, log_fn(sc["I_B"]).astype(np.float32))
+    if log_fn is None:
+        evis.evis_log_luminance(ctx, b.I_A, 1e-3, out=b.L_A)
+        evis.evis_log_luminance(ctx, b.I_B, 1e-3, out=b.L_B)
+    for e in range(len(b.shapes)):
+        H, W = b.shapes[e]
+        evis.evis_state_init(ctx, b.view(b.L_A, e), b.view(b.L_ref, e))
+    return b

@@ -163,8 +163,7 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
 // tile [Sx0,Sx1]x[Sy0,Sy1] with motion bounds b can put a footprint corner
 // into the target tile [Tx0,Tx1]x[Ty0,Ty1].  A corner lies in [Tx0,Tx1]
 // only if q_x = p_x - f m_x is in [Tx0 - 1, Tx1 + 1); over the tile q_x lies
-// in [Sx0 - f max m_x, Sx1 - f min m_x].  One pixel of slack covers
-// rounding; the substep range is widened by one on each side.
+// in [Sx0 - f max m_x, Sx1 - f min m_x].
 __device__ __forceinline__ void lin_le(float a, float bnd, float& flo, float& fhi) {
   if (a > 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));        // a f <= bnd
   else if (a < 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));
@@ -176,21 +175,24 @@ __device__ __forceinline__ void lin_ge(float a, float bnd, float& flo, float& fh
   else if (bnd > 0.0f) flo = 2.0f;
 }
 
-// (the bounds are conservative by a pixel and the substep range is widened
-// by one substep each side, far beyond the error of the fast division)
+// The footprint test is conservative by 1/64 px (far above the rounding of
+// q = p - f m for |q| < 4096 and |m| < 2^20) and the substep bounds by
+// 1/256 of a substep (above the error of the fast division), so no source
+// that can land in the tile at substep j is ever left out.
 __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy0, int Sy1,
                                               int Tx0, int Tx1, int Ty0, int Ty1, int K,
                                               int& jlo, int& jhi) {
   if (!(b.x <= b.y) || !(b.z <= b.w)) return false;   // no finite source
   float flo = 0.0f, fhi = 1.0f;
-  const float slack = 1.0f;
+  const float slack = 1.0f / 64.0f;
   lin_le(b.x, (float)(Sx1 - Tx0 + 1) + slack, flo, fhi);
   lin_ge(b.y, (float)(Sx0 - Tx1 - 1) - slack, flo, fhi);
   lin_le(b.z, (float)(Sy1 - Ty0 + 1) + slack, flo, fhi);
   lin_ge(b.w, (float)(Sy0 - Ty1 - 1) - slack, flo, fhi);
   if (!(flo <= fhi)) return false;
-  const int lo = max(1, (int)floorf(flo * (float)K) - 1);
-  const int hi = min(K - 1, (int)ceilf(fhi * (float)K) + 1);
+  const float Kf = (float)K;
+  const int lo = max(1, (int)ceilf(flo * Kf - (1.0f / 256.0f)));
+  const int hi = min(K - 1, (int)floorf(fhi * Kf + (1.0f / 256.0f)));
   if (lo > hi) return false;
   jlo = lo;
   jhi = hi;

@@ -207,6 +207,36 @@ int evis_autotune(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_even
                   int64_t capacity, int64_t *n_total, int32_t reps, evis_tuning *best,
                   float *best_ms, void *stream);
 
+/* Smooth event-count surrogate and its gradient (a differentiable stand-in
+ * for the crossing count of Eq. 4 that lets a contrast threshold and flow
+ * corrections be fitted by gradient descent).  Per pixel
+ *   S = sum_{j=1..K} sigmoid((|L_j - R_{j-1}| - C) / tau)
+ * with L_j the sub-frames of evis_interpolate (same warp, same blend) and
+ * R_0 = L_ref, R_j = R_{j-1} + p_j n_j C the hard reference level of Eq. 4
+ * with threshold C both ways (integer counts n_j, polarity p_j).  Where the
+ * counts do not change R does not move with L, and dR_j/dC = sum of p n up
+ * to j; the gradient of C includes that term.  The backward pass returns dLoss/dL_A,
+ * dLoss/dL_B, dLoss/dm_A (zero: the splat takes the winner's value, which
+ * does not move with m_A), dLoss/dm_B (through the gather position) and
+ * dLoss/dC per env, for a given dLoss/dS.  float32; gradients of L_A and L_B
+ * are accumulated with atomics, so their last bits depend on ordering. */
+typedef struct {
+  evis_pair pair;       /* t0_us / t1_us are ignored */
+  const float *L_ref;   /* [H*W] */
+  float *S;             /* [H*W] forward output */
+  const float *gS;      /* [H*W] backward input */
+  float *gL_A, *gL_B;   /* [H*W] backward outputs (overwritten) */
+  float *gm_A, *gm_B;   /* [H*W*2] backward outputs (overwritten) */
+} evis_soft_env;
+
+/* K in 1..EVIS_MAX_K (same for all envs), tau > 0, blend_mode EVIS_BLEND_*,
+ * C a DEVICE float array [n_envs] (> 0), gC a DEVICE float array [n_envs]. */
+int evis_soft_count_forward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_envs, int32_t K,
+                            float tau, int32_t blend_mode, const float *C, void *stream);
+int evis_soft_count_backward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_envs, int32_t K,
+                             float tau, int32_t blend_mode, const float *C, float *gC,
+                             void *stream);
+
 /* Kernel timing.  While profiling is enabled, each call records HIP events
  * on its stream around its main kernel (the fused tile kernel of
  * evis_step_batch, the tile kernel of evis_interpolate, the event kernel

@@ -10,11 +10,14 @@ logistic sigma((|L_j - R_{j-1}| - C) / tau):
     S(q) = sum_{j=1..K} sigma((|L_j(q) - R_{j-1}(q)| - C) / tau)
 
 where L_j are the sub-frames of the warp (Eq. 5-7 and the blend) and
-R_{j-1} is the hard reference-level trajectory of Eq. 4 (held constant:
-no gradient flows through it).  The gradient with respect to L_A, L_B, the
-motion fields and C follows by the chain rule through the blend, the
-winner-take-all splat (whose value does not depend on m_A, so d/dm_A = 0
-wherever the winners do not change) and the bilinear gather of B.
+R_{j-1} is the hard reference-level trajectory of Eq. 4 with threshold C
+both ways: R_j = R_{j-1} + p_j n_j C with integer n_j.  Where the n_j do not
+change, dR_j/dC = dR_{j-1}/dC + p_j n_j and R does not move with L (so the
+derivative through R is exact almost everywhere).  The gradient with
+respect to L_A, L_B, the motion fields and C follows by the chain rule
+through the blend, the winner-take-all splat (whose value does not depend on
+m_A, so d/dm_A = 0 wherever the winners do not change), the bilinear gather
+of B and, for C, the reference trajectory.
 
 Discrete decisions (splat winner, B validity, bilinear cell) are inputs
 ``D`` of the float64 evaluation: ``decisions32`` takes them from the float32
@@ -42,20 +45,45 @@ class Decisions:
 
 
 def reference_levels(frames32, L_ref32, C):
-    """Hard float32 reference trajectory R_0..R_K of Eq. 4 (threshold C for
-    both polarities), from the float32 sub-frames (the emission step of
-    the float32 oracle, events discarded)."""
+    """Hard float32 reference trajectory of Eq. 4 (threshold C for both
+    polarities) from the float32 sub-frames, by the emission step of the
+    float32 oracle (events discarded): (R_0..R_K, dR_0/dC..dR_K/dC)."""
     H, W = frames32[0].shape
     R = np.array(L_ref32, F32, copy=True)
     tl = np.full((H, W), o.T_LAST_INIT, np.int64)
     on = np.full((H, W), F32(C))
     traj = [R.copy()]
+    dRdC = [np.zeros((H, W))]
     log = o.EventLog()
     Dt = o.substep_dt(0, 16667, len(frames32) - 1)
+    c = float(F32(C))
     for j in range(1, len(frames32)):
+        before = R.astype(np.float64)
         o.emit_substep(j, frames32[j - 1], frames32[j], R, tl, on, on, 0, 0, Dt, 16667, 0, log, False)
+        moved = R.astype(np.float64) - before          # = p_j fl(n_j C)
+        pn = np.rint(moved / c)                         # p_j n_j (exact: |error| << 1/2)
         traj.append(R.copy())
-    return traj
+        dRdC.append(dRdC[-1] + pn)
+    return traj, dRdC
+
+
+def reference_levels64(frames64, L_ref, C, dRdC=None):
+    """The same trajectory in float64: (R, dR/dC).  Counts come from exact
+    float64 comparisons, or, with dRdC given (the cumulative p n of another
+    evaluation), are held at those: R_j = L_ref + C dRdC_j."""
+    if dRdC is not None:
+        L_ref = np.asarray(L_ref, np.float64)
+        return [L_ref + C * np.asarray(t, np.float64) for t in dRdC], list(dRdC)
+    R = np.array(L_ref, np.float64, copy=True)
+    traj, dRdC = [R.copy()], [np.zeros_like(R)]
+    for j in range(1, len(frames64)):
+        d = frames64[j] - R
+        a = np.abs(d)
+        n = np.where(a >= C, np.floor(a / C), 0.0)
+        R = R + np.sign(d) * n * C
+        traj.append(R.copy())
+        dRdC.append(dRdC[-1] + np.sign(d) * n)
+    return traj, dRdC
 
 
 def decisions32(pair: o.Pair, K: int) -> Decisions:
@@ -147,20 +175,60 @@ def _sigmoid(u):
     return 1.0 / (1.0 + np.exp(-u))
 
 
+def _subframe(LA, LB, mB, j, K, blend_mode, D: Decisions):
+    """Float64 sub-frame j along D, with the pieces its gradient needs.
+    j = K is L_B; 0 < j < K blends A^ = L_A[winner] and
+    B^ = bilinear(L_B, q - (1 - j/K) m_B(q)) with weight alpha = j/K (time
+    blend) or 1; where neither exists, lerp(L_A(q), L_B(q), alpha)."""
+    if j == K:
+        return LB, None
+    H, W = LA.shape
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    f = j / K
+    alpha = f if blend_mode == o.BLEND_TIME else 1.0
+    g = 1.0 - f
+    win = D.winner[j - 1]
+    vA = win >= 0
+    vB = D.vB[j - 1]
+    Ah = np.where(vA, LA.ravel()[np.where(vA, win, 0)].reshape(H, W), 0.0)
+    sx = xx - g * mB[..., 0]
+    sy = yy - g * mB[..., 1]
+    x0, y0 = D.cx[j - 1], D.cy[j - 1]
+    x1 = np.minimum(x0 + 1, W - 1)
+    y1 = np.minimum(y0 + 1, H - 1)
+    wx = np.where(vB, sx - x0, 0.0)
+    wy = np.where(vB, sy - y0, 0.0)
+    a, b = LB[y0, x0], LB[y0, x1]
+    c, d = LB[y1, x0], LB[y1, x1]
+    top = a + wx * (b - a)
+    bot = c + wx * (d - c)
+    Bh = top + wy * (bot - top)
+    both = vA & vB
+    L = np.where(both, Ah + alpha * (Bh - Ah),
+                 np.where(vA, Ah, np.where(vB, Bh, LA + alpha * (LB - LA))))
+    parts = dict(alpha=alpha, g=g, win=win, vA=vA, vB=vB, both=both, x0=x0, y0=y0, x1=x1, y1=y1,
+                 wx=wx, wy=wy, a=a, b=b, c=c, d=d, top=top, bot=bot)
+    return L, parts
+
+
+def subframes64(L_A, L_B, m_B, K, blend_mode, D: Decisions):
+    """Float64 sub-frames L_0 = L_A, L_1..L_K along the decisions D."""
+    LA = np.asarray(L_A, np.float64)
+    LB = np.asarray(L_B, np.float64)
+    mB = np.asarray(m_B, np.float64)
+    return [LA] + [_subframe(LA, LB, mB, j, K, blend_mode, D)[0] for j in range(1, K + 1)]
+
+
 def soft_count(L_A, L_B, m_A, m_B, C, R_traj, K, tau, blend_mode, D: Decisions, want_grad=False,
                gS=None):
     """Float64 S (and, with want_grad, the gradient of sum(gS * S) with
-    respect to L_A, L_B, m_A, m_B and C) along the decisions D.
-
-    Sub-frames: j = K is L_B; 0 < j < K blends A^ = L_A[winner] and
-    B^ = bilinear(L_B, q - (1 - j/K) m_B(q)) with weight alpha = j/K (time
-    blend) or 1; where neither exists, lerp(L_A(q), L_B(q), alpha).
-    """
+    respect to L_A, L_B, m_A, m_B and C) along the decisions D.  R_traj is
+    (R_0..R_K, dR_0/dC..dR_K/dC) of reference_levels / reference_levels64;
+    the sub-frames are those of _subframe."""
     LA = np.asarray(L_A, np.float64)
     LB = np.asarray(L_B, np.float64)
     mB = np.asarray(m_B, np.float64)
     H, W = LA.shape
-    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
     S = np.zeros((H, W))
     if want_grad:
         gS = np.ones((H, W)) if gS is None else np.asarray(gS, np.float64)
@@ -168,33 +236,11 @@ def soft_count(L_A, L_B, m_A, m_B, C, R_traj, K, tau, blend_mode, D: Decisions, 
         gLB = np.zeros(H * W)
         gmB = np.zeros((H, W, 2))
         gC = 0.0
+    R_list, dRdC_list = R_traj
     for j in range(1, K + 1):
-        R = np.asarray(R_traj[j - 1], np.float64)
-        if j == K:
-            L = LB
-        else:
-            f = j / K
-            alpha = f if blend_mode == o.BLEND_TIME else 1.0
-            g = 1.0 - f
-            win = D.winner[j - 1]
-            vA = win >= 0
-            vB = D.vB[j - 1]
-            Ah = np.where(vA, LA.ravel()[np.where(vA, win, 0)].reshape(H, W), 0.0)
-            sx = xx - g * mB[..., 0]
-            sy = yy - g * mB[..., 1]
-            x0, y0 = D.cx[j - 1], D.cy[j - 1]
-            x1 = np.minimum(x0 + 1, W - 1)
-            y1 = np.minimum(y0 + 1, H - 1)
-            wx = np.where(vB, sx - x0, 0.0)
-            wy = np.where(vB, sy - y0, 0.0)
-            a, b = LB[y0, x0], LB[y0, x1]
-            c, d = LB[y1, x0], LB[y1, x1]
-            top = a + wx * (b - a)
-            bot = c + wx * (d - c)
-            Bh = top + wy * (bot - top)
-            both = vA & vB
-            L = np.where(both, Ah + alpha * (Bh - Ah),
-                         np.where(vA, Ah, np.where(vB, Bh, LA + alpha * (LB - LA))))
+        R = np.asarray(R_list[j - 1], np.float64)
+        dRdC = np.asarray(dRdC_list[j - 1], np.float64)
+        L, p = _subframe(LA, LB, mB, j, K, blend_mode, D)
         dlt = L - R
         u = (np.abs(dlt) - C) / tau
         sg = _sigmoid(u)
@@ -203,23 +249,25 @@ def soft_count(L_A, L_B, m_A, m_B, C, R_traj, K, tau, blend_mode, D: Decisions, 
             continue
         dS = sg * (1.0 - sg) / tau
         gL = gS * dS * np.sign(dlt)
-        gC += float(np.sum(gS * dS * -1.0))
+        gC += float(np.sum(gS * dS * (-np.sign(dlt) * dRdC - 1.0)))
         if j == K:
             gLB += gL.ravel()
             continue
+        alpha, vA, vB, both, win = p["alpha"], p["vA"], p["vB"], p["both"], p["win"]
+        wx, wy = p["wx"], p["wy"]
         cA = np.where(both, 1.0 - alpha, np.where(vA, 1.0, 0.0)) * gL
         cB = np.where(both, alpha, np.where(vA, 0.0, np.where(vB, 1.0, 0.0))) * gL
         hole = ~vA & ~vB
         np.add.at(gLA, win[vA], cA[vA])
         gLA += np.where(hole, (1.0 - alpha) * gL, 0.0).ravel()
         gLB += np.where(hole, alpha * gL, 0.0).ravel()
-        for (ty, tx, wgt) in ((y0, x0, (1 - wx) * (1 - wy)), (y0, x1, wx * (1 - wy)),
-                              (y1, x0, (1 - wx) * wy), (y1, x1, wx * wy)):
+        for (ty, tx, wgt) in ((p["y0"], p["x0"], (1 - wx) * (1 - wy)), (p["y0"], p["x1"], wx * (1 - wy)),
+                              (p["y1"], p["x0"], (1 - wx) * wy), (p["y1"], p["x1"], wx * wy)):
             np.add.at(gLB, (ty * W + tx)[vB], (cB * wgt)[vB])
-        dBdwx = (1 - wy) * (b - a) + wy * (d - c)
-        dBdwy = bot - top
-        gmB[..., 0] += np.where(vB, cB * dBdwx * -g, 0.0)
-        gmB[..., 1] += np.where(vB, cB * dBdwy * -g, 0.0)
+        dBdwx = (1 - wy) * (p["b"] - p["a"]) + wy * (p["d"] - p["c"])
+        dBdwy = p["bot"] - p["top"]
+        gmB[..., 0] += np.where(vB, cB * dBdwx * -p["g"], 0.0)
+        gmB[..., 1] += np.where(vB, cB * dBdwy * -p["g"], 0.0)
     if not want_grad:
         return S
     return S, dict(L_A=gLA.reshape(H, W), L_B=gLB.reshape(H, W), m_A=np.zeros((H, W, 2)),

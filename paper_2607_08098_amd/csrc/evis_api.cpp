@@ -43,6 +43,8 @@ struct evis_ctx {
   DevBuf dz;          // float[sum H*W]
   DevBuf tb;          // float4[sum source tiles]
   DevBuf msq;         // one u64 for evis_substep_count
+  DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
+  std::vector<unsigned char> soft_shadow;
   // host staging of the descriptor block (pinned ring)
   void* stage[kStageSlots] = {};
   size_t stage_bytes = 0;
@@ -157,27 +159,34 @@ int ensure_stage(evis_ctx* ctx, size_t bytes) {
   return EVIS_OK;
 }
 
-// Copy the descriptor block to device memory unless it already holds it.
-int upload_meta(evis_ctx* ctx, const std::vector<unsigned char>& blob, hipStream_t s) {
+// Copy a block of host data to a device buffer unless it already holds it
+// (pinned staging ring; the copy is ordered on stream s).
+int upload_to(evis_ctx* ctx, DevBuf& dst, std::vector<unsigned char>& shadow,
+              const std::vector<unsigned char>& blob, hipStream_t s, bool* grew_out = nullptr) {
   bool grew = false;
-  int rc = ensure(ctx, ctx->meta, blob.size(), &grew);
+  int rc = ensure(ctx, dst, blob.size(), &grew);
   if (rc) return rc;
   if (grew) {
     drop_graphs(ctx);
-    ctx->shadow.clear();
+    shadow.clear();
   }
-  if (ctx->shadow == blob) return EVIS_OK;
+  if (grew_out) *grew_out = grew;
+  if (shadow == blob) return EVIS_OK;
   rc = ensure_stage(ctx, blob.size());
   if (rc) return rc;
   const int slot = ctx->stage_next;
   ctx->stage_next = (slot + 1) % kStageSlots;
   EVIS_HIP(hipEventSynchronize(ctx->stage_ev[slot]), "hipEventSynchronize");
   std::memcpy(ctx->stage[slot], blob.data(), blob.size());
-  EVIS_HIP(hipMemcpyAsync(ctx->meta.p, ctx->stage[slot], blob.size(), hipMemcpyHostToDevice, s),
+  EVIS_HIP(hipMemcpyAsync(dst.p, ctx->stage[slot], blob.size(), hipMemcpyHostToDevice, s),
            "hipMemcpyAsync(descriptors)");
   EVIS_HIP(hipEventRecord(ctx->stage_ev[slot], s), "hipEventRecord");
-  ctx->shadow = blob;
+  shadow = blob;
   return EVIS_OK;
+}
+
+int upload_meta(evis_ctx* ctx, const std::vector<unsigned char>& blob, hipStream_t s) {
+  return upload_to(ctx, ctx->meta, ctx->shadow, blob, s);
 }
 
 int check_pair(evis_ctx* ctx, const evis_pair& p, const char* who) {
@@ -393,7 +402,7 @@ void evis_destroy(evis_ctx* ctx) {
     hipEventDestroy(r.e1);
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
-  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->dz, &ctx->tb, &ctx->msq};
+  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->dz, &ctx->tb, &ctx->msq, &ctx->soft};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {
@@ -655,6 +664,103 @@ int evis_profile_read(evis_ctx* ctx, int32_t kernel, double* total_ms, int64_t* 
   if (total_ms) *total_ms = sum;
   if (launches) *launches = cnt;
   return EVIS_OK;
+}
+
+static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, int32_t K, float tau,
+                     int32_t blend_mode, const float* C, float* gC, bool backward,
+                     hipStream_t s) {
+  const char* who = backward ? "evis_soft_count_backward" : "evis_soft_count_forward";
+  if (!envs) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": null envs");
+  if (n_envs < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": n_envs must be >= 1");
+  if (n_envs > EVIS_MAX_ENVS) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": n_envs > 512");
+  if (K < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": K must be >= 1");
+  if (K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": K > 128");
+  if (!(tau > 0.0f) || !std::isfinite(tau)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": tau");
+  if (blend_mode != EVIS_BLEND_TIME && blend_mode != EVIS_BLEND_B_PRIMARY)
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown blend_mode");
+  if (!C || !aligned(C, 4)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": C");
+  if (backward && (!gC || !aligned(gC, 4))) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": gC");
+  Plan pl;
+  std::vector<SoftPtrs> ptrs(n_envs);
+  evis_sensor sen{};
+  sen.C_on = sen.C_off = 1.0f;
+  sen.K = K;
+  sen.K_max = K;
+  sen.blend_mode = blend_mode;
+  for (int e = 0; e < n_envs; ++e) {
+    const evis_soft_env& v = envs[e];
+    int rc = check_pair(ctx, v.pair, who);
+    if (rc) return rc;
+    const void* need[] = {v.L_ref, backward ? v.gS : v.S};
+    for (const void* q : need)
+      if (!q || !aligned(q, 4)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": L_ref / S / gS");
+    if (backward && (!v.gL_A || !v.gL_B || !v.gm_A || !v.gm_B || !aligned(v.gL_A, 4) ||
+                     !aligned(v.gL_B, 4) || !aligned(v.gm_A, 8) || !aligned(v.gm_B, 8)))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": gradient outputs");
+    evis_pair p = v.pair;
+    p.t0_us = 0;
+    p.t1_us = 1;
+    evis_state st{};
+    pl.desc.push_back(make_desc(p, sen, st, 0));
+    SoftPtrs& P = ptrs[e];
+    P.Lref = v.L_ref;
+    P.S = v.S;
+    P.gS = v.gS;
+    P.gLA = v.gL_A;
+    P.gLB = v.gL_B;
+    P.gmA = reinterpret_cast<float2*>(v.gm_A);
+    P.gmB = reinterpret_cast<float2*>(v.gm_B);
+  }
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  int rc = plan_envs(ctx, pl, kSoftTW, kSoftTH);
+  if (rc) return rc;
+  rc = upload_meta(ctx, meta_blob(pl), s);
+  if (rc) return rc;
+  std::vector<int32_t> item_prefix(n_envs + 1, 0);
+  for (int e = 0; e < n_envs; ++e)
+    item_prefix[e + 1] = item_prefix[e] + ((pl.desc[e].W + kSoftTW - 1) / kSoftTW) *
+                                              ((pl.desc[e].H + kSoftTH - 1) / kSoftTH);
+  const size_t off_ptrs = ((n_envs + 1) * sizeof(int32_t) + 15) & ~(size_t)15;
+  std::vector<unsigned char> blob(off_ptrs + n_envs * sizeof(SoftPtrs));
+  std::memcpy(blob.data(), item_prefix.data(), (n_envs + 1) * sizeof(int32_t));
+  std::memcpy(blob.data() + off_ptrs, ptrs.data(), n_envs * sizeof(SoftPtrs));
+  rc = upload_to(ctx, ctx->soft, ctx->soft_shadow, blob, s);
+  if (rc) return rc;
+  const EnvDesc* d_desc = static_cast<const EnvDesc*>(ctx->meta.p);
+  const int32_t* d_prefix = reinterpret_cast<const int32_t*>(
+      static_cast<const unsigned char*>(ctx->meta.p) + n_envs * sizeof(EnvDesc));
+  EnvDyn* d_dyn = static_cast<EnvDyn*>(ctx->dyn.p);
+  Sched sc = sched_ptrs(ctx, n_envs);
+  const SoftPtrs* d_ptrs = reinterpret_cast<const SoftPtrs*>(static_cast<unsigned char*>(ctx->soft.p) + off_ptrs);
+  EVIS_HIP(launch_reset(d_dyn, n_envs, sc.queue, nullptr, s), "k_reset");
+  EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n_envs, pl.src_total, s), "k_prep");
+  if (backward) EVIS_HIP(launch_soft_zero(d_ptrs, d_desc, n_envs, gC, s), "k_soft_zero");
+  SoftArgs a{};
+  a.envs = d_desc;
+  a.dyn = d_dyn;
+  a.item_prefix = static_cast<const int32_t*>(ctx->soft.p);
+  a.ptrs = d_ptrs;
+  a.n_envs = n_envs;
+  a.K = K;
+  a.inv_tau = 1.0f / tau;
+  a.list_cap = std::min(std::max(ctx->tuning.list_cap, 1), kListCapMax);
+  a.C = C;
+  a.gC = gC;
+  EVIS_HIP(launch_soft(backward, a, item_prefix[n_envs], s), "k_soft");
+  return EVIS_OK;
+}
+
+int evis_soft_count_forward(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, int32_t K,
+                            float tau, int32_t blend_mode, const float* C, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  return soft_call(ctx, envs, n_envs, K, tau, blend_mode, C, nullptr, false, (hipStream_t)stream);
+}
+
+int evis_soft_count_backward(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, int32_t K,
+                             float tau, int32_t blend_mode, const float* C, float* gC,
+                             void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  return soft_call(ctx, envs, n_envs, K, tau, blend_mode, C, gC, true, (hipStream_t)stream);
 }
 
 int evis_get_tuning(const evis_ctx* ctx, evis_tuning* out) {

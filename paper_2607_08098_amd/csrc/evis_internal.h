@@ -47,7 +47,36 @@ struct TileArgs {
   float* gC;                   // [n_envs]
 };
 
+// Smooth event-count surrogate (evis_soft_count_*): per-env pointers.
+struct SoftPtrs {
+  const float* Lref;   // [H*W] reference level at the start of the pair
+  float* S;            // [H*W] forward out
+  const float* gS;     // [H*W] backward in
+  float* gLA;          // [H*W] backward out (accumulated; zeroed first)
+  float* gLB;
+  float2* gmA;         // [H*W] backward out (written)
+  float2* gmB;
+};
+
+struct SoftArgs {
+  const EnvDesc* envs;
+  const EnvDyn* dyn;
+  const int32_t* item_prefix;   // [n_envs + 1] target tiles of each env
+  const SoftPtrs* ptrs;         // [n_envs]
+  int32_t n_envs;
+  int32_t K;
+  float inv_tau;
+  int32_t list_cap;
+  const float* C;               // [n_envs]
+  float* gC;                    // [n_envs] (backward, accumulated; zeroed first)
+};
+
+constexpr int kSoftTW = 32, kSoftTH = 16;
+
 // Kernel launchers (defined in evis_tile.hip / evis_events.hip).
+hipError_t launch_soft(bool backward, const SoftArgs& a, int n_items, hipStream_t s);
+hipError_t launch_soft_zero(const SoftPtrs* ptrs, const EnvDesc* envs, int n_envs, float* gC,
+                            hipStream_t s);
 hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
                         unsigned long long* cursor, hipStream_t s);   // queue: kXcd counters
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,

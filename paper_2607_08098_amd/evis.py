@@ -55,6 +55,12 @@ class EvisEnv(ctypes.Structure):
                 ("env_id", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class EvisSoftEnv(ctypes.Structure):
+    _fields_ = [("pair", EvisPair), ("L_ref", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("gS", ctypes.c_void_p), ("gL_A", ctypes.c_void_p), ("gL_B", ctypes.c_void_p),
+                ("gm_A", ctypes.c_void_p), ("gm_B", ctypes.c_void_p)]
+
+
 class EvisTuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("grid_mult", ctypes.c_int32), ("list_cap", ctypes.c_int32),
@@ -86,6 +92,11 @@ SIGNATURES = {
                                        _VP, _VP, ctypes.c_int32, _VP]),
     "evis_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
     "evis_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
+    "evis_soft_count_forward": (ctypes.c_int, [_VP, ctypes.POINTER(EvisSoftEnv), ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _VP, _VP]),
+    "evis_soft_count_backward": (ctypes.c_int, [_VP, ctypes.POINTER(EvisSoftEnv), ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _VP, _VP,
+                                                _VP]),
     "evis_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "evis_profile_read": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -289,6 +300,32 @@ def evis_autotune(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, 
     ctx.check(ctx.lib.evis_autotune(ctx.handle, arr, len(arr), _ptr(out), out.shape[0], _ptr(n_total),
                                     reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
     return best, ms.value
+
+
+def soft_env_array(L_A, L_B, m_A, m_B, Z_A, Z_B, L_ref, S=None, gS=None, gL_A=None, gL_B=None,
+                   gm_A=None, gm_B=None):
+    """evis_soft_env[n] from batched tensors [n, H, W] (m: [n, H, W, 2])."""
+    n = L_A.shape[0]
+    arr = (EvisSoftEnv * n)()
+    for e in range(n):
+        pair = make_pair(dict(L_A=L_A[e], L_B=L_B[e], m_A=m_A[e], m_B=m_B[e], Z_A=Z_A[e], Z_B=Z_B[e],
+                              t0=0, t1=1))
+        pick = lambda t: None if t is None else _ptr(t[e])
+        arr[e] = EvisSoftEnv(pair, pick(L_ref), pick(S), pick(gS), pick(gL_A), pick(gL_B), pick(gm_A),
+                             pick(gm_B))
+    return arr
+
+
+def evis_soft_count_forward(ctx: Context, envs, K: int, tau: float, blend_mode: int,
+                            C: torch.Tensor, stream=None):
+    ctx.check(ctx.lib.evis_soft_count_forward(ctx.handle, envs, len(envs), K, tau, blend_mode, _ptr(C),
+                                              _stream(stream)))
+
+
+def evis_soft_count_backward(ctx: Context, envs, K: int, tau: float, blend_mode: int,
+                             C: torch.Tensor, gC: torch.Tensor, stream=None):
+    ctx.check(ctx.lib.evis_soft_count_backward(ctx.handle, envs, len(envs), K, tau, blend_mode, _ptr(C),
+                                               _ptr(gC), _stream(stream)))
 
 
 EVIS_KERNEL_STEP = 0

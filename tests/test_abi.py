@@ -41,6 +41,7 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(evis.EvisState) == 16
     assert ctypes.sizeof(evis.EvisEnv) == ctypes.sizeof(evis.EvisPair) + 40 + 16 + 8
     assert ctypes.sizeof(evis.EvisTuning) == 24
+    assert ctypes.sizeof(evis.EvisSoftEnv) == ctypes.sizeof(evis.EvisPair) + 7 * 8
 
 
 def test_null_context_is_rejected_without_touching_a_gpu():

@@ -64,11 +64,80 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB three times (the reference kernel for HBM counters)")
+    ap.add_argument("--traffic-from", type=str, default=None, metavar="DIR",
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs in DIR/{fetch,write,"
+                         "cal_fetch,cal_write} into the traffic record (no GPU)")
+    ap.add_argument("--tile-label", type=str, default=None, help="WxH the counter runs used")
     return ap.parse_args()
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration():
+    """Three copies of 1 GiB: per dispatch the algorithmic traffic is
+    exactly 1 GiB read and 1 GiB written, which calibrates the counters."""
+    import torch
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(dict(copy_calibration_bytes=COPY_BYTES, dispatches=3)))
+
+
+def _counter_means(run_dir, counter):
+    """{kernel name: mean counter value per dispatch} from a rocprofv3 csv run."""
+    import csv
+    import glob
+    tot, disp = {}, {}
+    for f in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                k = r["Kernel_Name"]
+                tot[k] = tot.get(k, 0.0) + float(r["Counter_Value"])
+                disp.setdefault(k, set()).add(r["Dispatch_Id"])
+    return {k: tot[k] / len(disp[k]) for k in tot}
+
+
+def traffic_from(d, tile_label):
+    """HBM traffic of the fused tile kernel per launch: FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads
+    for a copy of exactly 1 GiB."""
+    def pick(means, key):
+        ks = [k for k in means if key(k)]
+        assert ks, f"no dispatch matched in {sorted(means)[:8]}"
+        ks.sort(key=lambda k: -means[k])
+        return ks[0], means[ks[0]]
+    is_tile = lambda k: "k_tile<" in k
+    is_copy = lambda k: "copy" in k.lower() or "elementwise" in k
+    kf, fetch = pick(_counter_means(os.path.join(d, "fetch"), "FETCH_SIZE"), is_tile)
+    kw, write = pick(_counter_means(os.path.join(d, "write"), "WRITE_SIZE"), is_tile)
+    _, cf = pick(_counter_means(os.path.join(d, "cal_fetch"), "FETCH_SIZE"), is_copy)
+    _, cw = pick(_counter_means(os.path.join(d, "cal_write"), "WRITE_SIZE"), is_copy)
+    f_fetch = COPY_BYTES / (cf * 1024.0)
+    f_write = COPY_BYTES / (cw * 1024.0)
+    rb, wb = fetch * 1024.0 * f_fetch, write * 1024.0 * f_write
+    tw, th = (int(v) for v in tile_label.lower().split("x"))
+    rec = dict(kernel=kf, kernel_hash=kernel_hash(), tuning=[tw, th],
+               fetch_kib_per_dispatch=round(fetch, 1), write_kib_per_dispatch=round(write, 1),
+               copy_fetch_kib=round(cf, 1), copy_write_kib=round(cw, 1),
+               fetch_factor=round(f_fetch, 4), write_factor=round(f_write, 4),
+               read_bytes=round(rb), write_bytes=round(wb), bytes_per_launch=round(rb + wb))
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
 
 
 def cpu_baseline(batch_specs, sample_envs):
@@ -94,6 +163,9 @@ def cpu_baseline(batch_specs, sample_envs):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(args.traffic_from, args.tile_label or "32x16")
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -106,6 +178,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     ctx = evis.Context(0)
     t = time.time()
     specs = scenes.mixed_batch_specs(3000)

@@ -229,13 +229,19 @@ typedef struct {
   float *gm_A, *gm_B;   /* [H*W*2] backward outputs (overwritten) */
 } evis_soft_env;
 
+/* flags of evis_soft_count_backward: with EVIS_SOFT_HOLD_REF the reference
+ * trajectory is treated as a constant (stop-gradient), so dS/dC is only the
+ * direct -sigma'/tau term; without it dC also flows through R. */
+enum { EVIS_SOFT_HOLD_REF = 1 };
+
 /* K in 1..EVIS_MAX_K (same for all envs), tau > 0, blend_mode EVIS_BLEND_*,
- * C a DEVICE float array [n_envs] (> 0), gC a DEVICE float array [n_envs]. */
+ * C a DEVICE float array [n_envs] (> 0), gC a DEVICE float array [n_envs],
+ * flags 0 or EVIS_SOFT_HOLD_REF. */
 int evis_soft_count_forward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_envs, int32_t K,
                             float tau, int32_t blend_mode, const float *C, void *stream);
 int evis_soft_count_backward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_envs, int32_t K,
                              float tau, int32_t blend_mode, const float *C, float *gC,
-                             void *stream);
+                             int32_t flags, void *stream);
 
 /* Kernel timing.  While profiling is enabled, each call records HIP events
  * on its stream around its main kernel (the fused tile kernel of

@@ -668,7 +668,7 @@ int evis_profile_read(evis_ctx* ctx, int32_t kernel, double* total_ms, int64_t* 
 
 static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, int32_t K, float tau,
                      int32_t blend_mode, const float* C, float* gC, bool backward,
-                     hipStream_t s) {
+                     int32_t flags, hipStream_t s) {
   const char* who = backward ? "evis_soft_count_backward" : "evis_soft_count_forward";
   if (!envs) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": null envs");
   if (n_envs < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": n_envs must be >= 1");
@@ -680,6 +680,7 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
     return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown blend_mode");
   if (!C || !aligned(C, 4)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": C");
   if (backward && (!gC || !aligned(gC, 4))) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": gC");
+  if (flags & ~EVIS_SOFT_HOLD_REF) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown flags");
   Plan pl;
   std::vector<SoftPtrs> ptrs(n_envs);
   evis_sensor sen{};
@@ -746,6 +747,7 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
   a.list_cap = std::min(std::max(ctx->tuning.list_cap, 1), kListCapMax);
   a.C = C;
   a.gC = gC;
+  a.hold_ref = (flags & EVIS_SOFT_HOLD_REF) ? 1 : 0;
   EVIS_HIP(launch_soft(backward, a, item_prefix[n_envs], s), "k_soft");
   return EVIS_OK;
 }
@@ -753,14 +755,14 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
 int evis_soft_count_forward(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, int32_t K,
                             float tau, int32_t blend_mode, const float* C, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;
-  return soft_call(ctx, envs, n_envs, K, tau, blend_mode, C, nullptr, false, (hipStream_t)stream);
+  return soft_call(ctx, envs, n_envs, K, tau, blend_mode, C, nullptr, false, 0, (hipStream_t)stream);
 }
 
 int evis_soft_count_backward(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, int32_t K,
                              float tau, int32_t blend_mode, const float* C, float* gC,
-                             void* stream) {
+                             int32_t flags, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;
-  return soft_call(ctx, envs, n_envs, K, tau, blend_mode, C, gC, true, (hipStream_t)stream);
+  return soft_call(ctx, envs, n_envs, K, tau, blend_mode, C, gC, true, flags, (hipStream_t)stream);
 }
 
 int evis_get_tuning(const evis_ctx* ctx, evis_tuning* out) {

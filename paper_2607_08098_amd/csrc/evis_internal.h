@@ -69,6 +69,7 @@ struct SoftArgs {
   int32_t list_cap;
   const float* C;               // [n_envs]
   float* gC;                    // [n_envs] (backward, accumulated; zeroed first)
+  int32_t hold_ref;             // 1: the reference trajectory carries no gradient
 };
 
 constexpr int kSoftTW = 32, kSoftTH = 16;

@@ -690,7 +690,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
 // the gather position (d s / d m_B = -(1 - f)); the splat value does not
 // depend on m_A, so its gradient is zero.  R does not move with L where the
 // counts stay put, but it does move with C: dR/dC accumulates p n per
-// substep, and dS/dC = -sigma' (1 + sign(L_j - R) dR/dC) / tau.
+// substep, and dS/dC = -sigma' (1 + sign(L_j - R) dR/dC) / tau (or only
+// -sigma' / tau with hold_ref, R a constant).
 template <int TW, int TH, bool BWD>
 __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
   constexpr int NPX = TW * TH;
@@ -794,7 +795,7 @@ __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
         const float dS = sg * (1.0f - sg) * a.inv_tau;
         const float sgn = (dl > 0.0f) ? 1.0f : ((dl < 0.0f) ? -1.0f : 0.0f);
         const float gL = gSq[k] * dS * sgn;
-        gCacc -= gSq[k] * dS * (1.0f + sgn * dRdC[k]);
+        gCacc -= gSq[k] * dS * (a.hold_ref ? 1.0f : (1.0f + sgn * dRdC[k]));
         if (j == K) {
           regB[k] += gL;
         } else if (vA || vB) {

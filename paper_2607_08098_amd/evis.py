@@ -96,7 +96,7 @@ SIGNATURES = {
                                                ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _VP, _VP]),
     "evis_soft_count_backward": (ctypes.c_int, [_VP, ctypes.POINTER(EvisSoftEnv), ctypes.c_int32,
                                                 ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _VP, _VP,
-                                                _VP]),
+                                                ctypes.c_int32, _VP]),
     "evis_profile_enable": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "evis_profile_read": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int64)]),
@@ -323,10 +323,12 @@ def evis_soft_count_forward(ctx: Context, envs, K: int, tau: float, blend_mode: 
 
 
 def evis_soft_count_backward(ctx: Context, envs, K: int, tau: float, blend_mode: int,
-                             C: torch.Tensor, gC: torch.Tensor, stream=None):
+                             C: torch.Tensor, gC: torch.Tensor, flags: int = 0, stream=None):
     ctx.check(ctx.lib.evis_soft_count_backward(ctx.handle, envs, len(envs), K, tau, blend_mode, _ptr(C),
-                                               _ptr(gC), _stream(stream)))
+                                               _ptr(gC), flags, _stream(stream)))
 
+
+EVIS_SOFT_HOLD_REF = 1
 
 EVIS_KERNEL_STEP = 0
 EVIS_KERNEL_INTERP = 1

@@ -42,7 +42,7 @@ BYTES_PER_EVENT = 8
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # plain VALU lane-ops: 39.3 T/s
 HBM_PEAK_GBS = 8000.0
 
-KERNEL_SOURCES = ["evis_common.h", "evis_sink.h", "evis_tile.hip"]
+KERNEL_SOURCES = ["evis_common.h", "evis_internal.h", "evis_sink.h", "evis_warp.h", "evis_tile.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tile_step_mixed64.json")
 
 

@@ -83,11 +83,11 @@ struct EventArgs {
 template <int PPT>
 __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   __shared__ uint2 evbuf[kEventBuf];
-  __shared__ int s_wtot[2][kWavesPerBlock];
+  __shared__ int s_evn, s_req[2];
   __shared__ unsigned long long s_gbase;
   __shared__ float s_con[kBlock * PPT], s_coff[kBlock * PPT];
   __shared__ int s_tl[kBlock * PPT];
-  const SinkShared sh{evbuf, s_wtot, &s_gbase, kEventBuf};
+  const SinkShared sh{evbuf, &s_evn, s_req, &s_gbase, kEventBuf};
   const SinkOut so{a.out, a.capacity, a.cursor};
   const int tid = threadIdx.x;
   const long long plane = (long long)a.H * a.W;
@@ -109,7 +109,9 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   }
   const PixAux aux{a.th_on ? s_con : nullptr, a.th_off ? s_coff : nullptr, s_tl, a.C_on, a.C_off,
                    0, 0, a.W, 0, base};
-  int ev_count = 0, round = 0;
+  SinkRound sr;
+  sink_init(sh);
+  __syncthreads();
   for (int j = 1; j <= a.K; ++j) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
@@ -119,7 +121,7 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
                                      : 0.0f;
     }
     emit_substep<PPT>(j, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.refr, a.env_bits, sh, so,
-                      ev_count, round);
+                      sr);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) Lp[k] = Lj[k];
   }
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
       if (a.tlast) a.tlast[q] = s_tl[tid + k * kBlock];
     }
   }
-  sink_flush(sh, so, ev_count);
+  sink_flush(sh, so);
 }
 
 static int grid_for(long long n, int per_block) {

@@ -1,6 +1,16 @@
 // Event emission (Eq. 4 with Eq. 8 thresholds and the refractory period)
 // and wave-ballot / prefix-sum compaction into a workgroup-local LDS buffer
 // that is appended to the global event stream with one atomic per flush.
+//
+// Emission takes no barrier: each wave reserves its slots in the LDS buffer
+// with a compare-and-swap on the buffer's count (or, if they do not fit,
+// writes straight to the stream after one global atomic) and raises a flush
+// request once the buffer is three quarters full.  Requests are read after
+// the next workgroup barrier, where every wave sees the same value: round r
+// writes request slot r & 1 and round r + 2 cannot start before the barrier
+// that follows round r + 1, by which time every wave has read slot r & 1.
+// So that this holds whatever the caller does, an emission that finds the
+// previous round unchecked takes the barrier and the check itself.
 #pragma once
 
 #include "evis_common.h"
@@ -9,7 +19,8 @@ namespace evis {
 
 struct SinkShared {
   uint2* buf;                   // LDS [cap] staged events
-  int (*wtot)[kWavesPerBlock];  // LDS [2][4] per-wave event totals (double-buffered)
+  int* cnt;                     // LDS: events staged
+  int* req;                     // LDS [2]: flush requests by round parity
   unsigned long long* gbase;    // LDS: global slot of the current flush
   int cap;
 };
@@ -19,6 +30,54 @@ struct SinkOut {
   long long capacity;
   unsigned long long* cursor;
 };
+
+// Workgroup-uniform sink state kept in registers.
+struct SinkRound {
+  int round = 0;          // emissions so far
+  bool unchecked = false; // the last emission's request has not been read yet
+};
+
+// Clear the LDS state; a barrier must follow before the first emission.
+__device__ __forceinline__ void sink_init(const SinkShared& sh) {
+  if (threadIdx.x == 0) {
+    *sh.cnt = 0;
+    sh.req[0] = sh.req[1] = 0;
+  }
+}
+
+// Append the staged events to the stream.  Every thread calls it, right
+// after a barrier that follows the last emission.
+__device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& so) {
+  const int tid = threadIdx.x;
+  const int n = *sh.cnt;   // stable: no wave emits until the closing barrier
+  if (n == 0) return;      // workgroup-uniform
+  __syncthreads();         // every wave has read cnt
+  if (tid == 0) *sh.gbase = atomicAdd(so.cursor, (unsigned long long)n);
+  __syncthreads();
+  const unsigned long long gb = *sh.gbase;
+  for (int i = tid; i < n; i += kBlock) {
+    if ((long long)(gb + i) < so.capacity) {
+      const uint2 r = sh.buf[i];
+      so.out[gb + i] = evis_event{r.x, (int32_t)r.y};
+    }
+  }
+  __syncthreads();         // copies done before the buffer is reused
+  if (tid == 0) {
+    *sh.cnt = 0;
+    sh.req[0] = sh.req[1] = 0;
+  }
+  __syncthreads();
+}
+
+// Read the last emission's flush request and flush if it is set.  Call it
+// right after a workgroup barrier (every thread).
+__device__ __forceinline__ void sink_check(const SinkShared& sh, const SinkOut& so,
+                                           SinkRound& sr) {
+  if (!sr.unchecked) return;
+  sr.unchecked = false;
+  const int want = __builtin_amdgcn_readfirstlane(sh.req[(sr.round - 1) & 1]);
+  if (want) sink_drain(sh, so);
+}
 
 // Per-pixel state that only a crossing pixel reads: thresholds, last event
 // time, coordinates.  Kept in LDS (index tid + k * kBlock) so that it costs
@@ -54,15 +113,19 @@ struct PixAux {
   }
 };
 
-// One substep of the event model for the PPT pixels of this thread, followed
-// by the workgroup's compaction round.  Every thread of the workgroup must
-// call it (it holds a barrier).  ev_count and round are workgroup-uniform.
+// One substep of the event model for the PPT pixels of this thread and the
+// wave's compaction.  Every thread of the workgroup must call it (it takes a
+// barrier only when the previous round was not checked).
 template <int PPT>
 __device__ __forceinline__ void emit_substep(
     int j, const float (&Lj)[PPT], const float (&Lp)[PPT], float (&R)[PPT], const PixAux& aux,
     uint32_t okbits, long long t0, int span, float Dt, int refr, uint32_t env_bits,
-    const SinkShared& sh, const SinkOut& so, int& ev_count, int& round) {
+    const SinkShared& sh, const SinkOut& so, SinkRound& sr) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  if (sr.unchecked) {
+    __syncthreads();
+    sink_check(sh, so, sr);
+  }
   int nn[PPT];
   uint32_t posbits = 0;
   int m = 0;
@@ -93,42 +156,36 @@ __device__ __forceinline__ void emit_substep(
       }
     }
   }
-  // Workgroup offsets: wave prefix sums, then the per-wave totals in LDS.
+  // Wave offsets by prefix sum; the wave's slots by one reservation.
   const int incl = wave_inclusive_scan(m);
   const int excl = incl - m;
-  const int rb = round & 1;
-  if (lane == kWave - 1) sh.wtot[rb][wave] = incl;
-  __syncthreads();
-  int off_w = 0, grand = 0;
-#pragma unroll
-  for (int w = 0; w < kWavesPerBlock; ++w) {
-    const int v = sh.wtot[rb][w];
-    off_w += (w < wave) ? v : 0;
-    grand += v;
-  }
-  ++round;
-  if (grand > 0) {   // workgroup-uniform
-    bool to_global = false;
-    unsigned long long gbase_w = 0;   // this wave's first slot in the stream
-    int lbase_w = 0;                  // ... or in the LDS buffer
-    if (ev_count + grand <= sh.cap) {
-      lbase_w = ev_count + off_w;
-      ev_count += grand;
-    } else {
-      // Flush the staged events and write this round straight to the stream.
-      if (tid == 0) *sh.gbase = atomicAdd(so.cursor, (unsigned long long)(ev_count + grand));
-      __syncthreads();
-      const unsigned long long gb = *sh.gbase;
-      for (int i = tid; i < ev_count; i += kBlock) {
-        if ((long long)(gb + i) < so.capacity) {
-          const uint2 r = sh.buf[i];
-          so.out[gb + i] = evis_event{r.x, (int32_t)r.y};
+  const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+  const int slot_req = sr.round & 1;
+  ++sr.round;
+  sr.unchecked = true;
+  if (wtot > 0) {   // wave-uniform
+    int lb = -1;
+    if (lane == kWave - 1) {
+      int cur = __atomic_load_n(sh.cnt, __ATOMIC_RELAXED);
+      while (cur + wtot <= sh.cap) {
+        const int prev = atomicCAS(sh.cnt, cur, cur + wtot);
+        if (prev == cur) {
+          lb = cur;
+          break;
         }
+        cur = prev;
       }
-      to_global = true;
-      gbase_w = gb + (unsigned long long)(ev_count + off_w);
-      ev_count = 0;
     }
+    lb = __builtin_amdgcn_readlane(lb, kWave - 1);
+    const bool to_global = lb < 0;
+    unsigned long long gbase_w = 0;
+    if (to_global) {
+      unsigned long long g = 0;
+      if (lane == kWave - 1) g = atomicAdd(so.cursor, (unsigned long long)wtot);
+      gbase_w = __shfl(g, kWave - 1, kWave);
+    }
+    if (lane == kWave - 1 && (to_global || lb + wtot > sh.cap - sh.cap / 4)) sh.req[slot_req] = 1;
+    const int lbase_w = to_global ? 0 : lb;
     auto put = [&](int slot, uint32_t word, int t) {
       if (to_global) {
         const unsigned long long idx = gbase_w + (unsigned long long)slot;
@@ -137,7 +194,6 @@ __device__ __forceinline__ void emit_substep(
         sh.buf[lbase_w + slot] = make_uint2(word, (uint32_t)t);
       }
     };
-    const int wtot = __shfl(incl, kWave - 1, kWave);
     if (refr == 0) {
       // Expansion: lane l writes events l, l + 64, ... of the wave.  Event e
       // belongs to the lane whose exclusive prefix is the largest <= e; its
@@ -218,20 +274,9 @@ __device__ __forceinline__ void emit_substep(
 }
 
 // Write out whatever is still staged.  Every thread must call it.
-__device__ __forceinline__ void sink_flush(const SinkShared& sh, const SinkOut& so, int& ev_count) {
+__device__ __forceinline__ void sink_flush(const SinkShared& sh, const SinkOut& so) {
   __syncthreads();
-  if (ev_count == 0) return;   // workgroup-uniform
-  const int tid = threadIdx.x;
-  if (tid == 0) *sh.gbase = atomicAdd(so.cursor, (unsigned long long)ev_count);
-  __syncthreads();
-  const unsigned long long gb = *sh.gbase;
-  for (int i = tid; i < ev_count; i += kBlock) {
-    if ((long long)(gb + i) < so.capacity) {
-      const uint2 r = sh.buf[i];
-      so.out[gb + i] = evis_event{r.x, (int32_t)r.y};
-    }
-  }
-  ev_count = 0;
+  sink_drain(sh, so);
 }
 
 }  // namespace evis

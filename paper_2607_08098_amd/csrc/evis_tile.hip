@@ -21,6 +21,7 @@
 // can touch the tile is kept in an LDS list.
 #include "evis_internal.h"
 #include "evis_sink.h"
+#include "evis_warp.h"
 
 namespace evis {
 
@@ -155,253 +156,17 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
   }
 }
 
-// ---------------------------------------------------------------------------
-// candidate source tiles
-// ---------------------------------------------------------------------------
-
-// Conservative interval of substeps during which some source of the 8x8
-// tile [Sx0,Sx1]x[Sy0,Sy1] with motion bounds b can put a footprint corner
-// into the target tile [Tx0,Tx1]x[Ty0,Ty1].  A corner lies in [Tx0,Tx1]
-// only if q_x = p_x - f m_x is in [Tx0 - 1, Tx1 + 1); over the tile q_x lies
-// in [Sx0 - f max m_x, Sx1 - f min m_x].
-__device__ __forceinline__ void lin_le(float a, float bnd, float& flo, float& fhi) {
-  if (a > 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));        // a f <= bnd
-  else if (a < 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));
-  else if (bnd < 0.0f) flo = 2.0f;
-}
-__device__ __forceinline__ void lin_ge(float a, float bnd, float& flo, float& fhi) {
-  if (a > 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));        // a f >= bnd
-  else if (a < 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));
-  else if (bnd > 0.0f) flo = 2.0f;
-}
-
-// The footprint test is conservative by 1/64 px (far above the rounding of
-// q = p - f m for |q| < 4096 and |m| < 2^20) and the substep bounds by
-// 1/256 of a substep (above the error of the fast division), so no source
-// that can land in the tile at substep j is ever left out.
-__device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy0, int Sy1,
-                                              int Tx0, int Tx1, int Ty0, int Ty1, int K,
-                                              int& jlo, int& jhi) {
-  if (!(b.x <= b.y) || !(b.z <= b.w)) return false;   // no finite source
-  float flo = 0.0f, fhi = 1.0f;
-  const float slack = 1.0f / 64.0f;
-  lin_le(b.x, (float)(Sx1 - Tx0 + 1) + slack, flo, fhi);
-  lin_ge(b.y, (float)(Sx0 - Tx1 - 1) - slack, flo, fhi);
-  lin_le(b.z, (float)(Sy1 - Ty0 + 1) + slack, flo, fhi);
-  lin_ge(b.w, (float)(Sy0 - Ty1 - 1) - slack, flo, fhi);
-  if (!(flo <= fhi)) return false;
-  const float Kf = (float)K;
-  const int lo = max(1, (int)ceilf(flo * Kf - (1.0f / 256.0f)));
-  const int hi = min(K - 1, (int)floorf(fhi * Kf + (1.0f / 256.0f)));
-  if (lo > hi) return false;
-  jlo = lo;
-  jhi = hi;
-  return true;
-}
-
-// The LDS z-buffer of a TW x TH target tile has rows of ZS(TW) = TW + 8
-// keys: consecutive rows then start 64 bytes apart in the 32 banks, so the
-// 8 rows touched by one source tile's footprint spread over all banks.
-template <int TW>
-__device__ __forceinline__ constexpr int zrow() { return TW + 8; }
-
-// Splat up to kChunk source tiles (one source per lane and tile) at fraction
-// f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].  The loads of
-// all tiles of the chunk are issued before any of them is used.
-constexpr int kChunk = 4;
-
-template <int TW>
-__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kChunk], int nb,
-                                            float f, int Tx0, int Tx1, int Ty0, int Ty1,
-                                            unsigned long long* zbuf) {
-  const int lane = threadIdx.x & (kWave - 1);
-  float2 m[kChunk];
-  float za[kChunk], dz[kChunk];
-  int sxs[kChunk], sys[kChunk];
-  bool ok[kChunk];
-#pragma unroll
-  for (int c = 0; c < kChunk; ++c) {
-    ok[c] = false;
-    sxs[c] = 0;
-    sys[c] = 0;
-    if (c < nb) {
-      const int sxt = st[c] >> 8, syt = st[c] & 0xFF;   // wave-uniform
-      sxs[c] = sxt * kSrcTile + (lane & 7);
-      sys[c] = syt * kSrcTile + (lane >> 3);
-      ok[c] = (sxs[c] < d.W) && (sys[c] < d.H);
-    }
-    if (ok[c]) {
-      const int p = sys[c] * d.W + sxs[c];
-      m[c] = ldg(d.mA, p);
-      za[c] = ldg(d.ZA, p);
-      dz[c] = ldg(d.dZ, p);
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < kChunk; ++c) {
-    if (!ok[c]) continue;
-    const float qx = (float)sxs[c] - f * m[c].x;
-    const float qy = (float)sys[c] - f * m[c].y;
-    const float zt = za[c] + f * dz[c];
-    if (!(zt > 0.0f)) continue;
-    if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
-          qy < (float)(Ty1 + 1)))
-      continue;
-    const float fx0 = floorf(qx), fy0 = floorf(qy);
-    const int x0 = (int)fx0, y0 = (int)fy0;
-    const bool bx = (qx - fx0) > 0.0f, by = (qy - fy0) > 0.0f;
-    const unsigned p = (unsigned)(sys[c] * d.W + sxs[c]);
-    const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | p;
-    const int lx = x0 - Tx0, ly = y0 - Ty0;
-    const bool in_x0 = x0 >= Tx0, in_x1 = bx && (x0 + 1 <= Tx1);
-    const bool in_y0 = y0 >= Ty0, in_y1 = by && (y0 + 1 <= Ty1);
-    constexpr int ZS = zrow<TW>();
-    unsigned long long* zr = zbuf + ly * ZS + lx;
-    if (in_x0 && in_y0) atomicMin(zr, key);
-    if (in_x1 && in_y0) atomicMin(zr + 1, key);
-    if (in_x0 && in_y1) atomicMin(zr + ZS, key);
-    if (in_x1 && in_y1) atomicMin(zr + ZS + 1, key);
-  }
-}
-
-// B gather at fraction g = 1 - f for one target pixel (x, y): the sample
-// position s = (x, y) - g m_B, its validity and the four taps of its cell.
-struct BTaps {
-  float a, b, c, d, wx, wy;
-  bool v;
-};
-
-__device__ __forceinline__ BTaps b_taps(const EnvDesc& d, int x, int y, float2 mB, float g,
-                                        bool pixel_ok) {
-  BTaps t;
-  const float sx = (float)x - g * mB.x;
-  const float sy = (float)y - g * mB.y;
-  t.v = pixel_ok && sx >= 0.0f && sx <= (float)(d.W - 1) && sy >= 0.0f && sy <= (float)(d.H - 1);
-  const float sxc = t.v ? sx : 0.0f, syc = t.v ? sy : 0.0f;
-  const float fx0 = floorf(sxc), fy0 = floorf(syc);
-  t.wx = sxc - fx0;
-  t.wy = syc - fy0;
-  const int x0 = (int)fx0, y0 = (int)fy0;
-  const int x1 = min(x0 + 1, d.W - 1), y1 = min(y0 + 1, d.H - 1);
-  t.a = t.b = t.c = t.d = 0.0f;
-  if (t.v) {
-    t.a = ldg(d.LB, y0 * d.W + x0);
-    t.b = ldg(d.LB, y0 * d.W + x1);
-    t.c = ldg(d.LB, y1 * d.W + x0);
-    t.d = ldg(d.LB, y1 * d.W + x1);
-  }
-  return t;
-}
-
-__device__ __forceinline__ float b_value(const BTaps& t) {
-  return lerp32(lerp32(t.a, t.b, t.wx), lerp32(t.c, t.d, t.wx), t.wy);
-}
-
-// Window of 8x8 source tiles that can reach a target tile: source tile
-// columns [wx0, wx0 + nwx), nwin tiles in all.
-struct Window {
-  int wx0, wy0, nwx, nwin;
-};
-
-// Candidate source tiles of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
-// during which each can reach it, appended to the LDS list (at most cap
-// entries: x-tile << 24 | y-tile << 16 | j_lo << 8 | j_hi).  *count must be
-// zero on entry; returns the number of candidates (uniform; more than cap
-// means the list overflowed).  Holds a barrier.
-__device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& dy, int K,
-                                                int Tx0, int Tx1, int Ty0, int Ty1,
-                                                uint32_t* list, int* count, int cap, Window& w) {
-  const int tid = threadIdx.x;
-  const int W = d.W, H = d.H;
-  const double M = __longlong_as_double((long long)dy.msq_bits);
-  const int Rw = (M > 1.0e12) ? (1 << 20) : ((int)ceil(sqrt(M)) + 3);
-  w.wx0 = max(0, Tx0 - Rw) / kSrcTile;
-  w.wy0 = max(0, Ty0 - Rw) / kSrcTile;
-  const int wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, W - 1) / kSrcTile);
-  const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcTile);
-  w.nwx = wx1 - w.wx0 + 1;
-  w.nwin = w.nwx * (wy1 - w.wy0 + 1);
-  for (int i = tid; i < w.nwin; i += kBlock) {
-    const int sxt = w.wx0 + i % w.nwx, syt = w.wy0 + i / w.nwx;
-    const int st = syt * d.ntx_src + sxt;
-    int jlo, jhi;
-    if (substep_range(ldg(d.tb, st), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
-                      syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1, K,
-                      jlo, jhi)) {
-      const int slot = atomicAdd(count, 1);
-      if (slot < cap)
-        list[slot] = ((uint32_t)sxt << 24) | ((uint32_t)syt << 16) | ((uint32_t)jlo << 8) | (uint32_t)jhi;
-    }
-  }
-  __syncthreads();
-  return __builtin_amdgcn_readfirstlane(*count);
-}
-
-// Splat every source that can reach the target tile at substep j (fraction
-// f): the active entries of the candidate list, or, if the list overflowed,
-// the active tiles of the whole window; each wave takes every fourth entry
-// and splats its active tiles in chunks.
-template <int TW>
-__device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_t* list, int nlist,
-                                                 bool overflow, const Window& w, int K, int j,
-                                                 float f, int Tx0, int Tx1, int Ty0, int Ty1,
-                                                 unsigned long long* zbuf) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int W = d.W, H = d.H;
-  if (!overflow) {
-    for (int base = 0; base < nlist; base += kBlock) {
-      const int e2 = base + lane * kWavesPerBlock + wave;
-      uint32_t ent = 0u;
-      bool act = false;
-      if (e2 < nlist) {
-        ent = list[e2];
-        const int jlo = (int)((ent >> 8) & 0xFFu), jhi = (int)(ent & 0xFFu);
-        act = (j >= jlo) && (j <= jhi);
-      }
-      unsigned long long mask = __ballot(act);
-      while (mask) {
-        int st[kChunk];
-        int nb = 0;
-#pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-          st[c] = 0;
-          if (mask) {
-            const int b = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            st[c] = (int)((uint32_t)__builtin_amdgcn_readlane((int)ent, b) >> 16);   // sxt<<8 | syt
-            ++nb;
-          }
-        }
-        splat_chunk<TW>(d, st, nb, f, Tx0, Tx1, Ty0, Ty1, zbuf);
-      }
-    }
-  } else {
-    // Window scan: the candidate list did not fit.
-    for (int i = wave; i < w.nwin; i += kWavesPerBlock) {
-      const int sxt = w.wx0 + i % w.nwx, syt = w.wy0 + i / w.nwx;
-      const int st0 = syt * d.ntx_src + sxt;
-      int jlo, jhi;
-      if (substep_range(ldg(d.tb, st0), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
-                        syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1, K,
-                        jlo, jhi) &&
-          j >= jlo && j <= jhi) {
-        int st[kChunk] = {};
-        st[0] = (sxt << 8) | syt;
-        splat_chunk<TW>(d, st, 1, f, Tx0, Tx1, Ty0, Ty1, zbuf);
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // the persistent tile kernel
 // ---------------------------------------------------------------------------
 
 // Per substep j of an item: (1) issue the B-gather loads of j, (2) splat j
-// into the LDS z-buffer, (3) read the winners of j and issue the loads of
-// their L_A, (4) blend and emit substep j - 1, whose loads were issued one
-// substep earlier.  The z-buffer is cleared by its readers in (3); the
-// barrier of (4) orders that before the next splat.
+// into LDS z-buffer j & 1, barrier, (3) read the winners of j and issue the
+// loads of their L_A, (4) blend and emit substep j - 1, whose loads were
+// issued one substep earlier.  The readers of (3) clear the z-buffer; the
+// next splat into the same buffer (j + 2) comes after the barrier of j + 1,
+// so one barrier per substep orders everything (emission takes none).
 template <int TW, int TH, int MODE>
 __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int NPX = TW * TH;
@@ -409,10 +174,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   static_assert(PPT * kBlock == NPX, "tile must be a multiple of the workgroup");
   constexpr int EVB = (MODE == MODE_STEP) ? kEventBuf : 1;
   constexpr int ZS = zrow<TW>();
-  __shared__ unsigned long long zbuf[ZS * TH];
+  __shared__ unsigned long long zbuf[2 * ZS * TH];
   __shared__ uint32_t list[kListCapMax];
   __shared__ uint2 evbuf[EVB];
-  __shared__ int s_wtot[2][kWavesPerBlock];
+  __shared__ int s_evn, s_req[2];
   __shared__ unsigned long long s_gbase;
   __shared__ int s_item, s_rank, s_q, s_lcnt;
   constexpr int AUXN = (MODE == MODE_STEP) ? NPX : 1;
@@ -420,16 +185,18 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   __shared__ int s_tl[AUXN];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int i = tid; i < ZS * TH; i += kBlock) zbuf[i] = kEmptyKey;
-  const SinkShared sh{evbuf, s_wtot, &s_gbase, EVB};
+  for (int i = tid; i < 2 * ZS * TH; i += kBlock) zbuf[i] = kEmptyKey;
+  const SinkShared sh{evbuf, &s_evn, s_req, &s_gbase, EVB};
   const SinkOut so{a.out, a.capacity, a.cursor};
-  int ev_count = 0, round = 0;
+  SinkRound sr;
+  sink_init(sh);
   const int home = (int)(blockIdx.x % kXcd);
   int qsel = 0;   // 0..kXcd-1: queues tried so far (own queue first, then stealing)
   int rcur = 0;   // rank of the last item taken from the current queue
 
   for (;;) {
     __syncthreads();
+    if (MODE == MODE_STEP) sink_check(sh, so, sr);
     if (tid == 0) {
       int item = -1, r = 0, q = -1;
       while (qsel < kXcd) {
@@ -554,7 +321,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
     auto consume = [&](int jj, const float (&Lj)[PPT], const uint32_t (&hb)[PPT]) {
       if (MODE == MODE_STEP) {
         emit_substep<PPT>(jj, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.refr, d.env_bits,
-                          sh, so, ev_count, round);
+                          sh, so, sr);
       } else if (MODE == MODE_INTERP) {
         const long long plane = (long long)H * W;
 #pragma unroll
@@ -601,14 +368,16 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
       float cAh[PPT], cBh[PPT];
       uint32_t chb[PPT];
+      unsigned long long* zb = zbuf + (j & 1) * (ZS * TH);
       if (!is_static) {
         // (1) B-gather loads of substep j
         BTaps bt[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) bt[k] = b_taps(d, pix_x(k), pix_y(k), mBq[k], g, (okbits >> k) & 1u);
         // (2) splat substep j
-        splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+        splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, zb);
         __syncthreads();
+        if (MODE == MODE_STEP) sink_check(sh, so, sr);
         // (3) winners of substep j: issue their L_A loads; B values
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -617,8 +386,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
           bool vA = false;
           cAh[k] = 0.0f;
           if ((okbits >> k) & 1u) {
-            const unsigned long long key = zbuf[zi];
-            zbuf[zi] = kEmptyKey;
+            const unsigned long long key = zb[zi];
+            zb[zi] = kEmptyKey;
             vA = key != kEmptyKey;
             if (vA) cAh[k] = ldg(d.LA, (int)(key & 0xFFFFFFFFull));
           }
@@ -626,6 +395,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
           chb[k] = (vA ? 0u : 1u) | (bt[k].v ? 0u : 2u);
         }
       } else {
+        __syncthreads();
+        if (MODE == MODE_STEP) sink_check(sh, so, sr);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           cAh[k] = 0.0f;
@@ -633,11 +404,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
           chb[k] = 0u;
         }
       }
-      // (4) substep j - 1.  In MODE_STEP its emission holds a barrier that
-      // orders (3) before the next splat; otherwise take one here.
-      const bool had_pending = pending;
+      // (4) substep j - 1
       if (pending) finish_pending();
-      if (!(MODE == MODE_STEP && had_pending)) __syncthreads();
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         pAh[k] = cAh[k];
@@ -672,204 +440,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       }
     }
   }
-  if (MODE == MODE_STEP) sink_flush(sh, so, ev_count);
+  if (MODE == MODE_STEP) sink_flush(sh, so);
 }
 
-// ---------------------------------------------------------------------------
-// smooth event-count surrogate and its backward
-// ---------------------------------------------------------------------------
-
-// One workgroup per target tile.  For j = 1..K the sub-frame L_j is built as
-// in the fused kernel (splat, gather, blend), then
-//   S += sigma((|L_j - R| - C) / tau)
-// with R the hard reference level of Eq. 4 (threshold C both ways), which is
-// then moved by p n C with an integer count n.  The backward pass rebuilds
-// the same sub-frames and sends dLoss/dL_j = gS sigma' sign(L_j - R) / tau
-// through the blend: to the winner's L_A (atomically: the winner may belong
-// to another tile), to the four B taps (atomically) and to m_B(q) through
-// the gather position (d s / d m_B = -(1 - f)); the splat value does not
-// depend on m_A, so its gradient is zero.  R does not move with L where the
-// counts stay put, but it does move with C: dR/dC accumulates p n per
-// substep, and dS/dC = -sigma' (1 + sign(L_j - R) dR/dC) / tau (or only
-// -sigma' / tau with hold_ref, R a constant).
-template <int TW, int TH, bool BWD>
-__global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
-  constexpr int NPX = TW * TH;
-  constexpr int PPT = NPX / kBlock;
-  constexpr int ZS = zrow<TW>();
-  __shared__ unsigned long long zbuf[ZS * TH];
-  __shared__ uint32_t list[kListCapMax];
-  __shared__ int s_lcnt;
-  __shared__ float s_red[kWavesPerBlock];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int i = tid; i < ZS * TH; i += kBlock) zbuf[i] = kEmptyKey;
-  if (tid == 0) s_lcnt = 0;
-  const int item = (int)blockIdx.x;
-  int lo = 0, hi = a.n_envs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.item_prefix[mid] <= item) lo = mid; else hi = mid - 1;
-  }
-  const int env = __builtin_amdgcn_readfirstlane(lo);
-  const EnvDesc d = a.envs[env];
-  const EnvDyn dy = a.dyn[env];
-  const SoftPtrs P = a.ptrs[env];
-  const float C = a.C[env];
-  const int K = a.K;
-  const int H = d.H, W = d.W;
-  const int ntx = (W + TW - 1) / TW;
-  const int tile = item - a.item_prefix[env];
-  const int Tx0 = (tile % ntx) * TW, Ty0 = (tile / ntx) * TH;
-  const int Tx1 = min(Tx0 + TW, W) - 1, Ty1 = min(Ty0 + TH, H) - 1;
-  __syncthreads();
-
-  float LAq[PPT], LBq[PPT], R[PPT], acc[PPT], gSq[PPT], regA[PPT], regB[PPT], dRdC[PPT];
-  float2 mBq[PPT], regm[PPT];
-  uint32_t okbits = 0;
-  auto pix_x = [&](int k) { return Tx0 + (tid + k * kBlock) % TW; };
-  auto pix_y = [&](int k) { return Ty0 + (tid + k * kBlock) / TW; };
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int x = pix_x(k), y = pix_y(k);
-    const bool ok = (x <= Tx1) && (y <= Ty1);
-    const int q = ok ? (y * W + x) : 0;
-    okbits |= (ok ? 1u : 0u) << k;
-    LAq[k] = ok ? ldg(d.LA, q) : 0.0f;
-    LBq[k] = ok ? ldg(d.LB, q) : 0.0f;
-    mBq[k] = ok ? ldg(d.mB, q) : make_float2(0.0f, 0.0f);
-    R[k] = ok ? ldg(P.Lref, q) : 0.0f;
-    gSq[k] = (BWD && ok) ? ldg(P.gS, q) : 0.0f;
-    acc[k] = 0.0f;
-    regA[k] = regB[k] = dRdC[k] = 0.0f;
-    regm[k] = make_float2(0.0f, 0.0f);
-  }
-  Window win{};
-  int nlist = 0;
-  bool overflow = false;
-  if (K > 1) {
-    nlist = build_candidates(d, dy, K, Tx0, Tx1, Ty0, Ty1, list, &s_lcnt, a.list_cap, win);
-    overflow = nlist > a.list_cap;
-  }
-  float gCacc = 0.0f;
-  for (int j = 1; j <= K; ++j) {
-    const float f = (float)j / (float)K;
-    const float g = 1.0f - f;
-    const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
-    if (j < K) {
-      splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, zbuf);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      if (!((okbits >> k) & 1u)) continue;
-      const int x = pix_x(k), y = pix_y(k);
-      float L;
-      bool vA = false, vB = false;
-      int widx = 0;
-      float Ah = 0.0f;
-      BTaps bt;
-      if (j < K) {
-        const int i = tid + k * kBlock;
-        const int zi = (i / TW) * ZS + (i % TW);
-        const unsigned long long key = zbuf[zi];
-        zbuf[zi] = kEmptyKey;
-        vA = key != kEmptyKey;
-        widx = (int)(key & 0xFFFFFFFFull);
-        if (vA) Ah = ldg(d.LA, widx);
-        bt = b_taps(d, x, y, mBq[k], g, true);
-        vB = bt.v;
-        const float Bh = vB ? b_value(bt) : 0.0f;
-        if (vA && vB) L = lerp32(Ah, Bh, alpha);
-        else if (vA) L = Ah;
-        else if (vB) L = Bh;
-        else L = lerp32(LAq[k], LBq[k], alpha);
-      } else {
-        L = LBq[k];
-      }
-      const float dl = L - R[k];
-      const float u = (fabsf(dl) - C) * a.inv_tau;
-      const float sg = 1.0f / (1.0f + expf(-u));
-      if (!BWD) {
-        acc[k] += sg;
-      } else {
-        const float dS = sg * (1.0f - sg) * a.inv_tau;
-        const float sgn = (dl > 0.0f) ? 1.0f : ((dl < 0.0f) ? -1.0f : 0.0f);
-        const float gL = gSq[k] * dS * sgn;
-        gCacc -= gSq[k] * dS * (a.hold_ref ? 1.0f : (1.0f + sgn * dRdC[k]));
-        if (j == K) {
-          regB[k] += gL;
-        } else if (vA || vB) {
-          const float gAh = vA ? (vB ? (1.0f - alpha) * gL : gL) : 0.0f;
-          const float gBh = vB ? (vA ? alpha * gL : gL) : 0.0f;
-          if (vA && gAh != 0.0f) unsafeAtomicAdd(&P.gLA[widx], gAh);
-          if (vB && gBh != 0.0f) {
-            const float fx0 = floorf((float)x - g * mBq[k].x), fy0 = floorf((float)y - g * mBq[k].y);
-            const int x0 = (int)fx0, y0 = (int)fy0;
-            const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
-            const float wx = bt.wx, wy = bt.wy;
-            unsafeAtomicAdd(&P.gLB[y0 * W + x0], gBh * ((1.0f - wx) * (1.0f - wy)));
-            unsafeAtomicAdd(&P.gLB[y0 * W + x1], gBh * (wx * (1.0f - wy)));
-            unsafeAtomicAdd(&P.gLB[y1 * W + x0], gBh * ((1.0f - wx) * wy));
-            unsafeAtomicAdd(&P.gLB[y1 * W + x1], gBh * (wx * wy));
-            const float top = lerp32(bt.a, bt.b, wx), bot = lerp32(bt.c, bt.d, wx);
-            const float dBdwx = (1.0f - wy) * (bt.b - bt.a) + wy * (bt.d - bt.c);
-            const float dBdwy = bot - top;
-            regm[k].x -= gBh * dBdwx * g;
-            regm[k].y -= gBh * dBdwy * g;
-          }
-        } else {
-          regA[k] += (1.0f - alpha) * gL;
-          regB[k] += alpha * gL;
-        }
-      }
-      // hard reference update (Eq. 4, threshold C both ways)
-      const float aa = fabsf(dl);
-      if (aa >= C && C > 0.0f) {
-        const float n = (float)crossing_count(aa, C);
-        const float nc = n * C;
-        R[k] = (dl > 0.0f) ? (R[k] + nc) : (R[k] - nc);
-        if (BWD) dRdC[k] += (dl > 0.0f) ? n : -n;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    if (!((okbits >> k) & 1u)) continue;
-    const int q = pix_y(k) * W + pix_x(k);
-    if (!BWD) {
-      stg(P.S, q, acc[k]);
-    } else {
-      if (regA[k] != 0.0f) unsafeAtomicAdd(&P.gLA[q], regA[k]);
-      if (regB[k] != 0.0f) unsafeAtomicAdd(&P.gLB[q], regB[k]);
-      stg(P.gmB, q, regm[k]);
-      stg(P.gmA, q, make_float2(0.0f, 0.0f));
-    }
-  }
-  if (BWD) {
-    const float w = wave_sum(gCacc);
-    if (lane == 0) s_red[wave] = w;
-    __syncthreads();
-    if (tid == 0) {
-      float t = 0.0f;
-      for (int i = 0; i < kWavesPerBlock; ++i) t += s_red[i];
-      unsafeAtomicAdd(&a.gC[env], t);
-    }
-  }
-}
-
-// Zero the accumulated outputs of the backward pass (one workgroup per env).
-__global__ __launch_bounds__(kBlock) void k_soft_zero(const SoftPtrs* ptrs, const EnvDesc* envs,
-                                                      float* gC) {
-  const int e = blockIdx.x;
-  const SoftPtrs P = ptrs[e];
-  const int n = envs[e].H * envs[e].W;
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    stg(P.gLA, i, 0.0f);
-    stg(P.gLB, i, 0.0f);
-  }
-  if (threadIdx.x == 0) gC[e] = 0.0f;
-}
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -879,21 +452,6 @@ hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue, unsigned l
                         hipStream_t s) {
   const int n = max(n_envs, kXcd);
   hipLaunchKernelGGL(k_reset, dim3((n + 255) / 256), dim3(256), 0, s, dyn, n_envs, queue, cursor);
-  return hipGetLastError();
-}
-
-hipError_t launch_soft(bool backward, const SoftArgs& a, int n_items, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  if (backward)
-    hipLaunchKernelGGL((k_soft<kSoftTW, kSoftTH, true>), dim3(n_items), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_soft<kSoftTW, kSoftTH, false>), dim3(n_items), dim3(kBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_soft_zero(const SoftPtrs* ptrs, const EnvDesc* envs, int n_envs, float* gC,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_soft_zero, dim3(n_envs), dim3(kBlock), 0, s, ptrs, envs, gC);
   return hipGetLastError();
 }
 

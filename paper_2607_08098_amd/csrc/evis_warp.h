@@ -1,0 +1,250 @@
+// Warp building blocks shared by the fused tile kernel and the surrogate
+// kernels (gfx950): the candidate source tiles of a target tile, the
+// depth-tested splat of those sources into an LDS z-buffer (Eq. 5 q_A,
+// bilinear footprint, Eq. 6, Eq. 7) and the bilinear gather of B at
+// s = q - (1 - f) m_B(q).
+#pragma once
+
+#include "evis_internal.h"
+
+namespace evis {
+
+// ---------------------------------------------------------------------------
+// candidate source tiles
+// ---------------------------------------------------------------------------
+
+// Conservative interval of substeps during which some source of the 8x8
+// tile [Sx0,Sx1]x[Sy0,Sy1] with motion bounds b can put a footprint corner
+// into the target tile [Tx0,Tx1]x[Ty0,Ty1].  A corner lies in [Tx0,Tx1]
+// only if q_x = p_x - f m_x is in [Tx0 - 1, Tx1 + 1); over the tile q_x lies
+// in [Sx0 - f max m_x, Sx1 - f min m_x].
+__device__ __forceinline__ void lin_le(float a, float bnd, float& flo, float& fhi) {
+  if (a > 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));        // a f <= bnd
+  else if (a < 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));
+  else if (bnd < 0.0f) flo = 2.0f;
+}
+__device__ __forceinline__ void lin_ge(float a, float bnd, float& flo, float& fhi) {
+  if (a > 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));        // a f >= bnd
+  else if (a < 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));
+  else if (bnd > 0.0f) flo = 2.0f;
+}
+
+// The footprint test is conservative by 1/64 px (far above the rounding of
+// q = p - f m for |q| < 4096 and |m| < 2^20) and the substep bounds by
+// 1/256 of a substep (above the error of the fast division), so no source
+// that can land in the tile at substep j is ever left out.
+__device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy0, int Sy1,
+                                              int Tx0, int Tx1, int Ty0, int Ty1, int K,
+                                              int& jlo, int& jhi) {
+  if (!(b.x <= b.y) || !(b.z <= b.w)) return false;   // no finite source
+  float flo = 0.0f, fhi = 1.0f;
+  const float slack = 1.0f / 64.0f;
+  lin_le(b.x, (float)(Sx1 - Tx0 + 1) + slack, flo, fhi);
+  lin_ge(b.y, (float)(Sx0 - Tx1 - 1) - slack, flo, fhi);
+  lin_le(b.z, (float)(Sy1 - Ty0 + 1) + slack, flo, fhi);
+  lin_ge(b.w, (float)(Sy0 - Ty1 - 1) - slack, flo, fhi);
+  if (!(flo <= fhi)) return false;
+  const float Kf = (float)K;
+  const int lo = max(1, (int)ceilf(flo * Kf - (1.0f / 256.0f)));
+  const int hi = min(K - 1, (int)floorf(fhi * Kf + (1.0f / 256.0f)));
+  if (lo > hi) return false;
+  jlo = lo;
+  jhi = hi;
+  return true;
+}
+
+// The LDS z-buffer of a TW x TH target tile has rows of ZS(TW) = TW + 8
+// keys: consecutive rows then start 64 bytes apart in the 32 banks, so the
+// 8 rows touched by one source tile's footprint spread over all banks.
+template <int TW>
+__device__ __forceinline__ constexpr int zrow() { return TW + 8; }
+
+// Splat up to kChunk source tiles (one source per lane and tile) at fraction
+// f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].  The loads of
+// all tiles of the chunk are issued before any of them is used.
+constexpr int kChunk = 4;
+
+template <int TW>
+__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kChunk], int nb,
+                                            float f, int Tx0, int Tx1, int Ty0, int Ty1,
+                                            unsigned long long* zbuf) {
+  const int lane = threadIdx.x & (kWave - 1);
+  float2 m[kChunk];
+  float za[kChunk], dz[kChunk];
+  int sxs[kChunk], sys[kChunk];
+  bool ok[kChunk];
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c) {
+    ok[c] = false;
+    sxs[c] = 0;
+    sys[c] = 0;
+    if (c < nb) {
+      const int sxt = st[c] >> 8, syt = st[c] & 0xFF;   // wave-uniform
+      sxs[c] = sxt * kSrcTile + (lane & 7);
+      sys[c] = syt * kSrcTile + (lane >> 3);
+      ok[c] = (sxs[c] < d.W) && (sys[c] < d.H);
+    }
+    if (ok[c]) {
+      const int p = sys[c] * d.W + sxs[c];
+      m[c] = ldg(d.mA, p);
+      za[c] = ldg(d.ZA, p);
+      dz[c] = ldg(d.dZ, p);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c) {
+    if (!ok[c]) continue;
+    const float qx = (float)sxs[c] - f * m[c].x;
+    const float qy = (float)sys[c] - f * m[c].y;
+    const float zt = za[c] + f * dz[c];
+    if (!(zt > 0.0f)) continue;
+    if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
+          qy < (float)(Ty1 + 1)))
+      continue;
+    const float fx0 = floorf(qx), fy0 = floorf(qy);
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const bool bx = (qx - fx0) > 0.0f, by = (qy - fy0) > 0.0f;
+    const unsigned p = (unsigned)(sys[c] * d.W + sxs[c]);
+    const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | p;
+    const int lx = x0 - Tx0, ly = y0 - Ty0;
+    const bool in_x0 = x0 >= Tx0, in_x1 = bx && (x0 + 1 <= Tx1);
+    const bool in_y0 = y0 >= Ty0, in_y1 = by && (y0 + 1 <= Ty1);
+    constexpr int ZS = zrow<TW>();
+    unsigned long long* zr = zbuf + ly * ZS + lx;
+    if (in_x0 && in_y0) atomicMin(zr, key);
+    if (in_x1 && in_y0) atomicMin(zr + 1, key);
+    if (in_x0 && in_y1) atomicMin(zr + ZS, key);
+    if (in_x1 && in_y1) atomicMin(zr + ZS + 1, key);
+  }
+}
+
+// B gather at fraction g = 1 - f for one target pixel (x, y): the sample
+// position s = (x, y) - g m_B, its validity and the four taps of its cell.
+struct BTaps {
+  float a, b, c, d, wx, wy;
+  bool v;
+};
+
+__device__ __forceinline__ BTaps b_taps(const EnvDesc& d, int x, int y, float2 mB, float g,
+                                        bool pixel_ok) {
+  BTaps t;
+  const float sx = (float)x - g * mB.x;
+  const float sy = (float)y - g * mB.y;
+  t.v = pixel_ok && sx >= 0.0f && sx <= (float)(d.W - 1) && sy >= 0.0f && sy <= (float)(d.H - 1);
+  const float sxc = t.v ? sx : 0.0f, syc = t.v ? sy : 0.0f;
+  const float fx0 = floorf(sxc), fy0 = floorf(syc);
+  t.wx = sxc - fx0;
+  t.wy = syc - fy0;
+  const int x0 = (int)fx0, y0 = (int)fy0;
+  const int x1 = min(x0 + 1, d.W - 1), y1 = min(y0 + 1, d.H - 1);
+  t.a = t.b = t.c = t.d = 0.0f;
+  if (t.v) {
+    t.a = ldg(d.LB, y0 * d.W + x0);
+    t.b = ldg(d.LB, y0 * d.W + x1);
+    t.c = ldg(d.LB, y1 * d.W + x0);
+    t.d = ldg(d.LB, y1 * d.W + x1);
+  }
+  return t;
+}
+
+__device__ __forceinline__ float b_value(const BTaps& t) {
+  return lerp32(lerp32(t.a, t.b, t.wx), lerp32(t.c, t.d, t.wx), t.wy);
+}
+
+// Window of 8x8 source tiles that can reach a target tile: source tile
+// columns [wx0, wx0 + nwx), nwin tiles in all.
+struct Window {
+  int wx0, wy0, nwx, nwin;
+};
+
+// Candidate source tiles of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
+// during which each can reach it, appended to the LDS list (at most cap
+// entries: x-tile << 24 | y-tile << 16 | j_lo << 8 | j_hi).  *count must be
+// zero on entry; returns the number of candidates (uniform; more than cap
+// means the list overflowed).  Holds a barrier.
+__device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& dy, int K,
+                                                int Tx0, int Tx1, int Ty0, int Ty1,
+                                                uint32_t* list, int* count, int cap, Window& w) {
+  const int tid = threadIdx.x;
+  const int W = d.W, H = d.H;
+  const double M = __longlong_as_double((long long)dy.msq_bits);
+  const int Rw = (M > 1.0e12) ? (1 << 20) : ((int)ceil(sqrt(M)) + 3);
+  w.wx0 = max(0, Tx0 - Rw) / kSrcTile;
+  w.wy0 = max(0, Ty0 - Rw) / kSrcTile;
+  const int wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, W - 1) / kSrcTile);
+  const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcTile);
+  w.nwx = wx1 - w.wx0 + 1;
+  w.nwin = w.nwx * (wy1 - w.wy0 + 1);
+  for (int i = tid; i < w.nwin; i += kBlock) {
+    const int sxt = w.wx0 + i % w.nwx, syt = w.wy0 + i / w.nwx;
+    const int st = syt * d.ntx_src + sxt;
+    int jlo, jhi;
+    if (substep_range(ldg(d.tb, st), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
+                      syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1, K,
+                      jlo, jhi)) {
+      const int slot = atomicAdd(count, 1);
+      if (slot < cap)
+        list[slot] = ((uint32_t)sxt << 24) | ((uint32_t)syt << 16) | ((uint32_t)jlo << 8) | (uint32_t)jhi;
+    }
+  }
+  __syncthreads();
+  return __builtin_amdgcn_readfirstlane(*count);
+}
+
+// Splat every source that can reach the target tile at substep j (fraction
+// f): the active entries of the candidate list, or, if the list overflowed,
+// the active tiles of the whole window; each wave takes every fourth entry
+// and splats its active tiles in chunks.
+template <int TW>
+__device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_t* list, int nlist,
+                                                 bool overflow, const Window& w, int K, int j,
+                                                 float f, int Tx0, int Tx1, int Ty0, int Ty1,
+                                                 unsigned long long* zbuf) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int W = d.W, H = d.H;
+  if (!overflow) {
+    for (int base = 0; base < nlist; base += kBlock) {
+      const int e2 = base + lane * kWavesPerBlock + wave;
+      uint32_t ent = 0u;
+      bool act = false;
+      if (e2 < nlist) {
+        ent = list[e2];
+        const int jlo = (int)((ent >> 8) & 0xFFu), jhi = (int)(ent & 0xFFu);
+        act = (j >= jlo) && (j <= jhi);
+      }
+      unsigned long long mask = __ballot(act);
+      while (mask) {
+        int st[kChunk];
+        int nb = 0;
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+          st[c] = 0;
+          if (mask) {
+            const int b = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            st[c] = (int)((uint32_t)__builtin_amdgcn_readlane((int)ent, b) >> 16);   // sxt<<8 | syt
+            ++nb;
+          }
+        }
+        splat_chunk<TW>(d, st, nb, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+      }
+    }
+  } else {
+    // Window scan: the candidate list did not fit.
+    for (int i = wave; i < w.nwin; i += kWavesPerBlock) {
+      const int sxt = w.wx0 + i % w.nwx, syt = w.wy0 + i / w.nwx;
+      const int st0 = syt * d.ntx_src + sxt;
+      int jlo, jhi;
+      if (substep_range(ldg(d.tb, st0), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
+                        syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1, K,
+                        jlo, jhi) &&
+          j >= jlo && j <= jhi) {
+        int st[kChunk] = {};
+        st[0] = (sxt << 8) | syt;
+        splat_chunk<TW>(d, st, 1, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+      }
+    }
+  }
+}
+
+}  // namespace evis

@@ -40,7 +40,7 @@ struct evis_ctx {
   DevBuf meta;        // EnvDesc[n] followed by int32 src_prefix[n + 1]
   DevBuf dyn;         // EnvDyn[n]
   DevBuf sched;       // xbegin[8][n + 1], env_order[n], n_items[8], queue counters[8]
-  DevBuf dz;          // float[sum H*W]
+  DevBuf src;         // float4[sum H*W]: per-source splat record
   DevBuf tb;          // float4[sum source tiles]
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
@@ -272,7 +272,7 @@ struct Plan {
   int items = 0;
 };
 
-// Lay out per-env scratch (dZ, tile bounds) and the descriptor block.
+// Lay out per-env scratch (splat records, tile bounds) and the descriptor block.
 int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   const int n = (int)pl.desc.size();
   long long px = 0;
@@ -289,7 +289,7 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   pl.src_total = src;
   pl.items = items;
   bool grew = false;
-  int rc = ensure(ctx, ctx->dz, (size_t)px * sizeof(float), &grew);
+  int rc = ensure(ctx, ctx->src, (size_t)px * sizeof(float4), &grew);
   if (rc) return rc;
   rc = ensure(ctx, ctx->tb, (size_t)src * sizeof(float4), &grew);
   if (rc) return rc;
@@ -303,7 +303,7 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   }
   long long off_px = 0;
   for (int e = 0; e < n; ++e) {
-    pl.desc[e].dZ = static_cast<float*>(ctx->dz.p) + off_px;
+    pl.desc[e].src = static_cast<float4*>(ctx->src.p) + off_px;
     pl.desc[e].tb = static_cast<float4*>(ctx->tb.p) + pl.src_prefix[e];
     pl.desc[e].src_tile_base = pl.src_prefix[e];
     off_px += (long long)pl.desc[e].H * pl.desc[e].W;
@@ -402,7 +402,7 @@ void evis_destroy(evis_ctx* ctx) {
     hipEventDestroy(r.e1);
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
-  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->dz, &ctx->tb, &ctx->msq, &ctx->soft};
+  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->src, &ctx->tb, &ctx->msq, &ctx->soft};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {

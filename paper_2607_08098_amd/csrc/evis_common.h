@@ -34,7 +34,7 @@ struct EnvDesc {
   int32_t* tlast;          // may be null
   const float* th_on;      // may be null: C_on everywhere
   const float* th_off;     // may be null: C_off everywhere
-  float* dZ;               // scratch [H*W]: Zend - Z_A
+  float4* src;             // scratch [H*W]: (m_A.x, m_A.y, Z_A, Zend - Z_A) per source
   float4* tb;              // scratch [n source tiles]: (mx_min, mx_max, my_min, my_max)
   int32_t H, W;
   int32_t ntx_src, nty_src;    // 8x8 source tiles
@@ -173,20 +173,70 @@ __device__ __forceinline__ int wave_inclusive_scan(int v) {
   return v;
 }
 
+// Wave reductions by DPP butterflies within each row of 16 lanes (swap
+// neighbours, swap pairs, mirror halves of 8, mirror the row), then the four
+// row results read out to scalars.  The result is wave-uniform.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v = fminf(v, __shfl_xor(v, d, kWave));
-  return v;
+  v = fminf(v, dpp_f<kDppQuadSwap1>(v));
+  v = fminf(v, dpp_f<kDppQuadSwap2>(v));
+  v = fminf(v, dpp_f<kDppHalfMirror>(v));
+  v = fminf(v, dpp_f<kDppRowMirror>(v));
+  const int b = __float_as_int(v);
+  return fminf(fminf(__int_as_float(__builtin_amdgcn_readlane(b, 0)),
+                     __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+               fminf(__int_as_float(__builtin_amdgcn_readlane(b, 32)),
+                     __int_as_float(__builtin_amdgcn_readlane(b, 48))));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, kWave));
-  return v;
+  v = fmaxf(v, dpp_f<kDppQuadSwap1>(v));
+  v = fmaxf(v, dpp_f<kDppQuadSwap2>(v));
+  v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+  v = fmaxf(v, dpp_f<kDppRowMirror>(v));
+  const int b = __float_as_int(v);
+  return fmaxf(fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 0)),
+                     __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+               fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 32)),
+                     __int_as_float(__builtin_amdgcn_readlane(b, 48))));
+}
+
+// Largest of non-negative doubles (their bit patterns order like their
+// values): a 64-bit unsigned max on (hi, lo) halves.
+template <int CTRL>
+__device__ __forceinline__ void u64_max_step(uint32_t& hi, uint32_t& lo) {
+  const uint32_t h2 = (uint32_t)dpp_i<CTRL>((int)hi), l2 = (uint32_t)dpp_i<CTRL>((int)lo);
+  const bool take = (h2 > hi) || (h2 == hi && l2 > lo);
+  hi = take ? h2 : hi;
+  lo = take ? l2 : lo;
 }
 __device__ __forceinline__ double wave_max_d(double v) {
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  uint32_t hi = (uint32_t)(bits >> 32), lo = (uint32_t)bits;
+  u64_max_step<kDppQuadSwap1>(hi, lo);
+  u64_max_step<kDppQuadSwap2>(hi, lo);
+  u64_max_step<kDppHalfMirror>(hi, lo);
+  u64_max_step<kDppRowMirror>(hi, lo);
+  unsigned long long best = 0ull;
 #pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, kWave));
-  return v;
+  for (int r = 0; r < 4; ++r) {
+    const unsigned long long w =
+        ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)hi, 16 * r) << 32) |
+        (uint32_t)__builtin_amdgcn_readlane((int)lo, 16 * r);
+    best = (w > best) ? w : best;
+  }
+  return __longlong_as_double((long long)best);
 }
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

@@ -38,8 +38,10 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
 }
 
 // One wave per 8x8 source tile: endpoint depth (Eq. 7, p_B = p - m_A(p),
-// Z_B edge-clamped) stored as Zend - Z_A, the tile's bounds of m_A over
-// sources with a finite motion vector, and the env's largest finite |m|^2.
+// Z_B edge-clamped), stored with m_A and Z_A as the source's splat record
+// (m_A.x, m_A.y, Z_A, Zend - Z_A) so that the splat reads one 16-byte value
+// per source; the tile's bounds of m_A over sources with a finite motion
+// vector; and the env's largest finite |m|^2.
 __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ envs, EnvDyn* dyn,
                                                  const int32_t* __restrict__ src_prefix,
                                                  int n_envs, int total) {
@@ -47,51 +49,85 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
   for (int i = threadIdx.x; i <= n_envs; i += kBlock) s_prefix[i] = src_prefix[i];
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
-  const int gt = blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
-  if (gt >= total) return;   // wave-uniform
-  int lo = 0, hi = n_envs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_prefix[mid] <= gt) lo = mid; else hi = mid - 1;
-  }
-  const int e = lo;
-  const EnvDesc& d = envs[e];
-  const int t = gt - s_prefix[e];
-  const int tx = t % d.ntx_src, ty = t / d.ntx_src;
-  const int x = tx * kSrcTile + (lane & 7), y = ty * kSrcTile + (lane >> 3);
+  const int nwaves = (int)gridDim.x * kWavesPerBlock;
+  const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
+  const int chunk = (total + nwaves - 1) / nwaves;
+  const int c0 = min(total, wid * chunk), c1 = min(total, c0 + chunk);
+  constexpr int U = 2;   // source tiles in flight per wave
   const float inf = __int_as_float(0x7f800000);
-  float mnx = inf, mxx = -inf, mny = inf, mxy = -inf;
-  double msq = 0.0;
-  if (x < d.W && y < d.H) {
-    const int p = y * d.W + x;
-    const float2 a = ldg(d.mA, p);
-    const float2 b = ldg(d.mB, p);
-    const float sx = clamp_into((float)x - a.x, (float)(d.W - 1));
-    const float sy = clamp_into((float)y - a.y, (float)(d.H - 1));
-    const float zend = bilinear(d.ZB, d.H, d.W, sx, sy);
-    stg(d.dZ, p, zend - ldg(d.ZA, p));
-    if (finite32(a.x) && finite32(a.y)) {
-      mnx = mxx = a.x;
-      mny = mxy = a.y;
+  // the env's largest |m|^2 seen by this wave, published when the env changes
+  int run_env = -1;
+  double run_msq = 0.0;
+  auto publish = [&]() {
+    if (run_env >= 0 && run_msq > 0.0 && lane == 0)
+      atomicMax(&dyn[run_env].msq_bits, (unsigned long long)__double_as_longlong(run_msq));
+  };
+  // each wave walks a contiguous run of source tiles (wave-uniform loop), U
+  // tiles at a time so that their loads overlap
+  for (int g0 = c0; g0 < c1; g0 += U) {
+    int e[U], t[U], x[U], y[U], p[U];
+    bool in[U];
+    float2 ma[U], mb[U];
+    float za[U], zend[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int gt = min(g0 + u, c1 - 1);   // a duplicate of the last tile is harmless
+      int lo = 0, hi = n_envs - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_prefix[mid] <= gt) lo = mid; else hi = mid - 1;
+      }
+      e[u] = lo;
+      const EnvDesc& d = envs[lo];
+      t[u] = gt - s_prefix[lo];
+      const int tx = t[u] % d.ntx_src, ty = t[u] / d.ntx_src;
+      x[u] = tx * kSrcTile + (lane & 7);
+      y[u] = ty * kSrcTile + (lane >> 3);
+      in[u] = x[u] < d.W && y[u] < d.H;
+      p[u] = in[u] ? y[u] * d.W + x[u] : 0;
+      ma[u] = ldg(d.mA, p[u]);
+      mb[u] = ldg(d.mB, p[u]);
+      za[u] = ldg(d.ZA, p[u]);
     }
-    const double ma = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-    const double mb = (double)b.x * (double)b.x + (double)b.y * (double)b.y;
-    if (ma <= 1.7976931348623157e308) msq = ma;
-    if (mb <= 1.7976931348623157e308 && mb > msq) msq = mb;
-  }
-  mnx = wave_min(mnx);
-  mxx = wave_max(mxx);
-  mny = wave_min(mny);
-  mxy = wave_max(mxy);
-  msq = wave_max_d(msq);
-  if (lane == 0) {
-    stg(d.tb, t, make_float4(mnx, mxx, mny, mxy));
-    if (msq > 0.0) {
-      unsigned long long* slot = &dyn[e].msq_bits;
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(msq);
-      if (bits > __atomic_load_n(slot, __ATOMIC_RELAXED)) atomicMax(slot, bits);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const EnvDesc& d = envs[e[u]];
+      const float sx = clamp_into((float)x[u] - ma[u].x, (float)(d.W - 1));
+      const float sy = clamp_into((float)y[u] - ma[u].y, (float)(d.H - 1));
+      zend[u] = bilinear(d.ZB, d.H, d.W, sx, sy);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const EnvDesc& d = envs[e[u]];
+      float mnx = inf, mxx = -inf, mny = inf, mxy = -inf;
+      double msq = 0.0;
+      if (in[u]) {
+        const float2 a = ma[u], b = mb[u];
+        stg(d.src, p[u], make_float4(a.x, a.y, za[u], zend[u] - za[u]));
+        if (finite32(a.x) && finite32(a.y)) {
+          mnx = mxx = a.x;
+          mny = mxy = a.y;
+        }
+        const double mda = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        const double mdb = (double)b.x * (double)b.x + (double)b.y * (double)b.y;
+        if (mda <= 1.7976931348623157e308) msq = mda;
+        if (mdb <= 1.7976931348623157e308 && mdb > msq) msq = mdb;
+      }
+      mnx = wave_min(mnx);
+      mxx = wave_max(mxx);
+      mny = wave_min(mny);
+      mxy = wave_max(mxy);
+      msq = wave_max_d(msq);
+      if (lane == 0) stg(d.tb, t[u], make_float4(mnx, mxx, mny, mxy));
+      if (e[u] != run_env) {   // wave-uniform
+        publish();
+        run_env = e[u];
+        run_msq = 0.0;
+      }
+      run_msq = fmax(run_msq, msq);
     }
   }
+  publish();
 }
 
 // Single workgroup: each env's K (fixed or the exact adaptive count), its
@@ -458,7 +494,8 @@ hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue, unsigned l
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
                        int total_src_tiles, hipStream_t s) {
   if (total_src_tiles <= 0) return hipSuccess;
-  const int blocks = (total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  // a run of source tiles per wave: 256 CUs x 8 workgroups at most
+  const int blocks = std::min((total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
   hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kBlock), 0, s, envs, dyn, src_prefix, n_envs,
                      total_src_tiles);
   return hipGetLastError();

@@ -69,34 +69,25 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kC
                                             float f, int Tx0, int Tx1, int Ty0, int Ty1,
                                             unsigned long long* zbuf) {
   const int lane = threadIdx.x & (kWave - 1);
-  float2 m[kChunk];
-  float za[kChunk], dz[kChunk];
-  int sxs[kChunk], sys[kChunk];
-  bool ok[kChunk];
+  float4 rec[kChunk];   // (m_A.x, m_A.y, Z_A, Zend - Z_A)
+  int src[kChunk];      // source index, -1 outside the image or past nb
+  // All loads first, unconditionally (a lane without a source reads record
+  // 0), so that they are in flight together.
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
-    ok[c] = false;
-    sxs[c] = 0;
-    sys[c] = 0;
-    if (c < nb) {
-      const int sxt = st[c] >> 8, syt = st[c] & 0xFF;   // wave-uniform
-      sxs[c] = sxt * kSrcTile + (lane & 7);
-      sys[c] = syt * kSrcTile + (lane >> 3);
-      ok[c] = (sxs[c] < d.W) && (sys[c] < d.H);
-    }
-    if (ok[c]) {
-      const int p = sys[c] * d.W + sxs[c];
-      m[c] = ldg(d.mA, p);
-      za[c] = ldg(d.ZA, p);
-      dz[c] = ldg(d.dZ, p);
-    }
+    const int sxt = st[c] >> 8, syt = st[c] & 0xFF;   // wave-uniform
+    const int sx = sxt * kSrcTile + (lane & 7), sy = syt * kSrcTile + (lane >> 3);
+    const bool ok = (c < nb) && (sx < d.W) && (sy < d.H);
+    src[c] = ok ? sy * d.W + sx : -1;
+    rec[c] = ldg(d.src, ok ? src[c] : 0);
   }
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
-    if (!ok[c]) continue;
-    const float qx = (float)sxs[c] - f * m[c].x;
-    const float qy = (float)sys[c] - f * m[c].y;
-    const float zt = za[c] + f * dz[c];
+    if (src[c] < 0) continue;
+    const int sxt = st[c] >> 8, syt = st[c] & 0xFF;
+    const float qx = (float)(sxt * kSrcTile + (lane & 7)) - f * rec[c].x;
+    const float qy = (float)(syt * kSrcTile + (lane >> 3)) - f * rec[c].y;
+    const float zt = rec[c].z + f * rec[c].w;
     if (!(zt > 0.0f)) continue;
     if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
           qy < (float)(Ty1 + 1)))
@@ -104,8 +95,7 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kC
     const float fx0 = floorf(qx), fy0 = floorf(qy);
     const int x0 = (int)fx0, y0 = (int)fy0;
     const bool bx = (qx - fx0) > 0.0f, by = (qy - fy0) > 0.0f;
-    const unsigned p = (unsigned)(sys[c] * d.W + sxs[c]);
-    const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | p;
+    const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | (uint32_t)src[c];
     const int lx = x0 - Tx0, ly = y0 - Ty0;
     const bool in_x0 = x0 >= Tx0, in_x1 = bx && (x0 + 1 <= Tx1);
     const bool in_y0 = y0 >= Ty0, in_y1 = by && (y0 + 1 <= Ty1);

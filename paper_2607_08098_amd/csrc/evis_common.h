@@ -84,6 +84,26 @@ __device__ __forceinline__ void stg(T* p, int idx, T v) {
 #endif
 }
 
+// Loads and stores of workgroup-shared (LDS) arrays reached through a plain
+// pointer: the cast lets the compiler emit LDS instructions instead of
+// generic (flat) ones, which would also wait on outstanding global loads.
+template <typename T>
+__device__ __forceinline__ T lds_ld(const T* p, int idx) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return ((const __attribute__((address_space(3))) T*)p)[idx];
+#else
+  return p[idx];
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(T* p, int idx, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ((__attribute__((address_space(3))) T*)p)[idx] = v;
+#else
+  p[idx] = v;
+#endif
+}
+
 __device__ __forceinline__ float lerp32(float a, float b, float w) {
   return a + w * (b - a);
 }

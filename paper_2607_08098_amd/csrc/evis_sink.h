@@ -49,7 +49,7 @@ __device__ __forceinline__ void sink_init(const SinkShared& sh) {
 // after a barrier that follows the last emission.
 __device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& so) {
   const int tid = threadIdx.x;
-  const int n = *sh.cnt;   // stable: no wave emits until the closing barrier
+  const int n = lds_ld(sh.cnt, 0);   // stable: no wave emits until the closing barrier
   if (n == 0) return;      // workgroup-uniform
   __syncthreads();         // every wave has read cnt
   if (tid == 0) *sh.gbase = atomicAdd(so.cursor, (unsigned long long)n);
@@ -57,7 +57,7 @@ __device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& 
   const unsigned long long gb = *sh.gbase;
   for (int i = tid; i < n; i += kBlock) {
     if ((long long)(gb + i) < so.capacity) {
-      const uint2 r = sh.buf[i];
+      const uint2 r = lds_ld(sh.buf, i);
       so.out[gb + i] = evis_event{r.x, (int32_t)r.y};
     }
   }
@@ -75,7 +75,7 @@ __device__ __forceinline__ void sink_check(const SinkShared& sh, const SinkOut& 
                                            SinkRound& sr) {
   if (!sr.unchecked) return;
   sr.unchecked = false;
-  const int want = __builtin_amdgcn_readfirstlane(sh.req[(sr.round - 1) & 1]);
+  const int want = __builtin_amdgcn_readfirstlane(lds_ld(sh.req, (sr.round - 1) & 1));
   if (want) sink_drain(sh, so);
 }
 
@@ -93,12 +93,12 @@ struct PixAux {
   int row_shift;    // log2(row) for a tile (row a power of two); unused for a flat range
   long long flat0;  // first pixel of the block when row == W (flat range), else -1
   __device__ __forceinline__ float c_at(int i, bool pos) const {
-    if (pos) return con ? con[i] : C_on;
-    return coff ? coff[i] : C_off;
+    if (pos) return con ? lds_ld(con, i) : C_on;
+    return coff ? lds_ld(coff, i) : C_off;
   }
   __device__ __forceinline__ float c(int k, bool pos) const { return c_at(threadIdx.x + k * kBlock, pos); }
-  __device__ __forceinline__ int tlast(int k) const { return tl[threadIdx.x + k * kBlock]; }
-  __device__ __forceinline__ void set_tlast_at(int i, int t) const { tl[i] = t; }
+  __device__ __forceinline__ int tlast(int k) const { return lds_ld(tl, (int)threadIdx.x + k * kBlock); }
+  __device__ __forceinline__ void set_tlast_at(int i, int t) const { lds_st(tl, i, t); }
   __device__ __forceinline__ uint32_t xy_at(int i) const {
     long long x, y;
     if (flat0 >= 0) {
@@ -184,14 +184,14 @@ __device__ __forceinline__ void emit_substep(
       if (lane == kWave - 1) g = atomicAdd(so.cursor, (unsigned long long)wtot);
       gbase_w = __shfl(g, kWave - 1, kWave);
     }
-    if (lane == kWave - 1 && (to_global || lb + wtot > sh.cap - sh.cap / 4)) sh.req[slot_req] = 1;
+    if (lane == kWave - 1 && (to_global || lb + wtot > sh.cap - sh.cap / 4)) lds_st(sh.req, slot_req, 1);
     const int lbase_w = to_global ? 0 : lb;
     auto put = [&](int slot, uint32_t word, int t) {
       if (to_global) {
         const unsigned long long idx = gbase_w + (unsigned long long)slot;
         if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
       } else {
-        sh.buf[lbase_w + slot] = make_uint2(word, (uint32_t)t);
+        lds_st(sh.buf, lbase_w + slot, make_uint2(word, (uint32_t)t));
       }
     };
     if (refr == 0) {

@@ -156,10 +156,14 @@ __device__ __forceinline__ void emit_substep(
       }
     }
   }
-  // Wave offsets by prefix sum; the wave's slots by one reservation.
-  const int incl = wave_inclusive_scan(m);
-  const int excl = incl - m;
-  const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+  // Wave offsets by prefix sum (skipped when no lane has an event); the
+  // wave's slots by one reservation.
+  int incl = 0, excl = 0, wtot = 0;
+  if (__ballot(m > 0) != 0ull) {   // wave-uniform
+    incl = wave_inclusive_scan(m);
+    excl = incl - m;
+    wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+  }
   const int slot_req = sr.round & 1;
   ++sr.round;
   sr.unchecked = true;

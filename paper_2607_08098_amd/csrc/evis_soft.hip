@@ -27,13 +27,13 @@ template <int TW, int TH, bool BWD>
 __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
   constexpr int NPX = TW * TH;
   constexpr int PPT = NPX / kBlock;
-  constexpr int ZS = zrow<TW>();
-  __shared__ unsigned long long zbuf[ZS * TH];
+  constexpr int ZN = zcells<TW, TH>();
+  __shared__ unsigned long long zbuf[ZN];
   __shared__ uint32_t list[kListCapMax];
   __shared__ int s_lcnt;
   __shared__ float s_red[kWavesPerBlock];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int i = tid; i < ZS * TH; i += kBlock) zbuf[i] = kEmptyKey;
+  for (int i = tid; i < ZN; i += kBlock) zbuf[i] = kEmptyKey;
   if (tid == 0) s_lcnt = 0;
   const int item = (int)blockIdx.x;
   int lo = 0, hi = a.n_envs - 1;
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
       BTaps bt;
       if (j < K) {
         const int i = tid + k * kBlock;
-        const int zi = (i / TW) * ZS + (i % TW);
+        const int zi = zcell<TW>(i % TW, i / TW);
         const unsigned long long key = zbuf[zi];
         zbuf[zi] = kEmptyKey;
         vA = key != kEmptyKey;

@@ -209,8 +209,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int PPT = NPX / kBlock;
   static_assert(PPT * kBlock == NPX, "tile must be a multiple of the workgroup");
   constexpr int EVB = (MODE == MODE_STEP) ? kEventBuf : 1;
-  constexpr int ZS = zrow<TW>();
-  __shared__ unsigned long long zbuf[2 * ZS * TH];
+  constexpr int ZN = zcells<TW, TH>();
+  __shared__ unsigned long long zbuf[2 * ZN];
   __shared__ uint32_t list[kListCapMax];
   __shared__ uint2 evbuf[EVB];
   __shared__ int s_evn, s_req[2];
@@ -221,7 +221,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   __shared__ int s_tl[AUXN];
 
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  for (int i = tid; i < 2 * ZS * TH; i += kBlock) zbuf[i] = kEmptyKey;
   const SinkShared sh{evbuf, &s_evn, s_req, &s_gbase, EVB};
   const SinkOut so{a.out, a.capacity, a.cursor};
   SinkRound sr;
@@ -233,6 +232,9 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   for (;;) {
     __syncthreads();
     if (MODE == MODE_STEP) sink_check(sh, so, sr);
+    // Readers clear the cells they read; apron cells and those of pixels
+    // outside the image are cleared here, once per item.
+    for (int i = tid; i < 2 * ZN; i += kBlock) zbuf[i] = kEmptyKey;
     if (tid == 0) {
       int item = -1, r = 0, q = -1;
       while (qsel < kXcd) {
@@ -404,7 +406,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
       float cAh[PPT], cBh[PPT];
       uint32_t chb[PPT];
-      unsigned long long* zb = zbuf + (j & 1) * (ZS * TH);
+      unsigned long long* zb = zbuf + (j & 1) * ZN;
       if (!is_static) {
         // (1) B-gather loads of substep j
         BTaps bt[PPT];
@@ -418,7 +420,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           const int i = tid + k * kBlock;
-          const int zi = (i / TW) * ZS + (i % TW);
+          const int zi = zcell<TW>(i % TW, i / TW);
           bool vA = false;
           cAh[k] = 0.0f;
           if ((okbits >> k) & 1u) {

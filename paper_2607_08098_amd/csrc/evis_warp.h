@@ -53,11 +53,19 @@ __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy
   return true;
 }
 
-// The LDS z-buffer of a TW x TH target tile has rows of ZS(TW) = TW + 8
-// keys: consecutive rows then start 64 bytes apart in the 32 banks, so the
-// 8 rows touched by one source tile's footprint spread over all banks.
+// The LDS z-buffer of a TW x TH target tile has an apron of one cell on
+// every side, so that every footprint corner of a source that lands in
+// [Tx0 - 1, Tx1 + 1) x [Ty0 - 1, Ty1 + 1) has a cell; apron cells (and
+// those of pixels outside the image) are written but never read.  Rows are
+// ZS(TW) = TW + 8 keys long: consecutive rows then start 64 bytes apart in
+// the banks, so the rows touched by one source tile's footprint spread.
 template <int TW>
 __device__ __forceinline__ constexpr int zrow() { return TW + 8; }
+template <int TW, int TH>
+__device__ __forceinline__ constexpr int zcells() { return zrow<TW>() * (TH + 2); }
+// Cell of target pixel (lx, ly) of the tile (lx in [-1, TW], ly in [-1, TH]).
+template <int TW>
+__device__ __forceinline__ int zcell(int lx, int ly) { return (ly + 1) * zrow<TW>() + (lx + 1); }
 
 // Splat up to kChunk source tiles (one source per lane and tile) at fraction
 // f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].  The loads of
@@ -93,18 +101,20 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kC
           qy < (float)(Ty1 + 1)))
       continue;
     const float fx0 = floorf(qx), fy0 = floorf(qy);
-    const int x0 = (int)fx0, y0 = (int)fy0;
-    const bool bx = (qx - fx0) > 0.0f, by = (qy - fy0) > 0.0f;
+    const bool bx = qx > fx0, by = qy > fy0;   // corners of strictly positive weight
     const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | (uint32_t)src[c];
-    const int lx = x0 - Tx0, ly = y0 - Ty0;
-    const bool in_x0 = x0 >= Tx0, in_x1 = bx && (x0 + 1 <= Tx1);
-    const bool in_y0 = y0 >= Ty0, in_y1 = by && (y0 + 1 <= Ty1);
+    // Corner (x0, y0) always; a corner of zero weight repeats it instead
+    // (the same key twice into one cell changes nothing), so the four
+    // atomics need no branches.
     constexpr int ZS = zrow<TW>();
-    unsigned long long* zr = zbuf + ly * ZS + lx;
-    if (in_x0 && in_y0) atomicMin(zr, key);
-    if (in_x1 && in_y0) atomicMin(zr + 1, key);
-    if (in_x0 && in_y1) atomicMin(zr + ZS, key);
-    if (in_x1 && in_y1) atomicMin(zr + ZS + 1, key);
+    const int c00 = zcell<TW>((int)fx0 - Tx0, (int)fy0 - Ty0);
+    const int c01 = bx ? c00 + 1 : c00;
+    const int c10 = by ? c00 + ZS : c00;
+    const int c11 = (bx && by) ? c00 + ZS + 1 : c00;
+    atomicMin(zbuf + c00, key);
+    atomicMin(zbuf + c01, key);
+    atomicMin(zbuf + c10, key);
+    atomicMin(zbuf + c11, key);
   }
 }
 

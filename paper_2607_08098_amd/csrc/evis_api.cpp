@@ -40,8 +40,8 @@ struct evis_ctx {
   DevBuf meta;        // EnvDesc[n] followed by int32 src_prefix[n + 1]
   DevBuf dyn;         // EnvDyn[n]
   DevBuf sched;       // xbegin[8][n + 1], env_order[n], n_items[8], queue counters[8]
-  DevBuf src;         // float4[sum H*W]: per-source splat record
-  DevBuf tb;          // float4[sum source tiles]
+  DevBuf src;         // float4[16 per 4x4 source block]: per-source splat records
+  DevBuf tb;          // float4[per 4x4 source block]: motion bounds
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
   std::vector<unsigned char> soft_shadow;
@@ -248,8 +248,8 @@ EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st
   d.th_off = s.theta_off;
   d.H = p.H;
   d.W = p.W;
-  d.ntx_src = (p.W + kSrcTile - 1) / kSrcTile;
-  d.nty_src = (p.H + kSrcTile - 1) / kSrcTile;
+  d.ntx_src = (p.W + kSrcBlk - 1) / kSrcBlk;
+  d.nty_src = (p.H + kSrcBlk - 1) / kSrcBlk;
   d.K_fixed = s.K > 0 ? s.K : 0;
   d.K_max = s.K_max;
   d.blend = s.blend_mode;
@@ -266,9 +266,9 @@ size_t sched_ints(int n) { return (size_t)kXcd * (n + 1) + n + 2 * kXcd; }
 
 struct Plan {
   std::vector<EnvDesc> desc;
-  std::vector<int32_t> src_prefix;   // n + 1
+  std::vector<int32_t> src_prefix;   // n + 1: groups of four source blocks before each env
   long long px_total = 0;
-  int src_total = 0;
+  int src_total = 0;                 // groups of four source blocks (prep work units)
   int items = 0;
 };
 
@@ -281,7 +281,7 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   for (int e = 0; e < n; ++e) {
     pl.src_prefix[e] = src;
     px += (long long)pl.desc[e].H * pl.desc[e].W;
-    src += pl.desc[e].ntx_src * pl.desc[e].nty_src;
+    src += (pl.desc[e].ntx_src * pl.desc[e].nty_src + 3) / 4;
     items += ((pl.desc[e].W + tw - 1) / tw) * ((pl.desc[e].H + th - 1) / th);
   }
   pl.src_prefix[n] = src;
@@ -289,9 +289,10 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   pl.src_total = src;
   pl.items = items;
   bool grew = false;
-  int rc = ensure(ctx, ctx->src, (size_t)px * sizeof(float4), &grew);
+  // per block: one bounds record and 16 splat records (four blocks per group)
+  int rc = ensure(ctx, ctx->src, (size_t)src * 4 * kBlkPx * sizeof(float4), &grew);
   if (rc) return rc;
-  rc = ensure(ctx, ctx->tb, (size_t)src * sizeof(float4), &grew);
+  rc = ensure(ctx, ctx->tb, (size_t)src * 4 * sizeof(float4), &grew);
   if (rc) return rc;
   rc = ensure(ctx, ctx->dyn, (size_t)n * sizeof(EnvDyn), &grew);
   if (rc) return rc;
@@ -301,12 +302,11 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
     drop_graphs(ctx);
     ctx->shadow.clear();
   }
-  long long off_px = 0;
   for (int e = 0; e < n; ++e) {
-    pl.desc[e].src = static_cast<float4*>(ctx->src.p) + off_px;
-    pl.desc[e].tb = static_cast<float4*>(ctx->tb.p) + pl.src_prefix[e];
+    const long long blk0 = 4LL * pl.src_prefix[e];
+    pl.desc[e].src = static_cast<float4*>(ctx->src.p) + blk0 * kBlkPx;
+    pl.desc[e].tb = static_cast<float4*>(ctx->tb.p) + blk0;
     pl.desc[e].src_tile_base = pl.src_prefix[e];
-    off_px += (long long)pl.desc[e].H * pl.desc[e].W;
   }
   return EVIS_OK;
 }

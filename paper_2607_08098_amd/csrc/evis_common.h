@@ -17,7 +17,8 @@ namespace evis {
 constexpr int kWave = 64;
 constexpr int kBlock = 256;                 // 4 waves per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kSrcTile = 8;                 // source tiles are 8x8 = one wave
+constexpr int kSrcBlk = 4;                  // source blocks are 4x4 pixels
+constexpr int kBlkPx = kSrcBlk * kSrcBlk;   // 16 lanes, one row of a wave
 constexpr uint64_t kEmptyKey = 0xFFFFFFFFFFFFFFFFull;
 constexpr int kMaxCross = EVIS_MAX_CROSSINGS;
 
@@ -34,11 +35,12 @@ struct EnvDesc {
   int32_t* tlast;          // may be null
   const float* th_on;      // may be null: C_on everywhere
   const float* th_off;     // may be null: C_off everywhere
-  float4* src;             // scratch [H*W]: (m_A.x, m_A.y, Z_A, Zend - Z_A) per source
-  float4* tb;              // scratch [n source tiles]: (mx_min, mx_max, my_min, my_max)
+  float4* src;             // scratch [blocks * 16]: (m_A.x, m_A.y, Z_A, Zend - Z_A) per
+                           // source, block-major (block by * ntx_src + bx, then row-major)
+  float4* tb;              // scratch [blocks]: (mx_min, mx_max, my_min, my_max) per block
   int32_t H, W;
-  int32_t ntx_src, nty_src;    // 8x8 source tiles
-  int32_t src_tile_base;       // prefix over envs, for the prep kernel
+  int32_t ntx_src, nty_src;    // 4x4 source blocks per row / column
+  int32_t src_tile_base;       // prefix over envs of groups of four blocks (prep work units)
   int32_t K_fixed;             // > 0: fixed K
   int32_t K_max;
   int32_t blend;
@@ -209,23 +211,28 @@ constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppRowMirror = 0x140;
 
-__device__ __forceinline__ float wave_min(float v) {
+// Minimum / maximum over each row of 16 lanes (every lane of the row gets it).
+__device__ __forceinline__ float row16_min(float v) {
   v = fminf(v, dpp_f<kDppQuadSwap1>(v));
   v = fminf(v, dpp_f<kDppQuadSwap2>(v));
   v = fminf(v, dpp_f<kDppHalfMirror>(v));
-  v = fminf(v, dpp_f<kDppRowMirror>(v));
-  const int b = __float_as_int(v);
+  return fminf(v, dpp_f<kDppRowMirror>(v));
+}
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp_f<kDppQuadSwap1>(v));
+  v = fmaxf(v, dpp_f<kDppQuadSwap2>(v));
+  v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+  return fmaxf(v, dpp_f<kDppRowMirror>(v));
+}
+__device__ __forceinline__ float wave_min(float v) {
+  const int b = __float_as_int(row16_min(v));
   return fminf(fminf(__int_as_float(__builtin_amdgcn_readlane(b, 0)),
                      __int_as_float(__builtin_amdgcn_readlane(b, 16))),
                fminf(__int_as_float(__builtin_amdgcn_readlane(b, 32)),
                      __int_as_float(__builtin_amdgcn_readlane(b, 48))));
 }
 __device__ __forceinline__ float wave_max(float v) {
-  v = fmaxf(v, dpp_f<kDppQuadSwap1>(v));
-  v = fmaxf(v, dpp_f<kDppQuadSwap2>(v));
-  v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
-  v = fmaxf(v, dpp_f<kDppRowMirror>(v));
-  const int b = __float_as_int(v);
+  const int b = __float_as_int(row16_max(v));
   return fmaxf(fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 0)),
                      __int_as_float(__builtin_amdgcn_readlane(b, 16))),
                fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 32)),

@@ -30,6 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
   constexpr int ZN = zcells<TW, TH>();
   __shared__ unsigned long long zbuf[ZN];
   __shared__ uint32_t list[kListCapMax];
+  __shared__ uint32_t s_wl[kWavesPerBlock][kWave];
   __shared__ int s_lcnt;
   __shared__ float s_red[kWavesPerBlock];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -87,7 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
     const float g = 1.0f - f;
     const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
     if (j < K) {
-      splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+      splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, s_wl[wave],
+                           zbuf);
       __syncthreads();
     }
 #pragma unroll

@@ -37,11 +37,13 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
   if (i == 0 && cursor) *cursor = 0ull;
 }
 
-// One wave per 8x8 source tile: endpoint depth (Eq. 7, p_B = p - m_A(p),
-// Z_B edge-clamped), stored with m_A and Z_A as the source's splat record
-// (m_A.x, m_A.y, Z_A, Zend - Z_A) so that the splat reads one 16-byte value
-// per source; the tile's bounds of m_A over sources with a finite motion
-// vector; and the env's largest finite |m|^2.
+// Per 4x4 source block (a row of 16 lanes; a wave takes four consecutive
+// blocks of one env): the endpoint depth (Eq. 7, p_B = p - m_A(p), Z_B
+// edge-clamped), stored with m_A and Z_A as the source's splat record
+// (m_A.x, m_A.y, Z_A, Zend - Z_A), block-major, so that the splat reads one
+// 16-byte value per source and a block's 16 records are contiguous; the
+// block's bounds of m_A over sources with a finite motion vector; and the
+// env's largest finite |m|^2.
 __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ envs, EnvDyn* dyn,
                                                  const int32_t* __restrict__ src_prefix,
                                                  int n_envs, int total) {
@@ -49,11 +51,12 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
   for (int i = threadIdx.x; i <= n_envs; i += kBlock) s_prefix[i] = src_prefix[i];
   __syncthreads();
   const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane >> 4, r = lane & (kBlkPx - 1);   // block of the group, lane in the block
   const int nwaves = (int)gridDim.x * kWavesPerBlock;
   const int wid = blockIdx.x * kWavesPerBlock + (threadIdx.x / kWave);
   const int chunk = (total + nwaves - 1) / nwaves;
   const int c0 = min(total, wid * chunk), c1 = min(total, c0 + chunk);
-  constexpr int U = 2;   // source tiles in flight per wave
+  constexpr int U = 2;   // groups in flight per wave
   const float inf = __int_as_float(0x7f800000);
   // the env's largest |m|^2 seen by this wave, published when the env changes
   int run_env = -1;
@@ -62,16 +65,16 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
     if (run_env >= 0 && run_msq > 0.0 && lane == 0)
       atomicMax(&dyn[run_env].msq_bits, (unsigned long long)__double_as_longlong(run_msq));
   };
-  // each wave walks a contiguous run of source tiles (wave-uniform loop), U
-  // tiles at a time so that their loads overlap
+  // each wave walks a contiguous run of block groups (wave-uniform loop), U
+  // groups at a time so that their loads overlap
   for (int g0 = c0; g0 < c1; g0 += U) {
-    int e[U], t[U], x[U], y[U], p[U];
-    bool in[U];
+    int e[U], blk[U], x[U], y[U], p[U];
+    bool has[U], in[U];
     float2 ma[U], mb[U];
     float za[U], zend[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int gt = min(g0 + u, c1 - 1);   // a duplicate of the last tile is harmless
+      const int gt = min(g0 + u, c1 - 1);   // a duplicate of the last group is harmless
       int lo = 0, hi = n_envs - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -79,11 +82,12 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
       }
       e[u] = lo;
       const EnvDesc& d = envs[lo];
-      t[u] = gt - s_prefix[lo];
-      const int tx = t[u] % d.ntx_src, ty = t[u] / d.ntx_src;
-      x[u] = tx * kSrcTile + (lane & 7);
-      y[u] = ty * kSrcTile + (lane >> 3);
-      in[u] = x[u] < d.W && y[u] < d.H;
+      blk[u] = (gt - s_prefix[lo]) * 4 + g;
+      has[u] = blk[u] < d.ntx_src * d.nty_src;
+      const int bx = has[u] ? blk[u] % d.ntx_src : 0, by = has[u] ? blk[u] / d.ntx_src : 0;
+      x[u] = bx * kSrcBlk + (r & 3);
+      y[u] = by * kSrcBlk + (r >> 2);
+      in[u] = has[u] && x[u] < d.W && y[u] < d.H;
       p[u] = in[u] ? y[u] * d.W + x[u] : 0;
       ma[u] = ldg(d.mA, p[u]);
       mb[u] = ldg(d.mB, p[u]);
@@ -103,7 +107,6 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
       double msq = 0.0;
       if (in[u]) {
         const float2 a = ma[u], b = mb[u];
-        stg(d.src, p[u], make_float4(a.x, a.y, za[u], zend[u] - za[u]));
         if (finite32(a.x) && finite32(a.y)) {
           mnx = mxx = a.x;
           mny = mxy = a.y;
@@ -113,12 +116,15 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
         if (mda <= 1.7976931348623157e308) msq = mda;
         if (mdb <= 1.7976931348623157e308 && mdb > msq) msq = mdb;
       }
-      mnx = wave_min(mnx);
-      mxx = wave_max(mxx);
-      mny = wave_min(mny);
-      mxy = wave_max(mxy);
+      if (has[u])
+        stg(d.src, blk[u] * kBlkPx + r,
+            in[u] ? make_float4(ma[u].x, ma[u].y, za[u], zend[u] - za[u]) : make_float4(0.f, 0.f, 0.f, 0.f));
+      mnx = row16_min(mnx);
+      mxx = row16_max(mxx);
+      mny = row16_min(mny);
+      mxy = row16_max(mxy);
       msq = wave_max_d(msq);
-      if (lane == 0) stg(d.tb, t[u], make_float4(mnx, mxx, mny, mxy));
+      if (r == 0 && has[u]) stg(d.tb, blk[u], make_float4(mnx, mxx, mny, mxy));
       if (e[u] != run_env) {   // wave-uniform
         publish();
         run_env = e[u];
@@ -212,6 +218,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int ZN = zcells<TW, TH>();
   __shared__ unsigned long long zbuf[2 * ZN];
   __shared__ uint32_t list[kListCapMax];
+  __shared__ uint32_t s_wl[kWavesPerBlock][kWave];   // per-wave packed active candidates
   __shared__ uint2 evbuf[EVB];
   __shared__ int s_evn, s_req[2];
   __shared__ unsigned long long s_gbase;
@@ -321,7 +328,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       bool okst = true;
       for (int e2 = tid; e2 < nlist; e2 += kBlock) {
         const uint32_t ent = list[e2];
-        const float4 b = ldg(d.tb, (int)((ent >> 16) & 0xFFu) * d.ntx_src + (int)(ent >> 24));
+        const float4 b = ldg(d.tb, cand_by(ent) * d.ntx_src + cand_bx(ent));
         okst = okst && b.x == 0.0f && b.y == 0.0f && b.z == 0.0f && b.w == 0.0f;
       }
 #pragma unroll
@@ -413,7 +420,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) bt[k] = b_taps(d, pix_x(k), pix_y(k), mBq[k], g, (okbits >> k) & 1u);
         // (2) splat substep j
-        splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, zb);
+        splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1,
+                             s_wl[wave], zb);
         __syncthreads();
         if (MODE == MODE_STEP) sink_check(sh, so, sr);
         // (3) winners of substep j: issue their L_A loads; B values
@@ -496,7 +504,7 @@ hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue, unsigned l
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
                        int total_src_tiles, hipStream_t s) {
   if (total_src_tiles <= 0) return hipSuccess;
-  // a run of source tiles per wave: 256 CUs x 8 workgroups at most
+  // a run of block groups per wave: 256 CUs x 8 workgroups at most
   const int blocks = std::min((total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
   hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kBlock), 0, s, envs, dyn, src_prefix, n_envs,
                      total_src_tiles);

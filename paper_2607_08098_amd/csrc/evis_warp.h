@@ -57,44 +57,59 @@ __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy
 // every side, so that every footprint corner of a source that lands in
 // [Tx0 - 1, Tx1 + 1) x [Ty0 - 1, Ty1 + 1) has a cell; apron cells (and
 // those of pixels outside the image) are written but never read.  Rows are
-// ZS(TW) = TW + 8 keys long: consecutive rows then start 64 bytes apart in
-// the banks, so the rows touched by one source tile's footprint spread.
+// ZS(TW) = TW + 4 keys long (TW a multiple of 16): consecutive rows start
+// 32 bytes further along the banks, so the four rows of a 4x4 block's
+// footprint fall in different banks.
 template <int TW>
-__device__ __forceinline__ constexpr int zrow() { return TW + 8; }
+__device__ __forceinline__ constexpr int zrow() { return TW + 4; }
 template <int TW, int TH>
 __device__ __forceinline__ constexpr int zcells() { return zrow<TW>() * (TH + 2); }
 // Cell of target pixel (lx, ly) of the tile (lx in [-1, TW], ly in [-1, TH]).
 template <int TW>
 __device__ __forceinline__ int zcell(int lx, int ly) { return (ly + 1) * zrow<TW>() + (lx + 1); }
 
-// Splat up to kChunk source tiles (one source per lane and tile) at fraction
-// f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].  The loads of
-// all tiles of the chunk are issued before any of them is used.
-constexpr int kChunk = 4;
+// Candidate-list entry of a 4x4 source block: bx << 23 | by << 14 | j_lo << 7
+// | j_hi (bx, by < 512; 1 <= j_lo <= j_hi <= 127), so 0 is never an entry
+// and marks an empty slot.
+__device__ __forceinline__ uint32_t cand_entry(int bx, int by, int jlo, int jhi) {
+  return ((uint32_t)bx << 23) | ((uint32_t)by << 14) | ((uint32_t)jlo << 7) | (uint32_t)jhi;
+}
+__device__ __forceinline__ int cand_bx(uint32_t e) { return (int)(e >> 23); }
+__device__ __forceinline__ int cand_by(uint32_t e) { return (int)((e >> 14) & 0x1FFu); }
+__device__ __forceinline__ int cand_jlo(uint32_t e) { return (int)((e >> 7) & 0x7Fu); }
+__device__ __forceinline__ int cand_jhi(uint32_t e) { return (int)(e & 0x7Fu); }
+
+// Splat kChunk slots of four source blocks each (lane group g = lane / 16
+// takes candidate entry blk[c] of slot c, one source per lane; 0 is empty)
+// at fraction f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].
+// The loads of all slots are issued before any of them is used.
+constexpr int kChunk = 3;
 
 template <int TW>
-__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const int (&st)[kChunk], int nb,
-                                            float f, int Tx0, int Tx1, int Ty0, int Ty1,
+__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&blk)[kChunk], float f,
+                                            int Tx0, int Tx1, int Ty0, int Ty1,
                                             unsigned long long* zbuf) {
-  const int lane = threadIdx.x & (kWave - 1);
+  const int r = threadIdx.x & (kBlkPx - 1);   // lane within the block: (r & 3, r >> 2)
   float4 rec[kChunk];   // (m_A.x, m_A.y, Z_A, Zend - Z_A)
-  int src[kChunk];      // source index, -1 outside the image or past nb
+  int src[kChunk];      // source index, -1 outside the image or for an empty slot
+  int sx[kChunk], sy[kChunk];
   // All loads first, unconditionally (a lane without a source reads record
   // 0), so that they are in flight together.
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
-    const int sxt = st[c] >> 8, syt = st[c] & 0xFF;   // wave-uniform
-    const int sx = sxt * kSrcTile + (lane & 7), sy = syt * kSrcTile + (lane >> 3);
-    const bool ok = (c < nb) && (sx < d.W) && (sy < d.H);
-    src[c] = ok ? sy * d.W + sx : -1;
-    rec[c] = ldg(d.src, ok ? src[c] : 0);
+    const uint32_t e = blk[c];
+    const int bx = cand_bx(e), by = cand_by(e);
+    sx[c] = bx * kSrcBlk + (r & 3);
+    sy[c] = by * kSrcBlk + (r >> 2);
+    const bool ok = e != 0u && sx[c] < d.W && sy[c] < d.H;
+    src[c] = ok ? sy[c] * d.W + sx[c] : -1;
+    rec[c] = ldg(d.src, ok ? (by * d.ntx_src + bx) * kBlkPx + r : 0);
   }
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
     if (src[c] < 0) continue;
-    const int sxt = st[c] >> 8, syt = st[c] & 0xFF;
-    const float qx = (float)(sxt * kSrcTile + (lane & 7)) - f * rec[c].x;
-    const float qy = (float)(syt * kSrcTile + (lane >> 3)) - f * rec[c].y;
+    const float qx = (float)sx[c] - f * rec[c].x;
+    const float qy = (float)sy[c] - f * rec[c].y;
     const float zt = rec[c].z + f * rec[c].w;
     if (!(zt > 0.0f)) continue;
     if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
@@ -151,17 +166,35 @@ __device__ __forceinline__ float b_value(const BTaps& t) {
   return lerp32(lerp32(t.a, t.b, t.wx), lerp32(t.c, t.d, t.wx), t.wy);
 }
 
-// Window of 8x8 source tiles that can reach a target tile: source tile
-// columns [wx0, wx0 + nwx), nwin tiles in all.
+// Window of 4x4 source blocks that can reach a target tile: block columns
+// [wx0, wx0 + nwx), nwin blocks in all.
 struct Window {
   int wx0, wy0, nwx, nwin;
 };
 
-// Candidate source tiles of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
+// Whether block (bx, by) can reach target tile [Tx0,Tx1]x[Ty0,Ty1], and during
+// which substeps.  A block whose positions over the whole gap (f in [0, 1])
+// stay clear of the tile by more than a pixel is rejected first, without
+// the divisions of substep_range (which rejects it too).
+__device__ __forceinline__ bool block_range(const EnvDesc& d, int bx, int by, int Tx0, int Tx1,
+                                            int Ty0, int Ty1, int K, int& jlo, int& jhi) {
+  const float4 b = ldg(d.tb, by * d.ntx_src + bx);
+  const int Sx0 = bx * kSrcBlk, Sx1 = min(bx * kSrcBlk + kSrcBlk - 1, d.W - 1);
+  const int Sy0 = by * kSrcBlk, Sy1 = min(by * kSrcBlk + kSrcBlk - 1, d.H - 1);
+  // q = p - f m over f in [0, 1] lies in [S0 - max(m_max, 0), S1 - min(m_min, 0)]
+  if ((float)Sx0 - fmaxf(b.y, 0.0f) >= (float)(Tx1 + 2) ||
+      (float)Sx1 - fminf(b.x, 0.0f) <= (float)(Tx0 - 2) ||
+      (float)Sy0 - fmaxf(b.w, 0.0f) >= (float)(Ty1 + 2) ||
+      (float)Sy1 - fminf(b.z, 0.0f) <= (float)(Ty0 - 2))
+    return false;
+  return substep_range(b, Sx0, Sx1, Sy0, Sy1, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi);
+}
+
+// Candidate source blocks of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
 // during which each can reach it, appended to the LDS list (at most cap
-// entries: x-tile << 24 | y-tile << 16 | j_lo << 8 | j_hi).  *count must be
-// zero on entry; returns the number of candidates (uniform; more than cap
-// means the list overflowed).  Holds a barrier.
+// entries, see cand_entry).  *count must be zero on entry; returns the
+// number of candidates (uniform; more than cap means the list overflowed).
+// Holds a barrier.
 __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& dy, int K,
                                                 int Tx0, int Tx1, int Ty0, int Ty1,
                                                 uint32_t* list, int* count, int cap, Window& w) {
@@ -169,22 +202,18 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
   const int W = d.W, H = d.H;
   const double M = __longlong_as_double((long long)dy.msq_bits);
   const int Rw = (M > 1.0e12) ? (1 << 20) : ((int)ceil(sqrt(M)) + 3);
-  w.wx0 = max(0, Tx0 - Rw) / kSrcTile;
-  w.wy0 = max(0, Ty0 - Rw) / kSrcTile;
-  const int wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, W - 1) / kSrcTile);
-  const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcTile);
+  w.wx0 = max(0, Tx0 - Rw) / kSrcBlk;
+  w.wy0 = max(0, Ty0 - Rw) / kSrcBlk;
+  const int wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, W - 1) / kSrcBlk);
+  const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcBlk);
   w.nwx = wx1 - w.wx0 + 1;
   w.nwin = w.nwx * (wy1 - w.wy0 + 1);
   for (int i = tid; i < w.nwin; i += kBlock) {
-    const int sxt = w.wx0 + i % w.nwx, syt = w.wy0 + i / w.nwx;
-    const int st = syt * d.ntx_src + sxt;
+    const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
     int jlo, jhi;
-    if (substep_range(ldg(d.tb, st), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
-                      syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1, K,
-                      jlo, jhi)) {
+    if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi)) {
       const int slot = atomicAdd(count, 1);
-      if (slot < cap)
-        list[slot] = ((uint32_t)sxt << 24) | ((uint32_t)syt << 16) | ((uint32_t)jlo << 8) | (uint32_t)jhi;
+      if (slot < cap) list[slot] = cand_entry(bx, by, jlo, jhi);
     }
   }
   __syncthreads();
@@ -193,56 +222,52 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
 
 // Splat every source that can reach the target tile at substep j (fraction
 // f): the active entries of the candidate list, or, if the list overflowed,
-// the active tiles of the whole window; each wave takes every fourth entry
-// and splats its active tiles in chunks.
+// the active blocks of the whole window.  Each wave takes every fourth
+// entry, packs its active entries into its 64-entry LDS slice `wl` and
+// splats them four blocks (one per lane group) per slot.
 template <int TW>
 __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_t* list, int nlist,
                                                  bool overflow, const Window& w, int K, int j,
                                                  float f, int Tx0, int Tx1, int Ty0, int Ty1,
-                                                 unsigned long long* zbuf) {
+                                                 uint32_t* wl, unsigned long long* zbuf) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int W = d.W, H = d.H;
+  const int g = lane >> 4;
   if (!overflow) {
     for (int base = 0; base < nlist; base += kBlock) {
       const int e2 = base + lane * kWavesPerBlock + wave;
       uint32_t ent = 0u;
       bool act = false;
       if (e2 < nlist) {
-        ent = list[e2];
-        const int jlo = (int)((ent >> 8) & 0xFFu), jhi = (int)(ent & 0xFFu);
-        act = (j >= jlo) && (j <= jhi);
+        ent = lds_ld(list, e2);
+        act = (j >= cand_jlo(ent)) && (j <= cand_jhi(ent));
       }
-      unsigned long long mask = __ballot(act);
-      while (mask) {
-        int st[kChunk];
-        int nb = 0;
+      const unsigned long long mask = __ballot(act);
+      const int nact = __popcll(mask);
+      if (act) lds_st(wl, __popcll(mask & ((1ull << lane) - 1ull)), ent);
+      for (int s0 = 0; s0 < nact; s0 += 4 * kChunk) {
+        uint32_t blk[kChunk];
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
-          st[c] = 0;
-          if (mask) {
-            const int b = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            st[c] = (int)((uint32_t)__builtin_amdgcn_readlane((int)ent, b) >> 16);   // sxt<<8 | syt
-            ++nb;
-          }
+          const int i = s0 + c * 4 + g;
+          blk[c] = (i < nact) ? lds_ld(wl, i) : 0u;
         }
-        splat_chunk<TW>(d, st, nb, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+        splat_chunk<TW>(d, blk, f, Tx0, Tx1, Ty0, Ty1, zbuf);
       }
     }
   } else {
-    // Window scan: the candidate list did not fit.
-    for (int i = wave; i < w.nwin; i += kWavesPerBlock) {
-      const int sxt = w.wx0 + i % w.nwx, syt = w.wy0 + i / w.nwx;
-      const int st0 = syt * d.ntx_src + sxt;
-      int jlo, jhi;
-      if (substep_range(ldg(d.tb, st0), sxt * kSrcTile, min(sxt * kSrcTile + 7, W - 1),
-                        syt * kSrcTile, min(syt * kSrcTile + 7, H - 1), Tx0, Tx1, Ty0, Ty1, K,
-                        jlo, jhi) &&
-          j >= jlo && j <= jhi) {
-        int st[kChunk] = {};
-        st[0] = (sxt << 8) | syt;
-        splat_chunk<TW>(d, st, 1, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+    // Window scan: the candidate list did not fit.  Four blocks per pass.
+    for (int i0 = wave * 4; i0 < w.nwin; i0 += 4 * kWavesPerBlock) {
+      const int i = i0 + g;
+      uint32_t blk[kChunk];
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) blk[c] = 0u;
+      if (i < w.nwin) {
+        const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
+        int jlo, jhi;
+        if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && j >= jlo && j <= jhi)
+          blk[0] = cand_entry(bx, by, jlo, jhi);
       }
+      splat_chunk<TW>(d, blk, f, Tx0, Tx1, Ty0, Ty1, zbuf);
     }
   }
 }

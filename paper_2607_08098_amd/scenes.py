@@ -222,3 +222,178 @@ def disc_pair(H: int, W: int, seed: int, step: int = 0, frame_rate: float = 60.0
 def frame_time_us(i: int, frame_rate: float = 60.0) -> int:
     """Keyframe i's timestamp in integer microseconds: round(i * 1e6 / rate)."""
     return int(round(i * 1e6 / frame_rate))
+
+
+# ---------------------------------------------------------------------------
+# Textured planes seen by a moving pinhole camera (exact flow and depth).
+# ---------------------------------------------------------------------------
+
+def _perlin_table(rng: np.random.Generator) -> np.ndarray:
+    p = rng.permutation(256).astype(np.int64)
+    return np.concatenate([p, p])
+
+
+def _perlin2(u: np.ndarray, v: np.ndarray, perm: np.ndarray) -> np.ndarray:
+    """2-D gradient noise after Perlin's improved noise (quintic fade, hashed
+    gradient directions); about [-1, 1]."""
+    fu, fv = np.floor(u), np.floor(v)
+    xi = fu.astype(np.int64) & 255
+    yi = fv.astype(np.int64) & 255
+    xf, yf = u - fu, v - fv
+    fade = lambda t: t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+    dirs = np.array([[1, 1], [-1, 1], [1, -1], [-1, -1], [1, 0], [-1, 0], [0, 1], [0, -1]], np.float64)
+
+    def grad(h, x, y):
+        g = dirs[h & 7]
+        return g[..., 0] * x + g[..., 1] * y
+
+    aa = perm[perm[xi] + yi]
+    ba = perm[perm[xi + 1] + yi]
+    ab = perm[perm[xi] + yi + 1]
+    bb = perm[perm[xi + 1] + yi + 1]
+    wu, wv = fade(xf), fade(yf)
+    x1 = grad(aa, xf, yf) + wu * (grad(ba, xf - 1.0, yf) - grad(aa, xf, yf))
+    x2 = grad(ab, xf, yf - 1.0) + wu * (grad(bb, xf - 1.0, yf - 1.0) - grad(ab, xf, yf - 1.0))
+    return x1 + wv * (x2 - x1)
+
+
+def _rodrigues(w: np.ndarray) -> np.ndarray:
+    th = float(np.linalg.norm(w))
+    if th < 1e-12:
+        return np.eye(3)
+    k = w / th
+    Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(th) * Kx + (1 - math.cos(th)) * (Kx @ Kx)
+
+
+class PlaneScene:
+    """Twelve textured planes (one background plane at 8 m plus 11 rectangles
+    at depth U[0.3, 8] m, normals within 30 degrees of the optical axis),
+    each with its own gradient-noise albedo in [0.05, 1] and irradiance
+    10^U[-3, 3] (six decades), seen by a pinhole camera (f = 500 px, centre
+    at the image middle) on a 6-DoF random walk (angular-velocity steps
+    N(0, 0.5^2) rad/s and linear-velocity steps N(0, 0.2^2) m/s per frame);
+    three of the rectangles also move rigidly on random walks of their own.
+    Depth is the camera-space z of the first hit; motion vectors project
+    the same material point at the other keyframe exactly."""
+
+    def __init__(self, H: int, W: int, seed: int, n_frames: int, frame_rate: float = 60.0,
+                 focal: float = 500.0):
+        rng = rng_for(seed)
+        self.H, self.W, self.f = H, W, focal
+        self.cx, self.cy = (W - 1) / 2.0, (H - 1) / 2.0
+        self.frame_rate = frame_rate
+        dt = 1.0 / frame_rate
+        planes = []
+        for i in range(12):
+            if i == 0:
+                c, n, half = np.array([0.0, 0.0, 8.0]), np.array([0.0, 0.0, -1.0]), (1e9, 1e9)
+            else:
+                z = rng.uniform(0.3, 8.0)
+                x = rng.uniform(-0.5, 0.5) * z * W / focal
+                y = rng.uniform(-0.5, 0.5) * z * H / focal
+                c = np.array([x, y, z])
+                tilt = math.radians(rng.uniform(0.0, 30.0))
+                az = rng.uniform(0.0, 2.0 * math.pi)
+                n = np.array([math.sin(tilt) * math.cos(az), math.sin(tilt) * math.sin(az), -math.cos(tilt)])
+                s = z * min(H, W) / focal
+                half = (rng.uniform(0.1, 0.4) * s, rng.uniform(0.1, 0.4) * s)
+            u = np.cross(n, [0.0, 1.0, 0.0])
+            u /= np.linalg.norm(u)
+            v = np.cross(n, u)
+            planes.append(dict(c=c, R=np.stack([u, v, n], axis=1), half=half,
+                               perm=_perlin_table(rng), freq=rng.uniform(4.0, 12.0),
+                               irr=10.0 ** rng.uniform(-3.0, 3.0), moving=i in (1, 2, 3)))
+        self.planes = planes
+        # poses per frame: camera (R, o) and the moving planes (R, c)
+        Rc, oc = np.eye(3), np.zeros(3)
+        wc, vc = np.zeros(3), np.zeros(3)
+        self.cam = []
+        pl_state = {i: (planes[i]["R"].copy(), planes[i]["c"].copy(), np.zeros(3), np.zeros(3))
+                    for i in range(12) if planes[i]["moving"]}
+        self.pl_pose = []
+        for k in range(n_frames + 1):
+            self.cam.append((Rc.copy(), oc.copy()))
+            self.pl_pose.append({i: (s[0].copy(), s[1].copy()) for i, s in pl_state.items()})
+            wc = wc + rng.normal(0.0, 0.5, 3)
+            vc = vc + rng.normal(0.0, 0.2, 3)
+            Rc = Rc @ _rodrigues(wc * dt)
+            oc = oc + Rc @ (vc * dt)
+            for i, (Rp, cp, wp, vp) in list(pl_state.items()):
+                wp = wp + rng.normal(0.0, 0.5, 3)
+                vp = vp + rng.normal(0.0, 0.2, 3)
+                pl_state[i] = (_rodrigues(wp * dt) @ Rp, cp + vp * dt, wp, vp)
+
+    def _plane_pose(self, i: int, k: int):
+        p = self.planes[i]
+        if p["moving"]:
+            return self.pl_pose[k][i]
+        return p["R"], p["c"]
+
+    def _hit(self, k: int):
+        """First hit per pixel at frame k: plane index, local (u, v), depth."""
+        H, W = self.H, self.W
+        yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+        d_cam = np.stack([(xx - self.cx) / self.f, (yy - self.cy) / self.f, np.ones_like(xx)], -1)
+        Rc, oc = self.cam[k]
+        d = d_cam @ Rc.T
+        best = np.full((H, W), np.inf)
+        idx = np.zeros((H, W), np.int64)
+        uu = np.zeros((H, W))
+        vv = np.zeros((H, W))
+        for i, p in enumerate(self.planes):
+            Rp, cp = self._plane_pose(i, k)
+            n = Rp[:, 2]
+            den = d @ n
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t = ((cp - oc) @ n) / den
+            X = oc + t[..., None] * d
+            lu = (X - cp) @ Rp[:, 0]
+            lv = (X - cp) @ Rp[:, 1]
+            ok = (t > 1e-3) & (np.abs(lu) <= p["half"][0]) & (np.abs(lv) <= p["half"][1]) & (t < best)
+            best = np.where(ok, t, best)
+            idx = np.where(ok, i, idx)
+            uu = np.where(ok, lu, uu)
+            vv = np.where(ok, lv, vv)
+        return idx, uu, vv, best
+
+    def _project(self, i, uu, vv, k):
+        """Pixel position at frame k of material point (u, v) of plane i."""
+        Rp, cp = self._plane_pose(i, k)
+        X = cp + uu[..., None] * Rp[:, 0] + vv[..., None] * Rp[:, 1]
+        Rc, oc = self.cam[k]
+        Xc = (X - oc) @ Rc
+        z = np.maximum(Xc[..., 2], 1e-3)
+        return self.f * Xc[..., 0] / z + self.cx, self.f * Xc[..., 1] / z + self.cy
+
+    def frame(self, k: int, other: int):
+        """Radiance, motion vectors towards keyframe `other` and depth of frame k.
+
+        With other = k + 1 the field is A's m_A(p) = p - p_B; with
+        other = k - 1 it is B's backward m_B(p) = p_A - p.
+        """
+        idx, uu, vv, Z = self._hit(k)
+        img = np.zeros((self.H, self.W))
+        px = np.zeros((self.H, self.W))
+        py = np.zeros((self.H, self.W))
+        for i, p in enumerate(self.planes):
+            sel = idx == i
+            if not sel.any():
+                continue
+            n = _perlin2(uu[sel] * p["freq"], vv[sel] * p["freq"], p["perm"])
+            alb = np.clip(0.525 + 0.475 * n, 0.05, 1.0)
+            img[sel] = alb * p["irr"]
+            qx, qy = self._project(i, uu[sel], vv[sel], other)
+            px[sel], py[sel] = qx, qy
+        yy, xx = np.mgrid[0:self.H, 0:self.W].astype(np.float64)
+        if other > k:
+            m = np.stack([xx - px, yy - py], -1)
+        else:
+            m = np.stack([px - xx, py - yy], -1)
+        return img.astype(F32), m.astype(F32), np.where(np.isfinite(Z), Z, 8.0).astype(F32)
+
+    def pair(self, k: int) -> dict:
+        """Keyframes k (A) and k + 1 (B)."""
+        I_A, m_A, Z_A = self.frame(k, k + 1)
+        I_B, m_B, Z_B = self.frame(k + 1, k)
+        return dict(H=self.H, W=self.W, I_A=I_A, I_B=I_B, m_A=m_A, m_B=m_B, Z_A=Z_A, Z_B=Z_B)

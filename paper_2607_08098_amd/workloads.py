@@ -9,6 +9,7 @@ used by tests so both sides see the same numbers) or from the library's own
 """
 from __future__ import annotations
 
+import math
 from typing import Callable, List, Optional, Sequence, Tuple
 
 import numpy as np
@@ -92,3 +93,82 @@ def mixed_batch(ctx: evis.Context, seed_base: int = 3000, device="cuda",
         H, W = b.shapes[e]
         evis.evis_state_init(ctx, b.view(b.L_A, e), b.view(b.L_ref, e))
     return b
+
+
+class DiscBatch(Batch):
+    """n copies of the rotating-disc scene (``scenes.disc_scene_params``, one
+    seed per env) at one resolution, advanced frame by frame on the device.
+
+    Motion vectors and depth of this scene do not change over time; only
+    the radiance does (the sector pattern turns), so each step generates
+    the next keyframe's radiance with torch on the device and takes its log
+    intensity with the library's own front end.  Frame i is at i / 60 s.
+    """
+
+    def __init__(self, ctx: evis.Context, n_envs: int = 512, H: int = 260, W: int = 346,
+                 seed_base: int = 4000, device="cuda", frame_rate: float = 60.0):
+        super().__init__([(H, W)] * n_envs, device)
+        self.ctx = ctx
+        self.frame_rate = frame_rate
+        self.H, self.W, self.n = H, W, n_envs
+        f64 = dict(dtype=torch.float64, device=device)
+        albedo, omega, phase, bg = [], [], [], []
+        for e in range(n_envs):
+            p = scenes.disc_scene_params(H, W, seed_base + e)
+            albedo.append(p["albedo"])
+            omega.append(p["omega"])
+            phase.append(p["phase"])
+            bg.append(p["bg"])
+        self.omega = [float(w) for w in omega]
+        self.albedo = torch.tensor(np.stack(albedo), **f64)             # [n, 8]
+        self.w = torch.tensor(omega, **f64).view(n_envs, 1, 1)
+        self.phase = torch.tensor(phase, **f64).view(n_envs, 1, 1)
+        self.bg = torch.tensor(np.stack(bg), **f64)                      # [n, H, W]
+        yy, xx = torch.meshgrid(torch.arange(H, **f64), torch.arange(W, **f64), indexing="ij")
+        rx, ry = xx - (W - 1) / 2.0, yy - (H - 1) / 2.0
+        rad = 0.6 * min(H, W) / 2.0
+        self.inside = (rx * rx + ry * ry <= rad * rad)
+        self.ang0 = torch.atan2(ry, rx)
+        # static motion (the backward rotation of one frame) and depth, per env
+        for e in range(n_envs):
+            _, m, Z = scenes.disc_frame(H, W, dict(albedo=albedo[e], omega=omega[e], phase=phase[e],
+                                                   bg=bg[e]), 0.0, frame_rate)
+            mt = torch.from_numpy(np.ascontiguousarray(m))
+            zt = torch.from_numpy(np.ascontiguousarray(Z))
+            self.view(self.m_A, e).copy_(mt)
+            self.view(self.m_B, e).copy_(mt)
+            self.view(self.Z_A, e).copy_(zt)
+            self.view(self.Z_B, e).copy_(zt)
+        self.frame = -1
+
+    def radiance(self, i: int, out: torch.Tensor) -> None:
+        """Linear radiance of every env at frame i into out [n * H * W]."""
+        t = i / self.frame_rate
+        ang = self.ang0.unsqueeze(0) - (self.phase + self.w * t)
+        two_pi = 2.0 * math.pi
+        sector = torch.floor(torch.remainder(ang, two_pi) / (two_pi / 8.0)).long() % 8
+        a = torch.gather(self.albedo, 1, sector.view(self.n, -1)).view(self.n, self.H, self.W)
+        img = torch.where(self.inside.unsqueeze(0), a, self.bg) * 100.0
+        out.view(self.n, self.H, self.W).copy_(img.to(torch.float32))
+
+    def start(self, i: int = 0) -> None:
+        """Keyframes i, i + 1 as L_A, L_B; L_ref = L_A; no refractory state."""
+        self.radiance(i, self.I_A)
+        self.radiance(i + 1, self.I_B)
+        evis.evis_log_luminance(self.ctx, self.I_A, 1e-3, out=self.L_A)
+        evis.evis_log_luminance(self.ctx, self.I_B, 1e-3, out=self.L_B)
+        for e in range(self.n):
+            evis.evis_state_init(self.ctx, self.view(self.L_A, e), self.view(self.L_ref, e))
+        self.frame = i
+
+    def advance(self) -> None:
+        """Move one keyframe on: L_A <- L_B, L_B <- log of the next frame
+        (buffers keep their addresses, so descriptors stay the same)."""
+        self.frame += 1
+        self.L_A.copy_(self.L_B)
+        self.radiance(self.frame + 1, self.I_B)
+        evis.evis_log_luminance(self.ctx, self.I_B, 1e-3, out=self.L_B)
+
+    def times(self) -> Tuple[int, int]:
+        return scenes.frame_time_us(self.frame, self.frame_rate), \
+            scenes.frame_time_us(self.frame + 1, self.frame_rate)

@@ -3,9 +3,10 @@
 // that is appended to the global event stream with one atomic per flush.
 //
 // Emission takes no barrier: each wave reserves its slots in the LDS buffer
-// with a compare-and-swap on the buffer's count (or, if they do not fit,
-// writes straight to the stream after one global atomic) and raises a flush
-// request once the buffer is three quarters full.  Requests are read after
+// with one atomic add on the buffer's count; slots past the end of the
+// buffer go straight to the stream after one global atomic (the count may
+// then exceed the buffer, whose every slot is still filled); the wave
+// raises a flush request once the buffer is three quarters full.  Requests are read after
 // the next workgroup barrier, where every wave sees the same value: round r
 // writes request slot r & 1 and round r + 2 cannot start before the barrier
 // that follows round r + 1, by which time every wave has read slot r & 1.
@@ -49,7 +50,7 @@ __device__ __forceinline__ void sink_init(const SinkShared& sh) {
 // after a barrier that follows the last emission.
 __device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& so) {
   const int tid = threadIdx.x;
-  const int n = lds_ld(sh.cnt, 0);   // stable: no wave emits until the closing barrier
+  const int n = min(lds_ld(sh.cnt, 0), sh.cap);   // stable: no wave emits until the closing barrier
   if (n == 0) return;      // workgroup-uniform
   __syncthreads();         // every wave has read cnt
   if (tid == 0) *sh.gbase = atomicAdd(so.cursor, (unsigned long long)n);
@@ -168,34 +169,24 @@ __device__ __forceinline__ void emit_substep(
   ++sr.round;
   sr.unchecked = true;
   if (wtot > 0) {   // wave-uniform
-    int lb = -1;
-    if (lane == kWave - 1) {
-      int cur = __atomic_load_n(sh.cnt, __ATOMIC_RELAXED);
-      while (cur + wtot <= sh.cap) {
-        const int prev = atomicCAS(sh.cnt, cur, cur + wtot);
-        if (prev == cur) {
-          lb = cur;
-          break;
-        }
-        cur = prev;
-      }
-    }
+    int lb = 0;
+    if (lane == kWave - 1) lb = atomicAdd(sh.cnt, wtot);
     lb = __builtin_amdgcn_readlane(lb, kWave - 1);
-    const bool to_global = lb < 0;
+    // slots [0, n_lds) of the wave go to the buffer, the rest to the stream
+    const int n_lds = max(0, min(wtot, sh.cap - lb));
     unsigned long long gbase_w = 0;
-    if (to_global) {
+    if (n_lds < wtot) {   // wave-uniform
       unsigned long long g = 0;
-      if (lane == kWave - 1) g = atomicAdd(so.cursor, (unsigned long long)wtot);
+      if (lane == kWave - 1) g = atomicAdd(so.cursor, (unsigned long long)(wtot - n_lds));
       gbase_w = __shfl(g, kWave - 1, kWave);
     }
-    if (lane == kWave - 1 && (to_global || lb + wtot > sh.cap - sh.cap / 4)) lds_st(sh.req, slot_req, 1);
-    const int lbase_w = to_global ? 0 : lb;
+    if (lane == kWave - 1 && lb + wtot > sh.cap - sh.cap / 4) lds_st(sh.req, slot_req, 1);
     auto put = [&](int slot, uint32_t word, int t) {
-      if (to_global) {
-        const unsigned long long idx = gbase_w + (unsigned long long)slot;
-        if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
+      if (slot < n_lds) {
+        lds_st(sh.buf, lb + slot, make_uint2(word, (uint32_t)t));
       } else {
-        lds_st(sh.buf, lbase_w + slot, make_uint2(word, (uint32_t)t));
+        const unsigned long long idx = gbase_w + (unsigned long long)(slot - n_lds);
+        if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
       }
     };
     if (refr == 0) {

@@ -18,21 +18,26 @@ namespace evis {
 // into the target tile [Tx0,Tx1]x[Ty0,Ty1].  A corner lies in [Tx0,Tx1]
 // only if q_x = p_x - f m_x is in [Tx0 - 1, Tx1 + 1); over the tile q_x lies
 // in [Sx0 - f max m_x, Sx1 - f min m_x].
+// bnd / a by the hardware reciprocal (relative error a few ulp)
+__device__ __forceinline__ float fast_div(float bnd, float a) {
+  return bnd * __builtin_amdgcn_rcpf(a);
+}
 __device__ __forceinline__ void lin_le(float a, float bnd, float& flo, float& fhi) {
-  if (a > 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));        // a f <= bnd
-  else if (a < 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));
+  if (a > 0.0f) fhi = fminf(fhi, fast_div(bnd, a));        // a f <= bnd
+  else if (a < 0.0f) flo = fmaxf(flo, fast_div(bnd, a));
   else if (bnd < 0.0f) flo = 2.0f;
 }
 __device__ __forceinline__ void lin_ge(float a, float bnd, float& flo, float& fhi) {
-  if (a > 0.0f) flo = fmaxf(flo, __fdividef(bnd, a));        // a f >= bnd
-  else if (a < 0.0f) fhi = fminf(fhi, __fdividef(bnd, a));
+  if (a > 0.0f) flo = fmaxf(flo, fast_div(bnd, a));        // a f >= bnd
+  else if (a < 0.0f) fhi = fminf(fhi, fast_div(bnd, a));
   else if (bnd > 0.0f) flo = 2.0f;
 }
 
 // The footprint test is conservative by 1/64 px (far above the rounding of
 // q = p - f m for |q| < 4096 and |m| < 2^20) and the substep bounds by
-// 1/256 of a substep (above the error of the fast division), so no source
-// that can land in the tile at substep j is ever left out.
+// 1/256 of a substep (far above K = 128 times the few-ulp error of the
+// reciprocal division for fractions in [0, 1]), so no source that can land
+// in the tile at substep j is ever left out.
 __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy0, int Sy1,
                                               int Tx0, int Tx1, int Ty0, int Ty1, int K,
                                               int& jlo, int& jhi) {

@@ -169,7 +169,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(environments shard by env across GPUs by design; see DESIGN.md)", file=sys.stderr)
+              "(environments are independent and would shard by env across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -124,7 +124,7 @@ void evis_destroy(evis_ctx *ctx);
 const char *evis_last_error(const evis_ctx *ctx);
 int evis_abi_version(void);
 
-/* a1 -- Eq. 3 Rec.709 luminance and the log intensity below it:
+/* Log intensity -- Eq. 3 Rec.709 luminance and the log intensity below it:
  * L = ln(Y + eps).  x is [n] luminance (channels == 1) or [n][3] linear RGB
  * (channels == 3); L_out is [n].  float32 arithmetic with the library's own
  * logarithm.  eps > 0. */
@@ -136,14 +136,14 @@ int evis_log_luminance(evis_ctx *ctx, const float *x, int32_t channels, int64_t 
 int evis_state_init(evis_ctx *ctx, const float *L_first, int32_t H, int32_t W,
                     const evis_state *state, void *stream);
 
-/* a2 -- substep count of one pair: the smallest K >= 1 with K^2 >= the
+/* Substep count of one pair: the smallest K >= 1 with K^2 >= the
  * largest finite |m|^2 over m_A and m_B (float64), at most K_max; so no
  * motion vector moves a pixel by more than one pixel per substep.
  * K_out is a device int32. */
 int evis_substep_count(evis_ctx *ctx, const evis_pair *pair, int32_t K_max, int32_t *K_out,
                        void *stream);
 
-/* a3-a5 -- intermediate log frames j in [j_begin, j_end) of K (0 <= j_begin <
+/* Sub-frames -- intermediate log frames j in [j_begin, j_end) of K (0 <= j_begin <
  * j_end <= K + 1, 1 <= K <= EVIS_MAX_K).  j = 0 and j = K return L_A and
  * L_B verbatim.  For 0 < j < K, f = j/K: keyframe A is splatted forward to
  * q = p - f m_A(p) over the bilinear footprint (corners with positive
@@ -159,7 +159,7 @@ int evis_interpolate(evis_ctx *ctx, const evis_pair *pair, int32_t K, int32_t j_
                      int32_t j_end, int32_t blend_mode, float *L_out, uint8_t *hole_mask,
                      void *stream);
 
-/* a6-a7 -- events from caller-supplied log frames L_seq[0..K] ([K+1][H*W];
+/* Events from caller-supplied log frames L_seq[0..K] ([K+1][H*W];
  * L_seq[0] is the previous sample, events come from j = 1..K) between
  * t0_us and t1_us.  Per pixel and substep j: d = L_j - L_ref, polarity
  * sgn d, threshold c = theta_on/C_on or theta_off/C_off, n = floor(|d|/c)
@@ -173,7 +173,7 @@ int evis_generate_events(evis_ctx *ctx, const float *L_seq, int32_t H, int32_t W
                          const evis_state *state, int32_t env_id, evis_event *out,
                          int64_t capacity, int64_t *n_total, int32_t flags, void *stream);
 
-/* a1-a8 fused -- one keyframe pair for each of n_envs environments
+/* Fused step -- one keyframe pair for each of n_envs environments
  * (1..EVIS_MAX_ENVS; envs is a HOST array of descriptors) in one
  * persistent launch: substep count, sub-frames and events of every env,
  * all events appended to one stream.  K_used (device [n_envs], nullable)

@@ -8,23 +8,23 @@ nothing from them.
 Paper: "EVIS: Real-Time Event Camera Simulation with Multimodal Supervision
 in NVIDIA Isaac Sim".  Steps, in the paper's order:
 
-  a1  log_luminance          Sec. "HDR Event Formation Model", Eq. 3 and the
-                             log-intensity definition that follows it
-  a2  adaptive_k             Sec. "Bidirectional Motion Vector Warping": K-1
-                             intermediate frames per keyframe gap, K chosen so
-                             that no pixel moves more than one px per substep
-  a3  endpoint_depth         Eq. 7, depth at the B-side endpoint of A's motion
-  a4  splat_forward          Eq. 5 (q_A), the bilinear footprint, Eq. 6 z-buffer,
-                             Eq. 7 intermediate depth
-  a5  resolve_gather_blend   Eq. 5 (q_B) evaluated as a backward gather, the
-                             hole-aware blend of A and B
-  a6  emit_events            Eq. 4 (crossing count, polarity, residual-keeping
-                             reference update), Eq. 8 threshold mismatch, the
-                             refractory period of Sec. "Sensor Calibration and
-                             Non-idealities"
-  a7  pack_events            the (x, y, t, p) event tuple of Sec. "Problem
-                             Formulation" as an 8-byte record
-      step / interpolate     the whole per-pair path
+  log_luminance          Sec. "HDR Event Formation Model", Eq. 3 and the
+                         log-intensity definition that follows it
+  adaptive_k             Sec. "Bidirectional Motion Vector Warping": K-1
+                         intermediate frames per keyframe gap, K chosen so
+                         that no pixel moves more than one px per substep
+  endpoint_depth         Eq. 7, depth at the B-side endpoint of A's motion
+  splat_forward          Eq. 5 (q_A), the bilinear footprint, Eq. 6 z-buffer,
+                         Eq. 7 intermediate depth
+  resolve_gather_blend   Eq. 5 (q_B) evaluated as a backward gather, the
+                         hole-aware blend of A and B
+  emit_events            Eq. 4 (crossing count, polarity, residual-keeping
+                         reference update), Eq. 8 threshold mismatch, the
+                         refractory period of Sec. "Sensor Calibration and
+                         Non-idealities"
+  pack_events            the (x, y, t, p) event tuple of Sec. "Problem
+                         Formulation" as an 8-byte record
+  step / interpolate     the whole per-pair path
 
 Precision.  Everything from the log intensity onwards is float32, every
 operation rounded to nearest in the order written: numpy float32 ufuncs and
@@ -32,7 +32,7 @@ float32 scalars do exactly that and never fuse a multiply with an add.  The
 splat winner, the footprint corners and the crossing count are discrete
 decisions taken on those float32 values; the crossing count is the exact
 floor of the real quotient of the two float32 numbers (``fractions``).
-a1 is the one float64 step: it holds a transcendental and sits upstream of
+The log intensity is the one float64 step: it holds a transcendental and sits upstream of
 the exact part, so it is compared within a tolerance.
 
 Readings of the paper taken here (each is restated where it is used):
@@ -113,7 +113,7 @@ def clamp_into(v: np.ndarray, hi: int) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# a1: log luminance (float64)
+# log luminance (float64)
 # ---------------------------------------------------------------------------
 
 def log_luminance(x, eps: float = 1e-3) -> np.ndarray:
@@ -128,7 +128,7 @@ def log_luminance(x, eps: float = 1e-3) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# a2: adaptive substep count
+# adaptive substep count
 # ---------------------------------------------------------------------------
 
 def adaptive_k(m_A: np.ndarray, m_B: np.ndarray, K_max: int) -> int:
@@ -154,7 +154,7 @@ def adaptive_k(m_A: np.ndarray, m_B: np.ndarray, K_max: int) -> int:
 
 
 # ---------------------------------------------------------------------------
-# a3: endpoint depth (Eq. 7)
+# endpoint depth (Eq. 7)
 # ---------------------------------------------------------------------------
 
 def endpoint_depth(Z_B: np.ndarray, m_A: np.ndarray) -> np.ndarray:
@@ -167,7 +167,7 @@ def endpoint_depth(Z_B: np.ndarray, m_A: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# a4: forward depth-tested splat of A (Eq. 5, Eq. 6, Eq. 7)
+# forward depth-tested splat of A (Eq. 5, Eq. 6, Eq. 7)
 # ---------------------------------------------------------------------------
 
 def substep_fraction(j: int, K: int):
@@ -220,7 +220,7 @@ def splat_forward(m_A, Z_A, Zend, f) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# a5: resolve, backward gather of B, hole-aware blend
+# resolve, backward gather of B, hole-aware blend
 # ---------------------------------------------------------------------------
 
 def resolve_gather_blend(zbuf, L_A, L_B, m_B, f, alpha):
@@ -299,7 +299,7 @@ def interpolate(pair: Pair, K: int, j_begin: int, j_end: int, blend_mode: int = 
 
 
 # ---------------------------------------------------------------------------
-# a6: event emission (Eq. 4, Eq. 8, refractory period)
+# event emission (Eq. 4, Eq. 8, refractory period)
 # ---------------------------------------------------------------------------
 
 @dataclass
@@ -427,7 +427,7 @@ def choose_k(pair: Pair, sensor: Sensor) -> int:
 
 
 def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0):
-    """One keyframe pair: K, sub-frames (a3-a5) and events (a6), streaming
+    """One keyframe pair: K, sub-frames (splat, gather, blend) and events, streaming
     over j.  Returns (events[N,5], L_ref', t_last', K)."""
     K = choose_k(pair, sensor)
     H, W = pair.shape
@@ -447,7 +447,7 @@ def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0):
 
 
 # ---------------------------------------------------------------------------
-# a7: event record
+# event record
 # ---------------------------------------------------------------------------
 
 def pack_events(ev: np.ndarray) -> np.ndarray:

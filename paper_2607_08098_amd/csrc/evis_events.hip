@@ -5,7 +5,7 @@
 
 namespace evis {
 
-// a1: Eq. 3 luminance, then ln(Y + eps).
+// Log intensity: Eq. 3 luminance, then ln(Y + eps).
 __global__ __launch_bounds__(kBlock) void k_log_luminance(const float* __restrict__ x, int channels,
                                                           long long n, float eps,
                                                           float* __restrict__ L) {
@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kBlock) void k_state_init(const float* __restrict__
   }
 }
 
-// a2 for one pair: largest finite |m|^2 (float64) over both fields.
+// Substep count of one pair: largest finite |m|^2 (float64) over both fields.
 __global__ __launch_bounds__(kBlock) void k_msq(const float2* __restrict__ mA,
                                                 const float2* __restrict__ mB, long long n,
                                                 unsigned long long* msq_bits) {
@@ -59,7 +59,7 @@ __global__ void k_zero_u64(unsigned long long* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
 }
 
-// a6-a7 over materialised frames: PPT pixels per thread, consecutive pixels
+// Events over materialised frames: PPT pixels per thread, consecutive pixels
 // across the workgroup, one pass over the K+1 frames with the state in
 // registers and the next frame's values loaded ahead.
 struct EventArgs {

@@ -11,7 +11,7 @@ F32 = np.float32
 
 
 def log_frames(scene: dict):
-    """Log intensity of both keyframes (the oracle's float64 a1, stored as
+    """Log intensity of both keyframes (the oracle's float64 log intensity, stored as
     float32): the common input of both sides."""
     return (o.log_luminance(scene["I_A"]).astype(F32), o.log_luminance(scene["I_B"]).astype(F32))
 

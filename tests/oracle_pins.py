@@ -47,7 +47,7 @@ def read_golden(name):
 
 
 # ---------------------------------------------------------------------------
-# a1
+# log intensity
 # ---------------------------------------------------------------------------
 
 def pin_log_luminance(o):
@@ -66,7 +66,7 @@ def pin_log_luminance(o):
 
 
 # ---------------------------------------------------------------------------
-# a2
+# substep count
 # ---------------------------------------------------------------------------
 
 def _field(H, W, vec=None):
@@ -101,7 +101,7 @@ def pin_adaptive_k(o):
 
 
 # ---------------------------------------------------------------------------
-# a3
+# endpoint depth
 # ---------------------------------------------------------------------------
 
 def pin_endpoint_depth_affine(o):
@@ -119,7 +119,7 @@ def pin_endpoint_depth_affine(o):
 
 
 # ---------------------------------------------------------------------------
-# a4
+# forward splat
 # ---------------------------------------------------------------------------
 
 def pin_splat_bruteforce(o):
@@ -276,7 +276,7 @@ def pin_tie_break(o):
 
 
 # ---------------------------------------------------------------------------
-# a5
+# resolve, gather, blend
 # ---------------------------------------------------------------------------
 
 def pin_gather_affine(o):
@@ -324,7 +324,7 @@ def pin_blend_modes(o):
 
 
 # ---------------------------------------------------------------------------
-# a6
+# event emission
 # ---------------------------------------------------------------------------
 
 def pin_goldens(o):
@@ -467,7 +467,7 @@ def pin_crossing_count_exact(o):
 
 
 # ---------------------------------------------------------------------------
-# a7
+# event record
 # ---------------------------------------------------------------------------
 
 def pin_event_record(o):

@@ -51,7 +51,7 @@ def check_interp(got_L, got_h, want_L, want_h, tag):
 
 
 # ---------------------------------------------------------------------------
-# interpolation (a3-a5)
+# interpolation (splat, gather, blend)
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mode", [o.BLEND_TIME, o.BLEND_B_PRIMARY])
@@ -112,7 +112,7 @@ def test_interpolate_occlusion_and_invalid_depth(torch, ctx):
 
 
 # ---------------------------------------------------------------------------
-# emission on caller-supplied frames (a6-a7)
+# emission on caller-supplied frames
 # ---------------------------------------------------------------------------
 
 def gen_events(torch, ctx, L_seq, t0, t1, sensor, L_ref, t_last, env_id=0, capacity=None):
@@ -193,7 +193,7 @@ def test_generate_events_capacity_overflow(torch, ctx):
 
 
 # ---------------------------------------------------------------------------
-# fused step (a2-a8)
+# fused step
 # ---------------------------------------------------------------------------
 
 def run_step(torch, ctx, pairs, sensors, L_refs, t_lasts, env_ids, capacity=8 * 1024 * 1024):
@@ -247,7 +247,7 @@ def test_step_config1(torch, ctx):
     pair = U.oracle_pair(U.blob_scene(128, 128, 1000))
     s = o.Sensor(C_on=0.2, C_off=0.2, K=8)
     args = ([pair], [s], [pair.L_A.copy()], [None], [0])
-    say("step_batch config-1 128x128 K=8")
+    say("step_batch 128x128 blob scene K=8")
     got = run_step(torch, ctx, *args)
     check_step(got, oracle_steps(*args))
     assert got[1] > 1000

@@ -39,7 +39,7 @@ struct evis_ctx {
   // device scratch
   DevBuf meta;        // EnvDesc[n] followed by int32 src_prefix[n + 1]
   DevBuf dyn;         // EnvDyn[n]
-  DevBuf sched;       // xbegin[8][n + 1], env_order[n], n_items[8], queue counters[8]
+  DevBuf sched;       // xbegin[8][n + 1], env_order[n], n_items[8], queue counters (256 B apart)
   DevBuf src;         // float4[16 per 4x4 source block]: per-source splat records
   DevBuf tb;          // float4[per 4x4 source block]: motion bounds
   DevBuf msq;         // one u64 for evis_substep_count
@@ -262,7 +262,10 @@ EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st
   return d;
 }
 
-size_t sched_ints(int n) { return (size_t)kXcd * (n + 1) + n + 2 * kXcd; }
+// xbegin, env_order and n_items, then the queue counters from a 256-byte
+// boundary, one per 256 bytes
+size_t sched_head_ints(int n) { return ((size_t)kXcd * (n + 1) + n + kXcd + kQueueStride - 1) / kQueueStride * kQueueStride; }
+size_t sched_ints(int n) { return sched_head_ints(n) + (size_t)kXcd * kQueueStride; }
 
 struct Plan {
   std::vector<EnvDesc> desc;
@@ -332,7 +335,7 @@ Sched sched_ptrs(evis_ctx* ctx, int n) {
   s.xbegin = base;                               // kXcd * (n + 1)
   s.env_order = base + kXcd * (n + 1);           // n
   s.n_items = s.env_order + n;                   // kXcd
-  s.queue = reinterpret_cast<unsigned int*>(s.n_items + kXcd);   // kXcd
+  s.queue = reinterpret_cast<unsigned int*>(base + sched_head_ints(n));   // kXcd * kQueueStride
   return s;
 }
 

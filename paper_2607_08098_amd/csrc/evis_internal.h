@@ -15,6 +15,7 @@ enum Mode { MODE_STEP = 0, MODE_INTERP = 1, MODE_SOFT_FWD = 2, MODE_SOFT_BWD = 3
 constexpr int kListCapMax = 1024;   // per-tile candidate source tiles held in LDS
 constexpr int kEventBuf = 2048;     // events staged in LDS per workgroup
 constexpr int kXcd = 8;             // work queues: one per accelerator complex die
+constexpr int kQueueStride = 64;    // queue counters 256 bytes apart (own cache lines)
 
 // Arguments of the fused tile kernel (all device pointers).
 struct TileArgs {
@@ -24,7 +25,8 @@ struct TileArgs {
   const int32_t* env_order;    // [n_envs] env index of each rank
   int32_t n_envs;
   int32_t list_cap;
-  unsigned int* queue;         // [kXcd] work-queue counters (zeroed before the launch)
+  unsigned int* queue;         // [kXcd * kQueueStride] work-queue counters, counter x at
+                               // x * kQueueStride (zeroed before the launch)
   const int32_t* n_items;      // [kXcd] items of each queue
   int32_t static_tiles;
   // MODE_STEP

@@ -33,7 +33,7 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
                         unsigned long long* cursor) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_envs) dyn[i].msq_bits = 0ull;
-  if (i < kXcd) queue[i] = 0u;
+  if (i < kXcd) queue[i * kQueueStride] = 0u;
   if (i == 0 && cursor) *cursor = 0ull;
 }
 
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       int item = -1, r = 0, q = -1;
       while (qsel < kXcd) {
         const int qq = (home + qsel) % kXcd;
-        const int it = (int)atomicAdd(&a.queue[qq], 1u);
+        const int it = (int)atomicAdd(&a.queue[qq * kQueueStride], 1u);
         if (it < a.n_items[qq]) {
           item = it;
           q = qq;

@@ -47,27 +47,30 @@ __device__ __forceinline__ void sink_init(const SinkShared& sh) {
 }
 
 // Append the staged events to the stream.  Every thread calls it, right
-// after a barrier that follows the last emission.
+// after a barrier that follows the last emission, and no wave emits until
+// it returns.  Thread 0 alone reads and resets the count (and hands the
+// number over with the global slot); the flush requests, which every wave
+// reads before calling, are cleared only after the second barrier.
 __device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& so) {
   const int tid = threadIdx.x;
-  const int n = min(lds_ld(sh.cnt, 0), sh.cap);   // stable: no wave emits until the closing barrier
-  if (n == 0) return;      // workgroup-uniform
-  __syncthreads();         // every wave has read cnt
-  if (tid == 0) *sh.gbase = atomicAdd(so.cursor, (unsigned long long)n);
+  if (tid == 0) {
+    const int n0 = min(lds_ld(sh.cnt, 0), sh.cap);
+    *sh.cnt = 0;
+    *sh.gbase = ((unsigned long long)(n0 > 0 ? atomicAdd(so.cursor, (unsigned long long)n0) : 0ull)
+                 << 16) | (unsigned long long)n0;
+  }
   __syncthreads();
-  const unsigned long long gb = *sh.gbase;
+  const unsigned long long hb = *sh.gbase;
+  const int n = (int)(hb & 0xFFFFull);
+  const unsigned long long gb = hb >> 16;
   for (int i = tid; i < n; i += kBlock) {
     if ((long long)(gb + i) < so.capacity) {
       const uint2 r = lds_ld(sh.buf, i);
       so.out[gb + i] = evis_event{r.x, (int32_t)r.y};
     }
   }
-  __syncthreads();         // copies done before the buffer is reused
-  if (tid == 0) {
-    *sh.cnt = 0;
-    sh.req[0] = sh.req[1] = 0;
-  }
-  __syncthreads();
+  __syncthreads();         // copies done (and gbase read) before the buffer is reused
+  if (tid == 0) sh.req[0] = sh.req[1] = 0;
 }
 
 // Read the last emission's flush request and flush if it is set.  Call it
@@ -139,7 +142,9 @@ __device__ __forceinline__ void emit_substep(
       const float c = aux.c(k, pos);
       const float a = fabsf(d);
       if (a >= c && c > 0.0f) {
-        const int n = crossing_count(a, c);
+        // c <= a < 2c (2c is exact) is one crossing: the common case skips
+        // the general count
+        const int n = (a < c + c) ? 1 : crossing_count(a, c);
         nn[k] = n;
         posbits |= (pos ? 1u : 0u) << k;
         if (refr == 0) {

@@ -91,6 +91,10 @@ def test_interpolate_subrange_and_list_fallback(torch, ctx):
         say("interpolate with the candidate list forced to overflow")
         got_L, got_h = run_interp(torch, ctx, pair, K, 3, 9, o.BLEND_TIME)
         check_interp(got_L, got_h, want_L, want_h, "fallback")
+        evis.evis_set_tuning(ctx, list_cap=40)    # some tiles overflow, some do not
+        say("interpolate with a partly overflowing candidate list")
+        got_L, got_h = run_interp(torch, ctx, pair, K, 3, 9, o.BLEND_TIME)
+        check_interp(got_L, got_h, want_L, want_h, "partly overflowing")
     finally:
         evis.evis_set_tuning(ctx, **old)
 
@@ -279,6 +283,24 @@ def test_step_mixed_small_batch(torch, ctx):
     want = oracle_steps(*args)
     say("step_batch mixed 5 envs")
     check_step(run_step(torch, ctx, *args), want)
+
+
+@pytest.mark.parametrize("list_cap", [12, 48, 160])
+def test_step_capped_candidate_lists(torch, ctx, list_cap):
+    """A fast rotation with the candidate list capped: tiles whose list
+    overflows take the window scan; the events must not change."""
+    from paper_2607_08098_amd import evis
+    pair = U.oracle_pair(U.blob_scene(96, 112, 41, flow="rotate", omega=19.0))
+    s = o.Sensor(C_on=0.2, C_off=0.2, K=0, K_max=64)
+    args = ([pair], [s], [pair.L_A.copy()], [None], [5])
+    want = oracle_steps(*args)
+    old = evis.evis_get_tuning(ctx).as_dict()
+    try:
+        evis.evis_set_tuning(ctx, list_cap=list_cap)
+        say("step_batch with list_cap", list_cap)
+        check_step(run_step(torch, ctx, *args), want)
+    finally:
+        evis.evis_set_tuning(ctx, **old)
 
 
 def test_step_static_scene_fast_path(torch, ctx):

@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
+    ap.add_argument("--disc-steps", type=int, default=200,
+                    help="steps of the 512-disc sustained run reported beside the metric (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB three times (the reference kernel for HBM counters)")
     ap.add_argument("--traffic-from", type=str, default=None, metavar="DIR",
@@ -138,6 +140,49 @@ def traffic_from(d, tile_label):
         json.dump(rec, fh, indent=1)
         fh.write("\n")
     print(json.dumps(rec))
+
+
+def disc_sustained(ctx, steps):
+    """512 rotating-disc envs at 346x260 (adaptive K <= 128, static background),
+    `steps` consecutive keyframe pairs with the state kept on the device; each
+    step's radiance is generated on the device before the step and only the
+    fused step is timed (HIP events on the stream)."""
+    import numpy as np
+    import torch
+    from paper_2607_08098_amd import evis, workloads
+    t = time.time()
+    batch = workloads.DiscBatch(ctx, n_envs=512, H=260, W=346, seed_base=4000)
+    batch.start(0)
+    sensor = dict(C_on=0.2, C_off=0.2, K=0, K_max=128, refractory_us=0)
+    out, n = evis.event_buffer(1 << 26)
+    K_used = torch.zeros(512, dtype=torch.int32, device="cuda")
+    tuning = evis.evis_get_tuning(ctx).as_dict()
+    log(f"disc512 ready in {time.time() - t:.1f}s")
+    ms, events, work, overflow = 0.0, 0, 0.0, False
+    px = 260 * 346
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for step in range(steps + 1):
+        if step > 0:
+            batch.advance()
+        t0, t1 = batch.times()
+        arr = evis.env_array(batch.env_dicts(sensor, t0, t1))
+        e0.record()
+        evis.evis_step_batch(ctx, arr, out, n, K_used, evis.EVIS_FLAG_RESET_CURSOR)
+        e1.record()
+        torch.cuda.synchronize()
+        if step == 0:
+            continue   # the first step also captures the graph
+        ms += e0.elapsed_time(e1)
+        cnt = int(n.item())
+        overflow |= cnt > out.shape[0]
+        events += cnt
+        work += float(K_used.cpu().numpy().astype(np.int64).sum()) * px
+        if step % 50 == 0:
+            log(f"disc512 step {step}: {cnt} events")
+    return dict(steps=steps, ms_per_step=round(ms / steps, 4),
+                mpix_substeps_per_s=round(work / 1e6 / (ms / 1e3), 1),
+                events_per_s=round(events / (ms / 1e3), 1), overflow=overflow, tuning=tuning)
 
 
 def cpu_baseline(batch_specs, sample_envs):
@@ -322,6 +367,8 @@ def main():
             log(f"{name}: {ms:.3f} ms/step")
         plain, fused_per_env = res["plain"], res["fused_per_env"]
 
+    disc = disc_sustained(ctx, args.disc_steps) if args.disc_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         sample = [0, 24]
@@ -343,7 +390,7 @@ def main():
         events_per_s=round(events_per_s, 1), events_per_step=round(events_total / args.steps, 1),
         per_env_plain=plain, per_env_fused=fused_per_env,
         batched_vs_plain=(round(value / plain["value"], 2) if plain else None),
-        roofline=roof, cpu_baseline=cpu,
+        roofline=roof, cpu_baseline=cpu, disc512_sustained=disc,
     )
     print(json.dumps(rec))
     ctx.close()

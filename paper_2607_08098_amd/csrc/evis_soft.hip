@@ -88,8 +88,10 @@ __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
     const float g = 1.0f - f;
     const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
     if (j < K) {
-      splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1, s_wl[wave],
-                           zbuf);
+      const float fs[1] = {f};
+      unsigned long long* const zs[1] = {zbuf};
+      splat_candidates<TW, 1>(d, list, nlist, overflow, win, K, j, 1, fs, Tx0, Tx1, Ty0, Ty1,
+                              s_wl[wave], zs);
       __syncthreads();
     }
 #pragma unroll

@@ -203,12 +203,14 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
 // the persistent tile kernel
 // ---------------------------------------------------------------------------
 
-// Per substep j of an item: (1) issue the B-gather loads of j, (2) splat j
-// into LDS z-buffer j & 1, barrier, (3) read the winners of j and issue the
-// loads of their L_A, (4) blend and emit substep j - 1, whose loads were
-// issued one substep earlier.  The readers of (3) clear the z-buffer; the
-// next splat into the same buffer (j + 2) comes after the barrier of j + 1,
-// so one barrier per substep orders everything (emission takes none).
+// Substeps go in pairs (j, j + 1) that share one splat pass (each source's
+// record is loaded once for both).  Per substep j: (1) issue the B-gather
+// loads of j; (2) at the first substep of a pair, splat j and j + 1 into LDS
+// z-buffers j & 1 and (j + 1) & 1, barrier; (3) read the winners of j
+// (clearing their cells) and issue the loads of their L_A; at the second
+// substep of a pair, barrier, so the next pair's splat comes after both
+// buffers are read; (4) blend and emit substep j - 1, whose loads were
+// issued one substep earlier.  One barrier per substep; emission takes none.
 template <int TW, int TH, int MODE>
 __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int NPX = TW * TH;
@@ -414,16 +416,22 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       float cAh[PPT], cBh[PPT];
       uint32_t chb[PPT];
       unsigned long long* zb = zbuf + (j & 1) * ZN;
+      const bool pair_start = ((j - j_first) & 1) == 0;   // uniform
       if (!is_static) {
         // (1) B-gather loads of substep j
         BTaps bt[PPT];
 #pragma unroll
         for (int k = 0; k < PPT; ++k) bt[k] = b_taps(d, pix_x(k), pix_y(k), mBq[k], g, (okbits >> k) & 1u);
-        // (2) splat substep j
-        splat_candidates<TW>(d, list, nlist, overflow, win, K, j, f, Tx0, Tx1, Ty0, Ty1,
-                             s_wl[wave], zb);
-        __syncthreads();
-        if (MODE == MODE_STEP) sink_check(sh, so, sr);
+        // (2) splat substeps j and j + 1
+        if (pair_start) {
+          const int nf = (j + 1 <= j_int_last) ? 2 : 1;
+          const float fs[2] = {f, (float)(j + 1) / (float)K};
+          unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 1) * ZN};
+          splat_candidates<TW, 2>(d, list, nlist, overflow, win, K, j, nf, fs, Tx0, Tx1, Ty0,
+                                  Ty1, s_wl[wave], zs);
+          __syncthreads();
+          if (MODE == MODE_STEP) sink_check(sh, so, sr);
+        }
         // (3) winners of substep j: issue their L_A loads; B values
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -441,14 +449,20 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
           chb[k] = (vA ? 0u : 1u) | (bt[k].v ? 0u : 2u);
         }
       } else {
-        __syncthreads();
-        if (MODE == MODE_STEP) sink_check(sh, so, sr);
+        if (pair_start) {
+          __syncthreads();
+          if (MODE == MODE_STEP) sink_check(sh, so, sr);
+        }
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           cAh[k] = 0.0f;
           cBh[k] = 0.0f;
           chb[k] = 0u;
         }
+      }
+      if (!pair_start) {   // both buffers of the pair are read and cleared
+        __syncthreads();
+        if (MODE == MODE_STEP) sink_check(sh, so, sr);
       }
       // (4) substep j - 1
       if (pending) finish_pending();

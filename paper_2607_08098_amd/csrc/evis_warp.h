@@ -86,14 +86,15 @@ __device__ __forceinline__ int cand_jhi(uint32_t e) { return (int)(e & 0x7Fu); }
 
 // Splat kChunk slots of four source blocks each (lane group g = lane / 16
 // takes candidate entry blk[c] of slot c, one source per lane; 0 is empty)
-// at fraction f into the LDS z-buffer of target tile [Tx0,Tx1]x[Ty0,Ty1].
-// The loads of all slots are issued before any of them is used.
+// into the LDS z-buffers of target tile [Tx0,Tx1]x[Ty0,Ty1]: at fraction
+// fs[t] into zs[t] for t < nf (nf <= NF consecutive substeps share the
+// loads).  The loads of all slots are issued before any of them is used.
 constexpr int kChunk = 3;
 
-template <int TW>
-__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&blk)[kChunk], float f,
-                                            int Tx0, int Tx1, int Ty0, int Ty1,
-                                            unsigned long long* zbuf) {
+template <int TW, int NF>
+__device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&blk)[kChunk],
+                                            const float (&fs)[NF], int nf, int Tx0, int Tx1,
+                                            int Ty0, int Ty1, unsigned long long* const (&zs)[NF]) {
   const int r = threadIdx.x & (kBlkPx - 1);   // lane within the block: (r & 3, r >> 2)
   float4 rec[kChunk];   // (m_A.x, m_A.y, Z_A, Zend - Z_A)
   int src[kChunk];      // source index, -1 outside the image or for an empty slot
@@ -113,28 +114,35 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
     if (src[c] < 0) continue;
-    const float qx = (float)sx[c] - f * rec[c].x;
-    const float qy = (float)sy[c] - f * rec[c].y;
-    const float zt = rec[c].z + f * rec[c].w;
-    if (!(zt > 0.0f)) continue;
-    if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
-          qy < (float)(Ty1 + 1)))
-      continue;
-    const float fx0 = floorf(qx), fy0 = floorf(qy);
-    const bool bx = qx > fx0, by = qy > fy0;   // corners of strictly positive weight
-    const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | (uint32_t)src[c];
-    // Corner (x0, y0) always; a corner of zero weight repeats it instead
-    // (the same key twice into one cell changes nothing), so the four
-    // atomics need no branches.
-    constexpr int ZS = zrow<TW>();
-    const int c00 = zcell<TW>((int)fx0 - Tx0, (int)fy0 - Ty0);
-    const int c01 = bx ? c00 + 1 : c00;
-    const int c10 = by ? c00 + ZS : c00;
-    const int c11 = (bx && by) ? c00 + ZS + 1 : c00;
-    atomicMin(zbuf + c00, key);
-    atomicMin(zbuf + c01, key);
-    atomicMin(zbuf + c10, key);
-    atomicMin(zbuf + c11, key);
+    const float px = (float)sx[c], py = (float)sy[c];
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+      if (t >= nf) break;   // uniform
+      const float f = fs[t];
+      const float qx = px - f * rec[c].x;
+      const float qy = py - f * rec[c].y;
+      const float zt = rec[c].z + f * rec[c].w;
+      if (!(zt > 0.0f)) continue;
+      if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
+            qy < (float)(Ty1 + 1)))
+        continue;
+      const float fx0 = floorf(qx), fy0 = floorf(qy);
+      const bool bx = qx > fx0, by = qy > fy0;   // corners of strictly positive weight
+      const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | (uint32_t)src[c];
+      // Corner (x0, y0) always; a corner of zero weight repeats it instead
+      // (the same key twice into one cell changes nothing), so the four
+      // atomics need no branches.
+      constexpr int ZS = zrow<TW>();
+      const int c00 = zcell<TW>((int)fx0 - Tx0, (int)fy0 - Ty0);
+      const int c01 = bx ? c00 + 1 : c00;
+      const int c10 = by ? c00 + ZS : c00;
+      const int c11 = (bx && by) ? c00 + ZS + 1 : c00;
+      unsigned long long* zb = zs[t];
+      atomicMin(zb + c00, key);
+      atomicMin(zb + c01, key);
+      atomicMin(zb + c10, key);
+      atomicMin(zb + c11, key);
+    }
   }
 }
 
@@ -225,18 +233,21 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
   return __builtin_amdgcn_readfirstlane(*count);
 }
 
-// Splat every source that can reach the target tile at substep j (fraction
-// f): the active entries of the candidate list, or, if the list overflowed,
-// the active blocks of the whole window.  Each wave takes every fourth
-// entry, packs its active entries into its 64-entry LDS slice `wl` and
-// splats them four blocks (one per lane group) per slot.
-template <int TW>
+// Splat every source that can reach the target tile at substeps j .. j+nf-1
+// (fractions fs, z-buffers zs): the candidate-list entries active at any of
+// them, or, if the list overflowed, the active blocks of the whole window.
+// Each wave takes every fourth entry, packs its active entries into its
+// 64-entry LDS slice `wl` and splats them four blocks (one per lane group)
+// per slot.
+template <int TW, int NF>
 __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_t* list, int nlist,
                                                  bool overflow, const Window& w, int K, int j,
-                                                 float f, int Tx0, int Tx1, int Ty0, int Ty1,
-                                                 uint32_t* wl, unsigned long long* zbuf) {
+                                                 int nf, const float (&fs)[NF], int Tx0, int Tx1,
+                                                 int Ty0, int Ty1, uint32_t* wl,
+                                                 unsigned long long* const (&zs)[NF]) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int g = lane >> 4;
+  const int jz = j + nf - 1;
   if (!overflow) {
     for (int base = 0; base < nlist; base += kBlock) {
       const int e2 = base + lane * kWavesPerBlock + wave;
@@ -244,7 +255,7 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
       bool act = false;
       if (e2 < nlist) {
         ent = lds_ld(list, e2);
-        act = (j >= cand_jlo(ent)) && (j <= cand_jhi(ent));
+        act = (jz >= cand_jlo(ent)) && (j <= cand_jhi(ent));
       }
       const unsigned long long mask = __ballot(act);
       const int nact = __popcll(mask);
@@ -256,7 +267,7 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
           const int i = s0 + c * 4 + g;
           blk[c] = (i < nact) ? lds_ld(wl, i) : 0u;
         }
-        splat_chunk<TW>(d, blk, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+        splat_chunk<TW, NF>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
       }
     }
   } else {
@@ -269,10 +280,10 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
       if (i < w.nwin) {
         const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
         int jlo, jhi;
-        if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && j >= jlo && j <= jhi)
+        if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && jz >= jlo && j <= jhi)
           blk[0] = cand_entry(bx, by, jlo, jhi);
       }
-      splat_chunk<TW>(d, blk, f, Tx0, Tx1, Ty0, Ty1, zbuf);
+      splat_chunk<TW, NF>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
     }
   }
 }

@@ -83,7 +83,7 @@ struct EventArgs {
 template <int PPT>
 __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   __shared__ uint2 evbuf[kEventBuf];
-  __shared__ int s_evn, s_req[2];
+  __shared__ int s_evn, s_req[4];
   __shared__ unsigned long long s_gbase;
   __shared__ float s_con[kBlock * PPT], s_coff[kBlock * PPT];
   __shared__ int s_tl[kBlock * PPT];

@@ -6,12 +6,14 @@
 // with one atomic add on the buffer's count; slots past the end of the
 // buffer go straight to the stream after one global atomic (the count may
 // then exceed the buffer, whose every slot is still filled); the wave
-// raises a flush request once the buffer is three quarters full.  Requests are read after
-// the next workgroup barrier, where every wave sees the same value: round r
-// writes request slot r & 1 and round r + 2 cannot start before the barrier
-// that follows round r + 1, by which time every wave has read slot r & 1.
-// So that this holds whatever the caller does, an emission that finds the
-// previous round unchecked takes the barrier and the check itself.
+// raises a flush request once the buffer is three quarters full.  Requests
+// are read after
+// the next workgroup barrier, where every wave sees the same values: round r
+// writes request slot r & 3, at most two rounds run between two checks, and
+// round r + 4 cannot start before the barrier that follows the check of
+// round r, by which time every wave has read slot r & 3.  So that this holds
+// whatever the caller does, an emission that finds two rounds unchecked
+// takes the barrier and the check itself.
 #pragma once
 
 #include "evis_common.h"
@@ -21,7 +23,7 @@ namespace evis {
 struct SinkShared {
   uint2* buf;                   // LDS [cap] staged events
   int* cnt;                     // LDS: events staged
-  int* req;                     // LDS [2]: flush requests by round parity
+  int* req;                     // LDS [4]: flush requests by round, modulo 4
   unsigned long long* gbase;    // LDS: global slot of the current flush
   int cap;
 };
@@ -35,14 +37,14 @@ struct SinkOut {
 // Workgroup-uniform sink state kept in registers.
 struct SinkRound {
   int round = 0;          // emissions so far
-  bool unchecked = false; // the last emission's request has not been read yet
+  int unchecked = 0;      // emissions whose requests have not been read yet (<= 2)
 };
 
 // Clear the LDS state; a barrier must follow before the first emission.
 __device__ __forceinline__ void sink_init(const SinkShared& sh) {
   if (threadIdx.x == 0) {
     *sh.cnt = 0;
-    sh.req[0] = sh.req[1] = 0;
+    sh.req[0] = sh.req[1] = sh.req[2] = sh.req[3] = 0;
   }
 }
 
@@ -70,17 +72,18 @@ __device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& 
     }
   }
   __syncthreads();         // copies done (and gbase read) before the buffer is reused
-  if (tid == 0) sh.req[0] = sh.req[1] = 0;
+  if (tid == 0) sh.req[0] = sh.req[1] = sh.req[2] = sh.req[3] = 0;
 }
 
-// Read the last emission's flush request and flush if it is set.  Call it
-// right after a workgroup barrier (every thread).
+// Read the flush requests of the emissions since the last check and flush
+// if one is set.  Call it right after a workgroup barrier (every thread).
 __device__ __forceinline__ void sink_check(const SinkShared& sh, const SinkOut& so,
                                            SinkRound& sr) {
-  if (!sr.unchecked) return;
-  sr.unchecked = false;
-  const int want = __builtin_amdgcn_readfirstlane(lds_ld(sh.req, (sr.round - 1) & 1));
-  if (want) sink_drain(sh, so);
+  if (sr.unchecked == 0) return;
+  int want = lds_ld(sh.req, (sr.round - 1) & 3);
+  if (sr.unchecked > 1) want |= lds_ld(sh.req, (sr.round - 2) & 3);
+  sr.unchecked = 0;
+  if (__builtin_amdgcn_readfirstlane(want)) sink_drain(sh, so);
 }
 
 // Per-pixel state that only a crossing pixel reads: thresholds, last event
@@ -119,14 +122,14 @@ struct PixAux {
 
 // One substep of the event model for the PPT pixels of this thread and the
 // wave's compaction.  Every thread of the workgroup must call it (it takes a
-// barrier only when the previous round was not checked).
+// barrier only when two rounds are unchecked).
 template <int PPT>
 __device__ __forceinline__ void emit_substep(
     int j, const float (&Lj)[PPT], const float (&Lp)[PPT], float (&R)[PPT], const PixAux& aux,
     uint32_t okbits, long long t0, int span, float Dt, int refr, uint32_t env_bits,
     const SinkShared& sh, const SinkOut& so, SinkRound& sr) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  if (sr.unchecked) {
+  if (sr.unchecked >= 2) {
     __syncthreads();
     sink_check(sh, so, sr);
   }
@@ -170,9 +173,9 @@ __device__ __forceinline__ void emit_substep(
     excl = incl - m;
     wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
   }
-  const int slot_req = sr.round & 1;
+  const int slot_req = sr.round & 3;
   ++sr.round;
-  sr.unchecked = true;
+  ++sr.unchecked;
   if (wtot > 0) {   // wave-uniform
     int lb = 0;
     if (lane == kWave - 1) lb = atomicAdd(sh.cnt, wtot);

@@ -222,7 +222,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   __shared__ uint32_t list[kListCapMax];
   __shared__ uint32_t s_wl[kWavesPerBlock][kWave];   // per-wave packed active candidates
   __shared__ uint2 evbuf[EVB];
-  __shared__ int s_evn, s_req[2];
+  __shared__ int s_evn, s_req[4];
   __shared__ unsigned long long s_gbase;
   __shared__ int s_item, s_rank, s_q, s_lcnt;
   constexpr int AUXN = (MODE == MODE_STEP) ? NPX : 1;

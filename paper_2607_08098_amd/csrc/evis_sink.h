@@ -197,7 +197,27 @@ __device__ __forceinline__ void emit_substep(
         if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
       }
     };
-    if (refr == 0) {
+    if (refr == 0 && wave_max_i(m) <= 4) {
+      // Few events per lane: each lane writes its own, in order.
+      int widx = excl;
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const int n = nn[k];
+        if (n > 0) {
+          const bool pos = (posbits >> k) & 1u;
+          const float c = aux.c(k, pos);
+          const int io = tid + k * kBlock;
+          const uint32_t word = aux.xy_at(io) | ((pos ? 1u : 0u) << 22) | env_bits;
+          int t = 0;
+          for (int kk = 1; kk <= n; ++kk) {
+            t = (int)(t0 + crossing_offset(j, kk, R[k], c, pos, Lp[k], Lj[k], Dt, span));
+            put(widx, word, t);
+            ++widx;
+          }
+          aux.set_tlast_at(io, t);   // the pixel's last event
+        }
+      }
+    } else if (refr == 0) {
       // Expansion: lane l writes events l, l + 64, ... of the wave.  Event e
       // belongs to the lane whose exclusive prefix is the largest <= e; its
       // rank within that lane's events picks the pixel slot and crossing.

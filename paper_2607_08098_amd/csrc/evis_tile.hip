@@ -397,11 +397,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       for (int k = 0; k < PPT; ++k) {
         const bool vA = !(phb[k] & 1u), vB = !(phb[k] & 2u);
         float v;
-        if (is_static) v = LAq[k];
+        if (is_static) v = Lp[k];   // every sample of a static tile is L_A
         else if (vA && vB) v = lerp32(pAh[k], pBh[k], palpha);
         else if (vA) v = pAh[k];
         else if (vB) v = pBh[k];
-        else v = lerp32(LAq[k], LBq[k], palpha);
+        else {   // neither side: the pixel's own values (rare; read again, not kept in registers)
+          const int qq = ((okbits >> k) & 1u) ? pix_y(k) * W + pix_x(k) : 0;
+          v = lerp32(ldg(d.LA, qq), ldg(d.LB, qq), palpha);
+        }
         Lj[k] = v;
       }
       consume(pj, Lj, phb);
@@ -482,7 +485,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       uint32_t hb[PPT];
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
-        Lj[k] = LBq[k];
+        Lj[k] = ((okbits >> k) & 1u) ? ldg(d.LB, pix_y(k) * W + pix_x(k)) : 0.0f;
         hb[k] = 0u;
       }
       consume(K, Lj, hb);

@@ -13,7 +13,7 @@ namespace evis {
 enum Mode { MODE_STEP = 0, MODE_INTERP = 1, MODE_SOFT_FWD = 2, MODE_SOFT_BWD = 3 };
 
 constexpr int kListCapMax = 1024;   // per-tile candidate source tiles held in LDS
-constexpr int kEventBuf = 2048;     // events staged in LDS per workgroup
+constexpr int kEventBuf = 1024;     // events staged in LDS per workgroup
 constexpr int kXcd = 8;             // work queues: one per accelerator complex die
 constexpr int kQueueStride = 64;    // queue counters 256 bytes apart (own cache lines)
 

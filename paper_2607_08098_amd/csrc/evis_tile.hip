@@ -206,11 +206,11 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
 // Substeps go in pairs (j, j + 1) that share one splat pass (each source's
 // record is loaded once for both).  Per substep j: (1) issue the B-gather
 // loads of j; (2) at the first substep of a pair, splat j and j + 1 into LDS
-// z-buffers j & 1 and (j + 1) & 1, barrier; (3) read the winners of j
-// (clearing their cells) and issue the loads of their L_A; at the second
-// substep of a pair, barrier, so the next pair's splat comes after both
-// buffers are read; (4) blend and emit substep j - 1, whose loads were
-// issued one substep earlier.  One barrier per substep; emission takes none.
+// z-buffers j & 3 and (j + 1) & 3, barrier; (3) read the winners of j
+// (clearing their cells) and issue the loads of their L_A; (4) blend and emit
+// substep j - 1, whose loads were issued one substep earlier.  The next pair
+// splats into the other two buffers, and the pair after it comes after the
+// next pair's barrier, so one barrier per pair suffices; emission takes none.
 template <int TW, int TH, int MODE>
 __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int NPX = TW * TH;
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   static_assert(PPT * kBlock == NPX, "tile must be a multiple of the workgroup");
   constexpr int EVB = (MODE == MODE_STEP) ? kEventBuf : 1;
   constexpr int ZN = zcells<TW, TH>();
-  __shared__ unsigned long long zbuf[2 * ZN];
+  __shared__ unsigned long long zbuf[4 * ZN];
   __shared__ uint32_t list[kListCapMax];
   __shared__ uint32_t s_wl[kWavesPerBlock][kWave];   // per-wave packed active candidates
   __shared__ uint2 evbuf[EVB];
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
     if (MODE == MODE_STEP) sink_check(sh, so, sr);
     // Readers clear the cells they read; apron cells and those of pixels
     // outside the image are cleared here, once per item.
-    for (int i = tid; i < 2 * ZN; i += kBlock) zbuf[i] = kEmptyKey;
+    for (int i = tid; i < 4 * ZN; i += kBlock) zbuf[i] = kEmptyKey;
     if (tid == 0) {
       int item = -1, r = 0, q = -1;
       while (qsel < kXcd) {
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
       float cAh[PPT], cBh[PPT];
       uint32_t chb[PPT];
-      unsigned long long* zb = zbuf + (j & 1) * ZN;
+      unsigned long long* zb = zbuf + (j & 3) * ZN;
       const bool pair_start = ((j - j_first) & 1) == 0;   // uniform
       if (!is_static) {
         // (1) B-gather loads of substep j
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
         if (pair_start) {
           const int nf = (j + 1 <= j_int_last) ? 2 : 1;
           const float fs[2] = {f, (float)(j + 1) / (float)K};
-          unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 1) * ZN};
+          unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 3) * ZN};
           splat_candidates<TW, 2>(d, list, nlist, overflow, win, K, j, nf, fs, Tx0, Tx1, Ty0,
                                   Ty1, s_wl[wave], zs);
           __syncthreads();
@@ -462,10 +462,6 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
           cBh[k] = 0.0f;
           chb[k] = 0u;
         }
-      }
-      if (!pair_start) {   // both buffers of the pair are read and cleared
-        __syncthreads();
-        if (MODE == MODE_STEP) sink_check(sh, so, sr);
       }
       // (4) substep j - 1
       if (pending) finish_pending();

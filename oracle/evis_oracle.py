@@ -18,6 +18,10 @@ in NVIDIA Isaac Sim".  Steps, in the paper's order:
                          Eq. 7 intermediate depth
   resolve_gather_blend   Eq. 5 (q_B) evaluated as a backward gather, the
                          hole-aware blend of A and B
+  start_depth,           the two-splat warp: B splatted backward to Eq. 5's
+  splat_backward,        q_B with its own z-buffer (or one z-buffer shared
+  resolve_two_splat      with A's splat, Eq. 6 over both keyframes) and
+                         the same hole-aware blend
   emit_events            Eq. 4 (crossing count, polarity, residual-keeping
                          reference update), Eq. 8 threshold mismatch, the
                          refractory period of Sec. "Sensor Calibration and
@@ -56,6 +60,19 @@ Readings of the paper taken here (each is restated where it is used):
       the previous and the current sample; integer microseconds, floor.
   R11 lerp(a, b, w) = a + w * (b - a); bilinear = two lerps along x, one
       along y; x1 = min(x0 + 1, W - 1).
+  R12 two-splat warp (WARP_SPLAT): B is splatted backward to
+      q_B = p + (1 - f) m_B(p) with Eq. 7 endpoints p_A = p + m_B(p),
+      p_B = p (Z_A sampled bilinearly at p_A, clamped into the image), the
+      same footprint, tie rule and visibility as A's splat, into a z-buffer
+      of its own; B^ is L_B at B's winner (valid where a B source landed)
+      and the blend is R2's.  With BLEND_B_PRIMARY this is the paper's
+      fusion: B's splat is the result and A fills only B's holes.
+  R13 joint warp (WARP_JOINT): one z-buffer over the sources of both
+      splats (Eq. 6 with X in {A, B}); at equal depth B wins (B is the
+      primary keyframe), then the smaller index.  The winner's own
+      intensity is the sub-frame; where nothing lands, R2's hole value.
+      The hole mask marks A invalid unless an A source won, B invalid
+      unless a B source won.
 """
 from __future__ import annotations
 
@@ -72,6 +89,12 @@ N_MAX = 65535                 # R8: crossings per pixel-substep are capped here
 T_LAST_INIT = -(2 ** 30)      # "never fired": far enough back for any refractory period
 BLEND_TIME = 0
 BLEND_B_PRIMARY = 1
+# Warp of B, or'ed into the mode word next to the blend: R1, R12, R13.
+WARP_GATHER = 0x00
+WARP_SPLAT = 0x10
+WARP_JOINT = 0x20
+WARP_MASK = 0x30
+A_TAG = np.uint64(0x8000_0000)    # R13: marks an A source in a joint key (B wins ties)
 REC709 = (0.2126, 0.7152, 0.0722)
 
 
@@ -202,20 +225,75 @@ def footprint(qx, qy):
             (x0 + 1, y0 + 1, (fx > 0) & (fy > 0))]
 
 
-def splat_forward(m_A, Z_A, Zend, f) -> np.ndarray:
-    """Eq. 6 z-buffer of A splatted to fraction f: uint64 key per target
-    pixel, EMPTY_KEY where nothing lands.  min over keys = nearest depth,
-    then smallest source index (R5)."""
-    H, W = Z_A.shape
-    qx, qy, zt, key = splat_keys(m_A, Z_A, Zend, f)
-    # R7 plus finiteness; positions far outside the image cannot reach it.
+def scatter_min(zbuf, qx, qy, zt, key):
+    """Eq. 6: every visible source (R7 plus finite position) lowers the
+    keys of its footprint cells inside the image to its own key; min over
+    keys = nearest depth, then smallest source index (R5).  zbuf is a flat
+    uint64 [H*W] array, updated in place."""
+    H, W = zt.shape
     live = (zt > 0) & (np.abs(qx) < 2.0 ** 24) & (np.abs(qy) < 2.0 ** 24)
     qx = np.where(live, qx, F32(-8))
     qy = np.where(live, qy, F32(-8))
-    zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
     for cx, cy, sel in footprint(qx, qy):
         sel = sel & live & (cx >= 0) & (cx < W) & (cy >= 0) & (cy < H)
         np.minimum.at(zbuf, (cy * W + cx)[sel], key[sel])
+
+
+def splat_forward(m_A, Z_A, Zend, f) -> np.ndarray:
+    """Eq. 6 z-buffer of A splatted to fraction f: uint64 key per target
+    pixel, EMPTY_KEY where nothing lands."""
+    H, W = Z_A.shape
+    qx, qy, zt, key = splat_keys(m_A, Z_A, Zend, f)
+    zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
+    scatter_min(zbuf, qx, qy, zt, key)
+    return zbuf.reshape(H, W)
+
+
+# ---------------------------------------------------------------------------
+# backward splat of B (Eq. 5 q_B, Eq. 6, Eq. 7; R12, R13)
+# ---------------------------------------------------------------------------
+
+def start_depth(Z_A: np.ndarray, m_B: np.ndarray) -> np.ndarray:
+    """Z_A at p_A = p + m_B(p), position clamped into the image (R12)."""
+    H, W = Z_A.shape
+    px, py = pixel_coords(H, W)
+    sx = clamp_into(px + m_B[..., 0], W - 1)
+    sy = clamp_into(py + m_B[..., 1], H - 1)
+    return bilinear(Z_A, sx, sy)
+
+
+def splat_keys_backward(m_B, Z_B, Zstart, f):
+    """Per B source: target q_B = p + (1 - f) m_B(p), intermediate depth
+    (1 - f) Z_A(p_A) + f Z_B(p) as lerp(Zstart, Z_B, f) and the packed key."""
+    H, W = Z_B.shape
+    px, py = pixel_coords(H, W)
+    g = F32(1) - f
+    qx = px + g * m_B[..., 0]
+    qy = py + g * m_B[..., 1]
+    zt = lerp(Zstart, Z_B, f)
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (np.ascontiguousarray(zt).view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def splat_backward(m_B, Z_B, Zstart, f) -> np.ndarray:
+    """Eq. 6 z-buffer of B splatted back to fraction f (R12)."""
+    H, W = Z_B.shape
+    qx, qy, zt, key = splat_keys_backward(m_B, Z_B, Zstart, f)
+    zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
+    scatter_min(zbuf, qx, qy, zt, key)
+    return zbuf.reshape(H, W)
+
+
+def splat_joint(m_A, Z_A, Zend, m_B, Z_B, Zstart, f) -> np.ndarray:
+    """One z-buffer over the sources of both splats (R13): A keys carry
+    A_TAG in their low word, so B wins at equal depth."""
+    H, W = Z_A.shape
+    zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
+    qx, qy, zt, key = splat_keys_backward(m_B, Z_B, Zstart, f)
+    scatter_min(zbuf, qx, qy, zt, key)
+    qx, qy, zt, key = splat_keys(m_A, Z_A, Zend, f)
+    scatter_min(zbuf, qx, qy, zt, key | A_TAG)
     return zbuf.reshape(H, W)
 
 
@@ -249,8 +327,36 @@ def resolve_gather_blend(zbuf, L_A, L_B, m_B, f, alpha):
     return out.astype(F32), vA, vB
 
 
+def resolve_two_splat(zA, zB, L_A, L_B, alpha):
+    """Intermediate log frame from the winners of the two splats (R12):
+    A^ = L_A at A's winner, B^ = L_B at B's winner, blend per R2.  Pass the
+    joint z-buffer as zA and None as zB for R13.  Returns (L_f, validA,
+    validB)."""
+    H, W = L_A.shape
+    low = np.uint64(0xFFFF_FFFF)
+    if zB is None:
+        key = zA.reshape(-1)
+        hit = key != EMPTY_KEY
+        isA = hit & ((key & A_TAG) != 0)
+        vA, vB = isA, hit & ~isA
+        sA = np.where(vA, key & (low ^ A_TAG), np.uint64(0)).astype(np.int64)
+        sB = np.where(vB, key & low, np.uint64(0)).astype(np.int64)
+    else:
+        kA, kB = zA.reshape(-1), zB.reshape(-1)
+        vA, vB = kA != EMPTY_KEY, kB != EMPTY_KEY
+        sA = np.where(vA, kA & low, np.uint64(0)).astype(np.int64)
+        sB = np.where(vB, kB & low, np.uint64(0)).astype(np.int64)
+    Ah = np.where(vA, L_A.reshape(-1)[sA], F32(0)).reshape(H, W)
+    Bh = np.where(vB, L_B.reshape(-1)[sB], F32(0)).reshape(H, W)
+    vA, vB = vA.reshape(H, W), vB.reshape(H, W)
+    both = lerp(Ah, Bh, alpha)
+    hole = lerp(L_A, L_B, alpha)
+    out = np.where(vA & vB, both, np.where(vA, Ah, np.where(vB, Bh, hole)))
+    return out.astype(F32), vA, vB
+
+
 def blend_alpha(f, blend_mode: int):
-    return f if blend_mode == BLEND_TIME else F32(1)
+    return f if (blend_mode & ~WARP_MASK) == BLEND_TIME else F32(1)
 
 
 @dataclass
@@ -272,19 +378,31 @@ class Pair:
 
 def substep_frames(pair: Pair, K: int, js: Iterable[int], blend_mode: int = BLEND_TIME):
     """Yields (j, L_j, hole) for j in js; L_0 = L_A and L_K = L_B exactly;
-    hole bit0 = A invalid, bit1 = B invalid (0 at j = 0 and j = K)."""
-    Zend = None
+    hole bit0 = A invalid, bit1 = B invalid (0 at j = 0 and j = K).
+    blend_mode is the mode word: a BLEND_* value or'ed with a WARP_* value."""
+    Zend = Zstart = None
     H, W = pair.shape
+    warp = blend_mode & WARP_MASK
     for j in js:
         if j == 0 or j == K:
             yield j, (pair.L_A if j == 0 else pair.L_B).astype(F32), np.zeros((H, W), np.uint8)
             continue
         if Zend is None:
             Zend = endpoint_depth(pair.Z_B, pair.m_A)
+            if warp != WARP_GATHER:
+                Zstart = start_depth(pair.Z_A, pair.m_B)
         f = substep_fraction(j, K)
-        zbuf = splat_forward(pair.m_A, pair.Z_A, Zend, f)
-        L, vA, vB = resolve_gather_blend(zbuf, pair.L_A, pair.L_B, pair.m_B, f,
-                                         blend_alpha(f, blend_mode))
+        alpha = blend_alpha(f, blend_mode)
+        if warp == WARP_GATHER:
+            zbuf = splat_forward(pair.m_A, pair.Z_A, Zend, f)
+            L, vA, vB = resolve_gather_blend(zbuf, pair.L_A, pair.L_B, pair.m_B, f, alpha)
+        elif warp == WARP_SPLAT:
+            zA = splat_forward(pair.m_A, pair.Z_A, Zend, f)
+            zB = splat_backward(pair.m_B, pair.Z_B, Zstart, f)
+            L, vA, vB = resolve_two_splat(zA, zB, pair.L_A, pair.L_B, alpha)
+        else:
+            zj = splat_joint(pair.m_A, pair.Z_A, Zend, pair.m_B, pair.Z_B, Zstart, f)
+            L, vA, vB = resolve_two_splat(zj, None, pair.L_A, pair.L_B, alpha)
         hole = ((~vA).astype(np.uint8) | ((~vB).astype(np.uint8) << 1))
         yield j, L, hole
 

@@ -324,6 +324,122 @@ def pin_blend_modes(o):
 
 
 # ---------------------------------------------------------------------------
+# two-splat and joint warp
+# ---------------------------------------------------------------------------
+
+def pin_start_depth_affine(o):
+    """Z_A sampled at p + m_B(p), clamped: exact on an affine depth map."""
+    H, W = 7, 10
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    Z_A = (2.0 + 0.25 * xx - 0.5 * yy).astype(F32)
+    m_B = np.zeros((H, W, 2), F32)
+    m_B[..., 0] = 2.5
+    m_B[..., 1] = -1.25
+    got = o.start_depth(Z_A, m_B).astype(np.float64)
+    sx = np.minimum(xx + 2.5, W - 1)
+    sy = np.maximum(yy - 1.25, 0.0)
+    assert np.array_equal(got, 2.0 + 0.25 * sx - 0.5 * sy)
+
+
+def pin_backward_splat_reversal(o):
+    """Time reversal: splatting B back to fraction f is splatting a keyframe
+    with motion -m_B forward by 1 - f with the depth roles of A and B
+    swapped (Eq. 5 and Eq. 7 are symmetric under t -> 1 - t).  On dyadic
+    inputs every value is exact in both forms, so the z-buffers agree bit
+    for bit; the forward splat is pinned by brute force above."""
+    rng = np.random.default_rng(37)
+    H, W = 9, 11
+    for trial in range(4):
+        m_B = (rng.integers(-12, 13, size=(H, W, 2)) / 4.0).astype(F32)
+        Z_A = rng.choice(np.array([1.0, 2.0, 3.0, 4.0], F32), size=(H, W))
+        Z_B = rng.choice(np.array([1.0, 2.0, 3.0, -1.0], F32), size=(H, W))
+        Zs = o.start_depth(Z_A, m_B)
+        for K, j in ((8, 3), (4, 1), (8, 6)):
+            f = F32(j) / F32(K)
+            got = o.splat_backward(m_B, Z_B, Zs, f)
+            neg = (-m_B).astype(F32)
+            want = o.splat_forward(neg, Z_B, o.endpoint_depth(Z_A, neg), F32(K - j) / F32(K))
+            assert np.array_equal(got, want), (trial, K, j)
+
+
+def _layer_scene(u=(2, 1), K=4, seed=41):
+    """A textured near square (depth 1) moving by u per substep over a static
+    textured far background (depth 5): keyframes, motion and the exact
+    frame at every substep."""
+    rng = np.random.default_rng(seed)
+    H, W = 22, 26
+    ux, uy = u
+    bg = rng.normal(0, 2, size=(H, W)).astype(F32)
+    tex = rng.normal(4, 1, size=(6, 6)).astype(F32)
+
+    def frame(j):
+        L = bg.copy()
+        Z = np.full((H, W), F32(5.0))
+        y0, x0 = 4 + j * uy, 4 + j * ux
+        L[y0:y0 + 6, x0:x0 + 6] = tex
+        Z[y0:y0 + 6, x0:x0 + 6] = 1.0
+        return L, Z
+
+    L_A, Z_A = frame(0)
+    L_B, Z_B = frame(K)
+    m_A = np.zeros((H, W, 2), F32)
+    m_B = np.zeros((H, W, 2), F32)
+    m_A[4:10, 4:10] = (-K * ux, -K * uy)
+    m_B[4 + K * uy:10 + K * uy, 4 + K * ux:10 + K * ux] = (-K * ux, -K * uy)
+    return (L_A, L_B, m_A, m_B, Z_A, Z_B), frame
+
+
+def pin_two_splat_layers(o):
+    """The near square over the static background: the two-splat warp (either
+    blend) and the joint warp rebuild every intermediate frame exactly, and
+    B's holes are exactly the background the square covers in B but not at
+    the substep (A's holes: covered in A but not at the substep)."""
+    K, u = 4, (2, 1)
+    args, frame = _layer_scene(u, K)
+    pair = o.Pair(*args)
+    H, W = pair.shape
+    yy, xx = np.mgrid[0:H, 0:W]
+
+    def square(j):
+        y0, x0 = 4 + j * u[1], 4 + j * u[0]
+        return (yy >= y0) & (yy < y0 + 6) & (xx >= x0) & (xx < x0 + 6)
+
+    for mode in (o.WARP_SPLAT | o.BLEND_B_PRIMARY, o.WARP_SPLAT | o.BLEND_TIME,
+                 o.WARP_JOINT | o.BLEND_TIME):
+        Ls, holes = o.interpolate(pair, K, 1, K, mode)
+        for j in range(1, K):
+            want, _ = frame(j)
+            assert np.array_equal(Ls[j - 1], want), (mode, j)
+            if mode & o.WARP_MASK == o.WARP_SPLAT:
+                bhole = square(K) & ~square(j)
+                ahole = square(0) & ~square(j)
+                assert np.array_equal((holes[j - 1] & 2) != 0, bhole), (mode, j)
+                assert np.array_equal((holes[j - 1] & 1) != 0, ahole), (mode, j)
+
+
+def pin_joint_priority(o):
+    """An A source and a B source land on the same pixel: the nearer wins,
+    and at equal depth B (the primary keyframe) wins."""
+    H, W, K = 1, 7, 2
+    L_A = np.arange(1, W + 1, dtype=F32).reshape(H, W)
+    L_B = (10 * L_A).astype(F32)
+    m_A = np.zeros((H, W, 2), F32)
+    m_B = np.zeros((H, W, 2), F32)
+    m_A[0, 0, 0] = -4.0         # A's x = 0 lands on x = 2 at f = 1/2; endpoint B x = 4
+    m_B[0, 5, 0] = -6.0         # B's x = 5 lands on x = 2 at f = 1/2; endpoint A x = 0 (clamped)
+    for e4, e5, want in ((3.0, 3.0, L_B[0, 5]), (2.0, 3.0, L_A[0, 0]), (3.0, 2.0, L_B[0, 5])):
+        Z_A = np.full((H, W), F32(100.0))
+        Z_B = np.full((H, W), F32(100.0))
+        Z_A[0, 0] = 1.0
+        Z_B[0, 4] = e4          # A's depth at f = 1/2: (1 + e4) / 2
+        Z_B[0, 5] = e5          # B's depth at f = 1/2: (1 + e5) / 2
+        pair = o.Pair(L_A, L_B, m_A, m_B, Z_A, Z_B)
+        Ls, holes = o.interpolate(pair, K, 1, 2, o.WARP_JOINT | o.BLEND_TIME)
+        assert Ls[0][0, 2] == want, (e4, e5, Ls[0][0, 2])
+        assert holes[0][0, 2] == (2 if want < 10 else 1), (e4, e5)
+
+
+# ---------------------------------------------------------------------------
 # event emission
 # ---------------------------------------------------------------------------
 

@@ -138,6 +138,61 @@ def _emit_variant(drop_residual=False, flip=False, refr_keeps_ref=False):
     return emit
 
 
+def m_backward_sign(m_B, Z_B, Zstart, f):
+    H, W = Z_B.shape
+    px, py = o.pixel_coords(H, W)
+    g = F32(1) - f
+    qx = px - g * m_B[..., 0]                      # planted: q_B = p - (1 - f) m_B
+    qy = py - g * m_B[..., 1]
+    zt = o.lerp(Zstart, Z_B, f)
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (np.ascontiguousarray(zt).view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def m_backward_fraction(m_B, Z_B, Zstart, f):
+    H, W = Z_B.shape
+    px, py = o.pixel_coords(H, W)
+    qx = px + f * m_B[..., 0]                      # planted: f where 1 - f belongs
+    qy = py + f * m_B[..., 1]
+    zt = o.lerp(Zstart, Z_B, f)
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (np.ascontiguousarray(zt).view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def m_backward_depth_swapped(m_B, Z_B, Zstart, f):
+    qx, qy, _, _ = o.__dict__["_orig_skb"](m_B, Z_B, Zstart, f)
+    H, W = Z_B.shape
+    zt = o.lerp(Z_B, Zstart, f)                    # planted: Eq. 7 endpoints swapped
+    src = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    key = (np.ascontiguousarray(zt).view(np.uint32).astype(np.uint64) << np.uint64(32)) | src
+    return qx, qy, zt, key
+
+
+def m_start_depth_sign(Z_A, m_B):
+    return o.endpoint_depth(Z_A, m_B)              # planted: Z_A at p - m_B(p)
+
+
+def m_joint_a_first(m_A, Z_A, Zend, m_B, Z_B, Zstart, f):
+    H, W = Z_A.shape
+    zbuf = np.full(H * W, o.EMPTY_KEY, dtype=np.uint64)
+    qx, qy, zt, key = o.splat_keys_backward(m_B, Z_B, Zstart, f)
+    o.scatter_min(zbuf, qx, qy, zt, key | o.A_TAG)   # planted: A wins ties
+    qx, qy, zt, key = o.splat_keys(m_A, Z_A, Zend, f)
+    o.scatter_min(zbuf, qx, qy, zt, key)
+    z = zbuf.reshape(H, W)
+    low = z & np.uint64(0xFFFF_FFFF)
+    hit = z != o.EMPTY_KEY
+    return np.where(hit, (z & ~np.uint64(0xFFFF_FFFF)) | (low ^ o.A_TAG), z)
+
+
+def m_two_splat_b_everywhere(zA, zB, L_A, L_B, alpha):
+    if zB is not None:                             # planted: B valid wherever A's splat is
+        zB = np.where(zB == o.EMPTY_KEY, np.arange(zB.size, dtype=np.uint64).reshape(zB.shape), zB)
+    return o.__dict__["_orig_rts"](zA, zB, L_A, L_B, alpha)
+
+
 def m_pack_shift(ev):
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     word = ev[:, 0] | (ev[:, 1] << 12) | (ev[:, 3] << 22) | (ev[:, 4] << 23)   # planted
@@ -159,6 +214,15 @@ MUTANTS = [
     ("polarity_flipped", "emit_substep", _emit_variant(flip=True), P.pin_goldens),
     ("suppressed_keep_reference", "emit_substep", _emit_variant(refr_keeps_ref=True), P.pin_goldens),
     ("pack_bit_position", "pack_events", m_pack_shift, P.pin_event_record),
+    ("backward_splat_sign", "splat_keys_backward", m_backward_sign, P.pin_backward_splat_reversal),
+    ("backward_splat_fraction", "splat_keys_backward", m_backward_fraction,
+     P.pin_backward_splat_reversal),
+    ("backward_depth_swapped", "splat_keys_backward", m_backward_depth_swapped,
+     P.pin_backward_splat_reversal),
+    ("start_depth_sign", "start_depth", m_start_depth_sign, P.pin_start_depth_affine),
+    ("joint_a_wins_ties", "splat_joint", m_joint_a_first, P.pin_joint_priority),
+    ("two_splat_b_everywhere", "resolve_two_splat", m_two_splat_b_everywhere,
+     P.pin_two_splat_layers),
 ]
 
 
@@ -173,6 +237,8 @@ def test_unmutated_variant_passes(monkeypatch):
 def test_pin_catches_mutant(monkeypatch, name, attr, mutant, pin):
     monkeypatch.setitem(o.__dict__, "_orig_rgb", o.resolve_gather_blend)
     monkeypatch.setitem(o.__dict__, "_orig_cto", o.crossing_time_offset)
+    monkeypatch.setitem(o.__dict__, "_orig_skb", o.splat_keys_backward)
+    monkeypatch.setitem(o.__dict__, "_orig_rts", o.resolve_two_splat)
     monkeypatch.setattr(o, attr, mutant)
     with pytest.raises((AssertionError, IndexError, ValueError)):
         pin(o)

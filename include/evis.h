@@ -70,6 +70,32 @@ enum {
   EVIS_BLEND_B_PRIMARY = 1  /* alpha = 1: backward-warped B is the result, A fills B's holes */
 };
 
+/* How keyframe B is warped to fraction f (same section, Eq. 5 and Eq. 6),
+ * or'ed with an EVIS_BLEND_* value into the mode word that the
+ * `blend_mode` arguments and fields carry.
+ *  GATHER  B is sampled bilinearly at s = q - (1 - f) m_B(q), with the
+ *          motion vector at the target (exact for locally constant flow).
+ *  SPLAT   B is splatted backward like A forward: source p of B goes to
+ *          q_B = p + (1 - f) m_B(p) over the same footprint, depth from
+ *          Eq. 7 with p_A = p + m_B(p), p_B = p (Z_A sampled with edge
+ *          clamping), into a z-buffer of its own; B^ is L_B at its winner
+ *          (missing where no B source landed) and the blend is as above.
+ *          With EVIS_BLEND_B_PRIMARY the backward-warped B is the result
+ *          and the forward-warped A fills only B's holes.
+ *  JOINT   both splats into one z-buffer (Eq. 6 over both keyframes): the
+ *          nearest source wins, B at equal depth, then the smaller index;
+ *          the sub-frame is the winner's own intensity, and
+ *          lerp(L_A(q), L_B(q), alpha) where nothing landed.
+ * The hole mask marks A missing / B missing per side (JOINT: the side
+ * that did not win).  The two splat warps are supported by
+ * evis_interpolate and evis_step_batch (one warp for all envs of a call),
+ * not by the surrogate. */
+enum {
+  EVIS_WARP_GATHER = 0x00,
+  EVIS_WARP_SPLAT = 0x10,
+  EVIS_WARP_JOINT = 0x20
+};
+
 enum { EVIS_FLAG_RESET_CURSOR = 1 };
 
 /* One event: x in bits 0..10, y in 11..21, polarity in 22 (1 = ON), env id
@@ -96,7 +122,7 @@ typedef struct {
   int32_t refractory_us;              /* >= 0; 0 = off */
   int32_t K;                          /* > 0: fixed substep count; <= 0: adaptive */
   int32_t K_max;                      /* 1..EVIS_MAX_K, cap of the adaptive count */
-  int32_t blend_mode;                 /* EVIS_BLEND_* */
+  int32_t blend_mode;                 /* EVIS_BLEND_* | EVIS_WARP_* */
 } evis_sensor;
 
 /* Per-pixel state carried from pair to pair (caller-owned device arrays). */
@@ -149,12 +175,13 @@ int evis_substep_count(evis_ctx *ctx, const evis_pair *pair, int32_t K_max, int3
  * q = p - f m_A(p) over the bilinear footprint (corners with positive
  * weight), a 64-bit (depth bits << 32 | source index) z-buffer keeps the
  * nearest source (Eq. 6; depth from Eq. 7 with p_B = p - m_A(p), Z_B
- * sampled with edge clamping); keyframe B is gathered bilinearly at
- * s = q - (1 - f) m_B(q); the two are blended per blend_mode, each side
- * alone where the other is missing, and lerp(L_A(q), L_B(q), alpha) where
- * both are missing.  L_out is [(j_end - j_begin)][H*W]; hole_mask (nullable) is
- * the same shape in bytes: bit 0 = no A source landed, bit 1 = s outside
- * the image. */
+ * sampled with edge clamping); keyframe B is warped per the mode word's
+ * EVIS_WARP_* (default: gathered bilinearly at s = q - (1 - f) m_B(q));
+ * the two are blended per its EVIS_BLEND_*, each side alone where the
+ * other is missing, and lerp(L_A(q), L_B(q), alpha) where both are
+ * missing.  L_out is [(j_end - j_begin)][H*W]; hole_mask (nullable) is the
+ * same shape in bytes: bit 0 = A missing (no A source landed), bit 1 = B
+ * missing (gather: s outside the image; splat: no B source landed). */
 int evis_interpolate(evis_ctx *ctx, const evis_pair *pair, int32_t K, int32_t j_begin,
                      int32_t j_end, int32_t blend_mode, float *L_out, uint8_t *hole_mask,
                      void *stream);
@@ -176,7 +203,8 @@ int evis_generate_events(evis_ctx *ctx, const float *L_seq, int32_t H, int32_t W
 /* Fused step -- one keyframe pair for each of n_envs environments
  * (1..EVIS_MAX_ENVS; envs is a HOST array of descriptors) in one
  * persistent launch: substep count, sub-frames and events of every env,
- * all events appended to one stream.  K_used (device [n_envs], nullable)
+ * all events appended to one stream.  All envs of a call use the same
+ * EVIS_WARP_* (else EVIS_ERR_UNSUPPORTED); blends may differ.  K_used (device [n_envs], nullable)
  * receives each env's K.  States are updated in place.  The launch
  * sequence is captured once into a HIP graph per (n_envs, out, cursor,
  * K_used, tuning) and replayed. */
@@ -187,8 +215,9 @@ int evis_step_batch(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_ev
 /* Tuning of the fused launch: target tile shape and persistent grid size.
  * tile_w x tile_h in {16x16, 32x16, 32x32, 64x16, 64x32}; grid_mult >= 1
  * workgroups per compute unit (0 = occupancy limit); list_cap in 1..1024
- * caps the per-tile candidate list (smaller values force the window-scan
- * fallback; 0 = the maximum); use_graph 0/1. */
+ * caps the per-tile candidate list (the two-splat warps, whose list holds
+ * both directions, take twice as many; smaller values force the
+ * window-scan fallback; 0 = the maximum); use_graph 0/1. */
 typedef struct {
   int32_t tile_w, tile_h;
   int32_t grid_mult;
@@ -234,7 +263,8 @@ typedef struct {
  * direct -sigma'/tau term; without it dC also flows through R. */
 enum { EVIS_SOFT_HOLD_REF = 1 };
 
-/* K in 1..EVIS_MAX_K (same for all envs), tau > 0, blend_mode EVIS_BLEND_*,
+/* K in 1..EVIS_MAX_K (same for all envs), tau > 0, blend_mode EVIS_BLEND_*
+ * (the gather warp only; a splat warp is EVIS_ERR_UNSUPPORTED),
  * C a DEVICE float array [n_envs] (> 0), gC a DEVICE float array [n_envs],
  * flags 0 or EVIS_SOFT_HOLD_REF. */
 int evis_soft_count_forward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_envs, int32_t K,

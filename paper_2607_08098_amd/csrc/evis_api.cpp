@@ -42,6 +42,8 @@ struct evis_ctx {
   DevBuf sched;       // xbegin[8][n + 1], env_order[n], n_items[8], queue counters (256 B apart)
   DevBuf src;         // float4[16 per 4x4 source block]: per-source splat records
   DevBuf tb;          // float4[per 4x4 source block]: motion bounds
+  DevBuf srcB;        // two-splat warps: B's splat records, same layout as src
+  DevBuf tbB;         // two-splat warps: bounds of -m_B per block
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
   std::vector<unsigned char> soft_shadow;
@@ -209,6 +211,14 @@ int check_times(evis_ctx* ctx, int64_t t0, int64_t t1, const char* who) {
   return EVIS_OK;
 }
 
+// blend_mode carries an EVIS_BLEND_* value or'ed with an EVIS_WARP_* value
+constexpr int kBlendMask = 0x0F, kWarpMask = 0x30;
+bool mode_word_ok(int m) {
+  const int b = m & kBlendMask, w = m & kWarpMask;
+  return (m & ~(kBlendMask | kWarpMask)) == 0 && (b == EVIS_BLEND_TIME || b == EVIS_BLEND_B_PRIMARY) &&
+         (w == EVIS_WARP_GATHER || w == EVIS_WARP_SPLAT || w == EVIS_WARP_JOINT);
+}
+
 int check_sensor(evis_ctx* ctx, const evis_sensor& s, const char* who, bool need_k) {
   const bool on_ok = s.theta_on ? aligned(s.theta_on, 4) : (s.C_on > 0.0f && std::isfinite(s.C_on));
   const bool off_ok = s.theta_off ? aligned(s.theta_off, 4) : (s.C_off > 0.0f && std::isfinite(s.C_off));
@@ -219,7 +229,7 @@ int check_sensor(evis_ctx* ctx, const evis_sensor& s, const char* who, bool need
     if (s.K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": K > 128");
     if (s.K <= 0 && (s.K_max < 1 || s.K_max > EVIS_MAX_K))
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": K_max must be in 1..128");
-    if (s.blend_mode != EVIS_BLEND_TIME && s.blend_mode != EVIS_BLEND_B_PRIMARY)
+    if (!mode_word_ok(s.blend_mode))
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown blend_mode");
   }
   return EVIS_OK;
@@ -252,7 +262,8 @@ EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st
   d.nty_src = (p.H + kSrcBlk - 1) / kSrcBlk;
   d.K_fixed = s.K > 0 ? s.K : 0;
   d.K_max = s.K_max;
-  d.blend = s.blend_mode;
+  d.blend = s.blend_mode & kBlendMask;
+  d.warp = s.blend_mode & kWarpMask;
   d.C_on = s.C_on;
   d.C_off = s.C_off;
   d.refr = s.refractory_us;
@@ -297,6 +308,13 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   if (rc) return rc;
   rc = ensure(ctx, ctx->tb, (size_t)src * 4 * sizeof(float4), &grew);
   if (rc) return rc;
+  const bool two = n > 0 && pl.desc[0].warp != EVIS_WARP_GATHER;   // one warp per plan
+  if (two) {
+    rc = ensure(ctx, ctx->srcB, (size_t)src * 4 * kBlkPx * sizeof(float4), &grew);
+    if (rc) return rc;
+    rc = ensure(ctx, ctx->tbB, (size_t)src * 4 * sizeof(float4), &grew);
+    if (rc) return rc;
+  }
   rc = ensure(ctx, ctx->dyn, (size_t)n * sizeof(EnvDyn), &grew);
   if (rc) return rc;
   rc = ensure(ctx, ctx->sched, sched_ints(n) * sizeof(int32_t), &grew);
@@ -309,6 +327,8 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
     const long long blk0 = 4LL * pl.src_prefix[e];
     pl.desc[e].src = static_cast<float4*>(ctx->src.p) + blk0 * kBlkPx;
     pl.desc[e].tb = static_cast<float4*>(ctx->tb.p) + blk0;
+    pl.desc[e].srcB = two ? static_cast<float4*>(ctx->srcB.p) + blk0 * kBlkPx : nullptr;
+    pl.desc[e].tbB = two ? static_cast<float4*>(ctx->tbB.p) + blk0 : nullptr;
     pl.desc[e].src_tile_base = pl.src_prefix[e];
   }
   return EVIS_OK;
@@ -359,12 +379,13 @@ int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileA
   ta.n_envs = n;
   ta.queue = sc.queue;
   ta.n_items = sc.n_items;
-  int occ = tile_occupancy(tw, th, mode);
+  const int warp = pl.desc.empty() ? EVIS_WARP_GATHER : pl.desc[0].warp;   // one warp per plan
+  int occ = tile_occupancy(tw, th, mode, warp);
   int per_cu = ctx->tuning.grid_mult > 0 ? std::min(ctx->tuning.grid_mult, occ) : occ;
   int grid = std::max(1, std::min(pl.items, per_cu * ctx->n_cu));
   {
     ProfScope ps(ctx, mode == MODE_STEP ? EVIS_KERNEL_STEP : EVIS_KERNEL_INTERP, s);
-    EVIS_HIP(launch_tile(tw, th, mode, ta, grid, s), "k_tile");
+    EVIS_HIP(launch_tile(tw, th, mode, warp, ta, grid, s), "k_tile");
   }
   return EVIS_OK;
 }
@@ -405,7 +426,8 @@ void evis_destroy(evis_ctx* ctx) {
     hipEventDestroy(r.e1);
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
-  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->src, &ctx->tb, &ctx->msq, &ctx->soft};
+  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn,  &ctx->sched, &ctx->src, &ctx->tb,
+                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {
@@ -479,7 +501,7 @@ int evis_interpolate(evis_ctx* ctx, const evis_pair* pair, int32_t K, int32_t j_
   if (K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_interpolate: K > 128");
   if (j_begin < 0 || j_end <= j_begin || j_end > K + 1)
     return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: need 0 <= j_begin < j_end <= K + 1");
-  if (blend_mode != EVIS_BLEND_TIME && blend_mode != EVIS_BLEND_B_PRIMARY)
+  if (!mode_word_ok(blend_mode))
     return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: unknown blend_mode");
   if (!L_out || !aligned(L_out, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_interpolate: L_out");
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
@@ -572,6 +594,8 @@ static int validate_envs(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, Pl
     if (v.env_id < 0 || v.env_id >= EVIS_MAX_ENVS)
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": env_id");
     pl.desc.push_back(make_desc(v.pair, v.sensor, v.state, v.env_id));
+    if (pl.desc.back().warp != pl.desc[0].warp)
+      return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": envs of one call need the same EVIS_WARP_*");
   }
   return EVIS_OK;
 }
@@ -593,10 +617,10 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
   if (!tu.use_graph || ctx->prof) return enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
 
   char key[256];
-  std::snprintf(key, sizeof(key), "%d|%d|%d|%p|%lld|%p|%p|%d|%d|%d|%d|%d|%d|%d", (int)pl.desc.size(),
+  std::snprintf(key, sizeof(key), "%d|%d|%d|%p|%lld|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d", (int)pl.desc.size(),
                 pl.src_total, pl.items, (void*)out, (long long)capacity, (void*)n_total,
                 (void*)K_used, flags & EVIS_FLAG_RESET_CURSOR, tu.tile_w, tu.tile_h, tu.grid_mult,
-                ta.list_cap, ta.static_tiles, (int)ctx->meta.bytes);
+                ta.list_cap, ta.static_tiles, (int)ctx->meta.bytes, pl.desc[0].warp);
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
     if (ctx->graphs.size() >= 512) drop_graphs(ctx);
@@ -679,8 +703,10 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
   if (K < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": K must be >= 1");
   if (K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": K > 128");
   if (!(tau > 0.0f) || !std::isfinite(tau)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": tau");
-  if (blend_mode != EVIS_BLEND_TIME && blend_mode != EVIS_BLEND_B_PRIMARY)
+  if (!mode_word_ok(blend_mode))
     return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown blend_mode");
+  if ((blend_mode & kWarpMask) != EVIS_WARP_GATHER)
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": the surrogate supports the gather warp only");
   if (!C || !aligned(C, 4)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": C");
   if (backward && (!gC || !aligned(gC, 4))) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": gC");
   if (flags & ~EVIS_SOFT_HOLD_REF) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": unknown flags");

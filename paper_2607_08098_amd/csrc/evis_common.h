@@ -43,13 +43,17 @@ struct EnvDesc {
   int32_t src_tile_base;       // prefix over envs of groups of four blocks (prep work units)
   int32_t K_fixed;             // > 0: fixed K
   int32_t K_max;
-  int32_t blend;
+  int32_t blend;               // EVIS_BLEND_*
   float C_on, C_off;
   int32_t refr;                // refractory period, us
   uint32_t env_bits;           // env_id << 23
   int64_t t0;
   int32_t span;                // t1 - t0 (us)
-  int32_t pad0;
+  int32_t warp;                // EVIS_WARP_*
+  float4* srcB;                // two-splat warps only (else null): (-m_B.x, -m_B.y, Zstart,
+                               // Z_B - Zstart) per source, Zstart = Z_A at p + m_B(p), same
+                               // layout as src
+  float4* tbB;                 // two-splat warps only: bounds of -m_B per block
 };
 
 // Per-environment values computed on the device each step.

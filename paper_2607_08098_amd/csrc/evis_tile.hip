@@ -16,12 +16,10 @@
 //           compacted by wave prefix sums into an LDS buffer that is
 //           appended to the global stream with one atomic per flush.
 // The sources that can reach a tile are found once per pair: the env's
-// 8x8 source tiles carry motion bounds (from the prep kernel), and each
+// 4x4 source blocks carry motion bounds (from the prep kernel), and each
 // candidate's interval of substeps [j_lo, j_hi] during which its footprint
 // can touch the tile is kept in an LDS list.
-#include "evis_internal.h"
-#include "evis_sink.h"
-#include "evis_warp.h"
+#include "evis_tile_kernel.h"
 
 namespace evis {
 
@@ -43,7 +41,10 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
 // (m_A.x, m_A.y, Z_A, Zend - Z_A), block-major, so that the splat reads one
 // 16-byte value per source and a block's 16 records are contiguous; the
 // block's bounds of m_A over sources with a finite motion vector; and the
-// env's largest finite |m|^2.
+// env's largest finite |m|^2.  For the two-splat warps also B's record
+// (-m_B.x, -m_B.y, Zstart, Z_B - Zstart), Zstart = Z_A at p + m_B(p)
+// (edge-clamped; Eq. 7 with p_A = p + m_B(p), p_B = p), and the block's
+// bounds of -m_B.
 __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ envs, EnvDyn* dyn,
                                                  const int32_t* __restrict__ src_prefix,
                                                  int n_envs, int total) {
@@ -99,6 +100,29 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
       const float sx = clamp_into((float)x[u] - ma[u].x, (float)(d.W - 1));
       const float sy = clamp_into((float)y[u] - ma[u].y, (float)(d.H - 1));
       zend[u] = bilinear(d.ZB, d.H, d.W, sx, sy);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const EnvDesc& d = envs[e[u]];
+      if (d.warp != EVIS_WARP_GATHER) {   // wave-uniform
+        const float zb = ldg(d.ZB, p[u]);
+        const float sx = clamp_into((float)x[u] + mb[u].x, (float)(d.W - 1));
+        const float sy = clamp_into((float)y[u] + mb[u].y, (float)(d.H - 1));
+        const float zs = bilinear(d.ZA, d.H, d.W, sx, sy);
+        float mnx = inf, mxx = -inf, mny = inf, mxy = -inf;
+        if (in[u] && finite32(mb[u].x) && finite32(mb[u].y)) {
+          mnx = mxx = -mb[u].x;
+          mny = mxy = -mb[u].y;
+        }
+        if (has[u])
+          stg(d.srcB, blk[u] * kBlkPx + r,
+              in[u] ? make_float4(-mb[u].x, -mb[u].y, zs, zb - zs) : make_float4(0.f, 0.f, 0.f, 0.f));
+        mnx = row16_min(mnx);
+        mxx = row16_max(mxx);
+        mny = row16_min(mny);
+        mxy = row16_max(mxy);
+        if (r == 0 && has[u]) stg(d.tbB, blk[u], make_float4(mnx, mxx, mny, mxy));
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -200,310 +224,6 @@ __global__ __launch_bounds__(EVIS_MAX_ENVS) void k_queue(const EnvDesc* __restri
 
 
 // ---------------------------------------------------------------------------
-// the persistent tile kernel
-// ---------------------------------------------------------------------------
-
-// Substeps go in pairs (j, j + 1) that share one splat pass (each source's
-// record is loaded once for both).  Per substep j: (1) issue the B-gather
-// loads of j; (2) at the first substep of a pair, splat j and j + 1 into LDS
-// z-buffers j & 3 and (j + 1) & 3, barrier; (3) read the winners of j
-// (clearing their cells) and issue the loads of their L_A; (4) blend and emit
-// substep j - 1, whose loads were issued one substep earlier.  The next pair
-// splats into the other two buffers, and the pair after it comes after the
-// next pair's barrier, so one barrier per pair suffices; emission takes none.
-template <int TW, int TH, int MODE>
-__global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
-  constexpr int NPX = TW * TH;
-  constexpr int PPT = NPX / kBlock;
-  static_assert(PPT * kBlock == NPX, "tile must be a multiple of the workgroup");
-  constexpr int EVB = (MODE == MODE_STEP) ? kEventBuf : 1;
-  constexpr int ZN = zcells<TW, TH>();
-  __shared__ unsigned long long zbuf[4 * ZN];
-  __shared__ uint32_t list[kListCapMax];
-  __shared__ uint32_t s_wl[kWavesPerBlock][kWave];   // per-wave packed active candidates
-  __shared__ uint2 evbuf[EVB];
-  __shared__ int s_evn, s_req[4];
-  __shared__ unsigned long long s_gbase;
-  __shared__ int s_item, s_rank, s_q, s_lcnt;
-  constexpr int AUXN = (MODE == MODE_STEP) ? NPX : 1;
-  __shared__ float s_con[AUXN], s_coff[AUXN];
-  __shared__ int s_tl[AUXN];
-
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const SinkShared sh{evbuf, &s_evn, s_req, &s_gbase, EVB};
-  const SinkOut so{a.out, a.capacity, a.cursor};
-  SinkRound sr;
-  sink_init(sh);
-  const int home = (int)(blockIdx.x % kXcd);
-  int qsel = 0;   // 0..kXcd-1: queues tried so far (own queue first, then stealing)
-  int rcur = 0;   // rank of the last item taken from the current queue
-
-  for (;;) {
-    __syncthreads();
-    if (MODE == MODE_STEP) sink_check(sh, so, sr);
-    // Readers clear the cells they read; apron cells and those of pixels
-    // outside the image are cleared here, once per item.
-    for (int i = tid; i < 4 * ZN; i += kBlock) zbuf[i] = kEmptyKey;
-    if (tid == 0) {
-      int item = -1, r = 0, q = -1;
-      while (qsel < kXcd) {
-        const int qq = (home + qsel) % kXcd;
-        const int it = (int)atomicAdd(&a.queue[qq * kQueueStride], 1u);
-        if (it < a.n_items[qq]) {
-          item = it;
-          q = qq;
-          break;
-        }
-        ++qsel;
-        rcur = 0;
-      }
-      if (item >= 0) {
-        // items of a queue are taken in increasing order: walk ranks forward
-        const int32_t* xb = a.xbegin + q * (a.n_envs + 1);
-        r = rcur;
-        while (r + 1 < a.n_envs && xb[r + 1] <= item) ++r;
-        rcur = r;
-      }
-      s_item = item;
-      s_rank = r;
-      s_q = q;
-      s_lcnt = 0;
-    }
-    __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(s_item);
-    if (item < 0) break;
-    const int rank = __builtin_amdgcn_readfirstlane(s_rank);
-    const int q = __builtin_amdgcn_readfirstlane(s_q);
-    const int env = __builtin_amdgcn_readfirstlane(a.env_order[rank]);
-    const EnvDesc d = a.envs[env];
-    const EnvDyn dy = a.dyn[env];
-    const int li = item - a.xbegin[q * (a.n_envs + 1) + rank];
-    const int H = d.H, W = d.W, K = dy.K;
-    const int row0 = q * dy.nty / kXcd;
-    const int tx = li % dy.ntx, ty = row0 + li / dy.ntx;
-    const int Tx0 = tx * TW, Ty0 = ty * TH;
-    const int Tx1 = min(Tx0 + TW, W) - 1, Ty1 = min(Ty0 + TH, H) - 1;
-
-    // per-pixel registers; pixel k of this thread is i = tid + k * kBlock,
-    // at (Tx0 + i % TW, Ty0 + i / TW)
-    float LAq[PPT], LBq[PPT], Lp[PPT], R[PPT];
-    float2 mBq[PPT];
-    uint32_t okbits = 0;
-    auto pix_x = [&](int k) { return Tx0 + (tid + k * kBlock) % TW; };
-    auto pix_y = [&](int k) { return Ty0 + (tid + k * kBlock) / TW; };
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int x = pix_x(k), y = pix_y(k);
-      const bool ok = (x <= Tx1) && (y <= Ty1);
-      const int qq = ok ? (y * W + x) : 0;
-      okbits |= (ok ? 1u : 0u) << k;
-      LAq[k] = ok ? ldg(d.LA, qq) : 0.0f;
-      LBq[k] = ok ? ldg(d.LB, qq) : 0.0f;
-      mBq[k] = ok ? ldg(d.mB, qq) : make_float2(0.0f, 0.0f);
-      Lp[k] = LAq[k];
-      R[k] = 0.0f;
-      if (MODE == MODE_STEP) {
-        const int i = tid + k * kBlock;
-        R[k] = ok ? ldg(d.Lref, qq) : 0.0f;
-        s_tl[i] = (ok && d.tlast) ? ldg(d.tlast, qq) : EVIS_T_LAST_INIT;
-        if (d.th_on) s_con[i] = ok ? ldg(d.th_on, qq) : 1.0f;
-        if (d.th_off) s_coff[i] = ok ? ldg(d.th_off, qq) : 1.0f;
-      }
-    }
-    const PixAux aux{(MODE == MODE_STEP && d.th_on) ? s_con : nullptr,
-                     (MODE == MODE_STEP && d.th_off) ? s_coff : nullptr, s_tl, d.C_on, d.C_off,
-                     Tx0, Ty0, TW, __builtin_ctz(TW), -1};
-
-    // Candidate source tiles and their substep intervals.
-    Window win{};
-    int nlist = 0;
-    bool overflow = false;
-    if (K > 1) {
-      nlist = build_candidates(d, dy, K, Tx0, Tx1, Ty0, Ty1, list, &s_lcnt, a.list_cap, win);
-      overflow = nlist > a.list_cap;
-    }
-
-    // Static tile: every source that can reach it does not move, it does not
-    // move in B and L_A == L_B on it, so every sub-frame equals L_A.
-    bool is_static = false;
-    if (MODE == MODE_STEP && a.static_tiles && K > 1 && !overflow) {
-      bool okst = true;
-      for (int e2 = tid; e2 < nlist; e2 += kBlock) {
-        const uint32_t ent = list[e2];
-        const float4 b = ldg(d.tb, cand_by(ent) * d.ntx_src + cand_bx(ent));
-        okst = okst && b.x == 0.0f && b.y == 0.0f && b.z == 0.0f && b.w == 0.0f;
-      }
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        if ((okbits >> k) & 1u) {
-          const int x = pix_x(k), y = pix_y(k);
-          const int x1 = min(x + 1, W - 1), y1 = min(y + 1, H - 1);
-          const float t1 = ldg(d.LB, y * W + x1), t2 = ldg(d.LB, y1 * W + x);
-          const float t3 = ldg(d.LB, y1 * W + x1);
-          okst = okst && mBq[k].x == 0.0f && mBq[k].y == 0.0f && LAq[k] == LBq[k] &&
-                 fabsf(LBq[k]) < 1e30f && fabsf(t1) < 1e30f && fabsf(t2) < 1e30f &&
-                 fabsf(t3) < 1e30f;
-        }
-      }
-      is_static = __syncthreads_and(okst ? 1 : 0) != 0;
-    }
-
-    int j_first = 1, j_last = K;
-    if (MODE == MODE_INTERP) {
-      if (a.j_begin == 0) {
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          if ((okbits >> k) & 1u) {
-            const int qq = pix_y(k) * W + pix_x(k);
-            a.L_out[qq] = LAq[k];
-            if (a.hole) a.hole[qq] = 0;
-          }
-        }
-      }
-      j_first = max(1, a.j_begin);
-      j_last = min(K, a.j_end - 1);
-    }
-
-    // Consumers of a finished sub-frame (substep jj, values Lj, holes hb).
-    auto consume = [&](int jj, const float (&Lj)[PPT], const uint32_t (&hb)[PPT]) {
-      if (MODE == MODE_STEP) {
-        emit_substep<PPT>(jj, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.refr, d.env_bits,
-                          sh, so, sr);
-      } else if (MODE == MODE_INTERP) {
-        const long long plane = (long long)H * W;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          if ((okbits >> k) & 1u) {
-            const long long o = (long long)(jj - a.j_begin) * plane + (pix_y(k) * W + pix_x(k));
-            a.L_out[o] = Lj[k];
-            if (a.hole) a.hole[o] = (uint8_t)hb[k];
-          }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) Lp[k] = Lj[k];
-    };
-
-    // pending interior substep (values whose loads were issued last iteration)
-    float pAh[PPT], pBh[PPT];
-    uint32_t phb[PPT];
-    float palpha = 0.0f;
-    bool pending = false;
-    int pj = 0;
-
-    auto finish_pending = [&]() {
-      float Lj[PPT];
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const bool vA = !(phb[k] & 1u), vB = !(phb[k] & 2u);
-        float v;
-        if (is_static) v = Lp[k];   // every sample of a static tile is L_A
-        else if (vA && vB) v = lerp32(pAh[k], pBh[k], palpha);
-        else if (vA) v = pAh[k];
-        else if (vB) v = pBh[k];
-        else {   // neither side: the pixel's own values (rare; read again, not kept in registers)
-          const int qq = ((okbits >> k) & 1u) ? pix_y(k) * W + pix_x(k) : 0;
-          v = lerp32(ldg(d.LA, qq), ldg(d.LB, qq), palpha);
-        }
-        Lj[k] = v;
-      }
-      consume(pj, Lj, phb);
-      pending = false;
-    };
-
-    const int j_int_last = min(j_last, K - 1);   // last interior substep to build
-    for (int j = j_first; j <= j_int_last; ++j) {
-      const float f = (float)j / (float)K;
-      const float g = 1.0f - f;
-      const float alpha = (d.blend == EVIS_BLEND_TIME) ? f : 1.0f;
-      float cAh[PPT], cBh[PPT];
-      uint32_t chb[PPT];
-      unsigned long long* zb = zbuf + (j & 3) * ZN;
-      const bool pair_start = ((j - j_first) & 1) == 0;   // uniform
-      if (!is_static) {
-        // (1) B-gather loads of substep j
-        BTaps bt[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) bt[k] = b_taps(d, pix_x(k), pix_y(k), mBq[k], g, (okbits >> k) & 1u);
-        // (2) splat substeps j and j + 1
-        if (pair_start) {
-          const int nf = (j + 1 <= j_int_last) ? 2 : 1;
-          const float fs[2] = {f, (float)(j + 1) / (float)K};
-          unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 3) * ZN};
-          splat_candidates<TW, 2>(d, list, nlist, overflow, win, K, j, nf, fs, Tx0, Tx1, Ty0,
-                                  Ty1, s_wl[wave], zs);
-          __syncthreads();
-          if (MODE == MODE_STEP) sink_check(sh, so, sr);
-        }
-        // (3) winners of substep j: issue their L_A loads; B values
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          const int i = tid + k * kBlock;
-          const int zi = zcell<TW>(i % TW, i / TW);
-          bool vA = false;
-          cAh[k] = 0.0f;
-          if ((okbits >> k) & 1u) {
-            const unsigned long long key = zb[zi];
-            zb[zi] = kEmptyKey;
-            vA = key != kEmptyKey;
-            if (vA) cAh[k] = ldg(d.LA, (int)(key & 0xFFFFFFFFull));
-          }
-          cBh[k] = bt[k].v ? b_value(bt[k]) : 0.0f;
-          chb[k] = (vA ? 0u : 1u) | (bt[k].v ? 0u : 2u);
-        }
-      } else {
-        if (pair_start) {
-          __syncthreads();
-          if (MODE == MODE_STEP) sink_check(sh, so, sr);
-        }
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-          cAh[k] = 0.0f;
-          cBh[k] = 0.0f;
-          chb[k] = 0u;
-        }
-      }
-      // (4) substep j - 1
-      if (pending) finish_pending();
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        pAh[k] = cAh[k];
-        pBh[k] = cBh[k];
-        phb[k] = chb[k];
-      }
-      palpha = alpha;
-      pj = j;
-      pending = true;
-    }
-    if (pending) finish_pending();
-    if (j_last == K) {
-      float Lj[PPT];
-      uint32_t hb[PPT];
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        Lj[k] = ((okbits >> k) & 1u) ? ldg(d.LB, pix_y(k) * W + pix_x(k)) : 0.0f;
-        hb[k] = 0u;
-      }
-      consume(K, Lj, hb);
-    }
-    if (MODE == MODE_INTERP) __syncthreads();
-
-    if (MODE == MODE_STEP) {
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        if ((okbits >> k) & 1u) {
-          const int qq = pix_y(k) * W + pix_x(k);
-          stg(d.Lref, qq, R[k]);
-          if (d.tlast) stg(d.tlast, qq, s_tl[tid + k * kBlock]);
-        }
-      }
-    }
-  }
-  if (MODE == MODE_STEP) sink_flush(sh, so);
-}
-
-
-// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -567,14 +287,17 @@ bool tile_shape_supported(int tw, int th) {
   return false;
 }
 
-hipError_t launch_tile(int tw, int th, int mode, const TileArgs& a, int grid, hipStream_t s) {
+hipError_t launch_tile(int tw, int th, int mode, int warp, const TileArgs& a, int grid,
+                       hipStream_t s) {
+  if (warp != EVIS_WARP_GATHER) return launch_tile_two(tw, th, mode, warp, a, grid, s);
 #define X(W_, H_) if (tw == W_ && th == H_) return launch_tile_shape<W_, H_>(mode, a, grid, s);
   EVIS_TILE_SHAPES(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-int tile_occupancy(int tw, int th, int mode) {
+int tile_occupancy(int tw, int th, int mode, int warp) {
+  if (warp != EVIS_WARP_GATHER) return tile_occupancy_two(tw, th, mode, warp);
   // Queried once per (shape, mode) and cached: no runtime query happens while
   // a launch sequence is being captured into a graph.
   static int cache[5][4] = {};

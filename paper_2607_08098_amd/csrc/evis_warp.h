@@ -3,6 +3,18 @@
 // depth-tested splat of those sources into an LDS z-buffer (Eq. 5 q_A,
 // bilinear footprint, Eq. 6, Eq. 7) and the bilinear gather of B at
 // s = q - (1 - f) m_B(q).
+//
+// The two-splat warps also splat B backward to q_B = p + (1 - f) m_B(p).
+// B's splat record holds -m_B, so that q_B = p - g (-m_B) with g = 1 - f is
+// the same arithmetic as A's q_A = p - f m_A (the negation is exact, so
+// the position is bit for bit p + g m_B), while the depth is still
+// interpolated at f from A's side (Z_A at p + m_B) to B's (Z_B at p).
+
+// Splat direction: A forward, B backward, or A forward with its keys
+// tagged (one z-buffer shared by both splats; a tagged key loses a depth
+// tie to B's).
+enum SplatDir { DIR_A = 0, DIR_B = 1, DIR_A_TAGGED = 2 };
+constexpr uint32_t kATag = 0x80000000u;   // tag bit in the low word of a key
 #pragma once
 
 #include "evis_internal.h"
@@ -38,9 +50,12 @@ __device__ __forceinline__ void lin_ge(float a, float bnd, float& flo, float& fh
 // 1/256 of a substep (far above K = 128 times the few-ulp error of the
 // reciprocal division for fractions in [0, 1]), so no source that can land
 // in the tile at substep j is ever left out.
+// With back = true the bounds are those of a backward splat, whose position
+// fraction is g = 1 - f: the interval [flo, fhi] of g maps to substeps
+// [K (1 - fhi), K (1 - flo)].
 __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy0, int Sy1,
                                               int Tx0, int Tx1, int Ty0, int Ty1, int K,
-                                              int& jlo, int& jhi) {
+                                              int& jlo, int& jhi, bool back = false) {
   if (!(b.x <= b.y) || !(b.z <= b.w)) return false;   // no finite source
   float flo = 0.0f, fhi = 1.0f;
   const float slack = 1.0f / 64.0f;
@@ -50,8 +65,9 @@ __device__ __forceinline__ bool substep_range(float4 b, int Sx0, int Sx1, int Sy
   lin_ge(b.w, (float)(Sy0 - Ty1 - 1) - slack, flo, fhi);
   if (!(flo <= fhi)) return false;
   const float Kf = (float)K;
-  const int lo = max(1, (int)ceilf(flo * Kf - (1.0f / 256.0f)));
-  const int hi = min(K - 1, (int)floorf(fhi * Kf + (1.0f / 256.0f)));
+  const float jl = back ? (1.0f - fhi) : flo, jh = back ? (1.0f - flo) : fhi;
+  const int lo = max(1, (int)ceilf(jl * Kf - (1.0f / 256.0f)));
+  const int hi = min(K - 1, (int)floorf(jh * Kf + (1.0f / 256.0f)));
   if (lo > hi) return false;
   jlo = lo;
   jhi = hi;
@@ -91,12 +107,13 @@ __device__ __forceinline__ int cand_jhi(uint32_t e) { return (int)(e & 0x7Fu); }
 // loads).  The loads of all slots are issued before any of them is used.
 constexpr int kChunk = 3;
 
-template <int TW, int NF>
+template <int TW, int NF, int DIR = DIR_A>
 __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&blk)[kChunk],
                                             const float (&fs)[NF], int nf, int Tx0, int Tx1,
                                             int Ty0, int Ty1, unsigned long long* const (&zs)[NF]) {
   const int r = threadIdx.x & (kBlkPx - 1);   // lane within the block: (r & 3, r >> 2)
-  float4 rec[kChunk];   // (m_A.x, m_A.y, Z_A, Zend - Z_A)
+  const float4* recs = (DIR == DIR_B) ? d.srcB : d.src;
+  float4 rec[kChunk];   // A: (m_A.x, m_A.y, Z_A, Zend - Z_A); B: (-m_B.x, -m_B.y, Zstart, Z_B - Zstart)
   int src[kChunk];      // source index, -1 outside the image or for an empty slot
   int sx[kChunk], sy[kChunk];
   // All loads first, unconditionally (a lane without a source reads record
@@ -109,7 +126,7 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
     sy[c] = by * kSrcBlk + (r >> 2);
     const bool ok = e != 0u && sx[c] < d.W && sy[c] < d.H;
     src[c] = ok ? sy[c] * d.W + sx[c] : -1;
-    rec[c] = ldg(d.src, ok ? (by * d.ntx_src + bx) * kBlkPx + r : 0);
+    rec[c] = ldg(recs, ok ? (by * d.ntx_src + bx) * kBlkPx + r : 0);
   }
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
@@ -119,8 +136,9 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
     for (int t = 0; t < NF; ++t) {
       if (t >= nf) break;   // uniform
       const float f = fs[t];
-      const float qx = px - f * rec[c].x;
-      const float qy = py - f * rec[c].y;
+      const float fp = (DIR == DIR_B) ? 1.0f - f : f;   // position fraction
+      const float qx = px - fp * rec[c].x;
+      const float qy = py - fp * rec[c].y;
       const float zt = rec[c].z + f * rec[c].w;
       if (!(zt > 0.0f)) continue;
       if (!(qx >= (float)(Tx0 - 1) && qx < (float)(Tx1 + 1) && qy >= (float)(Ty0 - 1) &&
@@ -128,7 +146,8 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
         continue;
       const float fx0 = floorf(qx), fy0 = floorf(qy);
       const bool bx = qx > fx0, by = qy > fy0;   // corners of strictly positive weight
-      const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | (uint32_t)src[c];
+      const uint32_t low = (DIR == DIR_A_TAGGED) ? ((uint32_t)src[c] | kATag) : (uint32_t)src[c];
+      const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | low;
       // Corner (x0, y0) always; a corner of zero weight repeats it instead
       // (the same key twice into one cell changes nothing), so the four
       // atomics need no branches.
@@ -189,9 +208,10 @@ struct Window {
 // which substeps.  A block whose positions over the whole gap (f in [0, 1])
 // stay clear of the tile by more than a pixel is rejected first, without
 // the divisions of substep_range (which rejects it too).
+template <bool BACK = false>
 __device__ __forceinline__ bool block_range(const EnvDesc& d, int bx, int by, int Tx0, int Tx1,
                                             int Ty0, int Ty1, int K, int& jlo, int& jhi) {
-  const float4 b = ldg(d.tb, by * d.ntx_src + bx);
+  const float4 b = ldg(BACK ? d.tbB : d.tb, by * d.ntx_src + bx);
   const int Sx0 = bx * kSrcBlk, Sx1 = min(bx * kSrcBlk + kSrcBlk - 1, d.W - 1);
   const int Sy0 = by * kSrcBlk, Sy1 = min(by * kSrcBlk + kSrcBlk - 1, d.H - 1);
   // q = p - f m over f in [0, 1] lies in [S0 - max(m_max, 0), S1 - min(m_min, 0)]
@@ -200,7 +220,7 @@ __device__ __forceinline__ bool block_range(const EnvDesc& d, int bx, int by, in
       (float)Sy0 - fmaxf(b.w, 0.0f) >= (float)(Ty1 + 2) ||
       (float)Sy1 - fminf(b.z, 0.0f) <= (float)(Ty0 - 2))
     return false;
-  return substep_range(b, Sx0, Sx1, Sy0, Sy1, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi);
+  return substep_range(b, Sx0, Sx1, Sy0, Sy1, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi, BACK);
 }
 
 // Candidate source blocks of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
@@ -233,18 +253,62 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
   return __builtin_amdgcn_readfirstlane(*count);
 }
 
+// Both directions' candidates (two-splat warps) in one list of cap entries:
+// A's from the front, B's from the back (B's entry e at cap - 1 - e).  One
+// 64-bit LDS counter holds A's count in its low and B's in its high word;
+// an entry is stored only if the two counts before its own increment leave
+// it room, which also keeps the two ends from meeting (of two entries
+// that would share a slot, the one counted second finds the list full).
+// *count must be zero on entry; nA and nB are uniform, and nA + nB > cap
+// means the list overflowed.  Holds a barrier.
+__device__ __forceinline__ void build_candidates_two(const EnvDesc& d, const EnvDyn& dy, int K,
+                                                     int Tx0, int Tx1, int Ty0, int Ty1,
+                                                     uint32_t* list, unsigned long long* count,
+                                                     int cap, Window& w, int& nA, int& nB) {
+  const int tid = threadIdx.x;
+  const int W = d.W, H = d.H;
+  const double M = __longlong_as_double((long long)dy.msq_bits);
+  const int Rw = (M > 1.0e12) ? (1 << 20) : ((int)ceil(sqrt(M)) + 3);
+  w.wx0 = max(0, Tx0 - Rw) / kSrcBlk;
+  w.wy0 = max(0, Ty0 - Rw) / kSrcBlk;
+  const int wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, W - 1) / kSrcBlk);
+  const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcBlk);
+  w.nwx = wx1 - w.wx0 + 1;
+  w.nwin = w.nwx * (wy1 - w.wy0 + 1);
+  for (int i = tid; i < w.nwin; i += kBlock) {
+    const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
+    int jlo, jhi;
+    if (block_range<false>(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi)) {
+      const unsigned long long old = atomicAdd(count, 1ull);
+      const int a = (int)(old & 0xFFFFFFFFull), b = (int)(old >> 32);
+      if (a + b < cap) list[a] = cand_entry(bx, by, jlo, jhi);
+    }
+    if (block_range<true>(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi)) {
+      const unsigned long long old = atomicAdd(count, 1ull << 32);
+      const int a = (int)(old & 0xFFFFFFFFull), b = (int)(old >> 32);
+      if (a + b < cap) list[cap - 1 - b] = cand_entry(bx, by, jlo, jhi);
+    }
+  }
+  __syncthreads();
+  const unsigned long long c = *count;
+  nA = __builtin_amdgcn_readfirstlane((int)(c & 0xFFFFFFFFull));
+  nB = __builtin_amdgcn_readfirstlane((int)(c >> 32));
+}
+
 // Splat every source that can reach the target tile at substeps j .. j+nf-1
 // (fractions fs, z-buffers zs): the candidate-list entries active at any of
 // them, or, if the list overflowed, the active blocks of the whole window.
 // Each wave takes every fourth entry, packs its active entries into its
 // 64-entry LDS slice `wl` and splats them four blocks (one per lane group)
-// per slot.
-template <int TW, int NF>
+// per slot.  Entry e sits at list[lbase + lstep * e] (lstep = -1 for the
+// backward splat's entries at the back of a shared list).
+template <int TW, int NF, int DIR = DIR_A>
 __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_t* list, int nlist,
                                                  bool overflow, const Window& w, int K, int j,
                                                  int nf, const float (&fs)[NF], int Tx0, int Tx1,
                                                  int Ty0, int Ty1, uint32_t* wl,
-                                                 unsigned long long* const (&zs)[NF]) {
+                                                 unsigned long long* const (&zs)[NF],
+                                                 int lbase = 0, int lstep = 1) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int g = lane >> 4;
   const int jz = j + nf - 1;
@@ -254,7 +318,7 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
       uint32_t ent = 0u;
       bool act = false;
       if (e2 < nlist) {
-        ent = lds_ld(list, e2);
+        ent = lds_ld(list, lbase + lstep * e2);
         act = (jz >= cand_jlo(ent)) && (j <= cand_jhi(ent));
       }
       const unsigned long long mask = __ballot(act);
@@ -267,7 +331,7 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
           const int i = s0 + c * 4 + g;
           blk[c] = (i < nact) ? lds_ld(wl, i) : 0u;
         }
-        splat_chunk<TW, NF>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
+        splat_chunk<TW, NF, DIR>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
       }
     }
   } else {
@@ -280,10 +344,11 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
       if (i < w.nwin) {
         const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
         int jlo, jhi;
-        if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && jz >= jlo && j <= jhi)
+        if (block_range<DIR == DIR_B>(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && jz >= jlo &&
+            j <= jhi)
           blk[0] = cand_entry(bx, by, jlo, jhi);
       }
-      splat_chunk<TW, NF>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
+      splat_chunk<TW, NF, DIR>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
     }
   }
 }

@@ -24,6 +24,9 @@ EVIS_ERR_HIP = -3
 EVIS_ERR_NOMEM = -4
 EVIS_BLEND_TIME = 0
 EVIS_BLEND_B_PRIMARY = 1
+EVIS_WARP_GATHER = 0x00       # or'ed with an EVIS_BLEND_* into the mode word
+EVIS_WARP_SPLAT = 0x10
+EVIS_WARP_JOINT = 0x20
 EVIS_FLAG_RESET_CURSOR = 1
 EVIS_T_LAST_INIT = -(2 ** 30)
 EVIS_MAX_CROSSINGS = 65535

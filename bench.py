@@ -14,8 +14,10 @@ Printed: one JSON line.  value = Mpix-substeps/s (sum over envs of H*W*K
 per step / step time); events/s beside it; the per-env-launch plain form
 (interpolate every sub-frame to HBM, then emit, env by env) and the per-env
 fused form on the same GPU; the roofline of the fused tile kernel, timed
-live with HIP events; the CPU oracle on a bounded sample of the same
-workload (rank 0, N = 1 only).
+live with HIP events; the same kernel with B splatted backward (the
+two-splat warps: own z-buffer with B primary, and one joint z-buffer);
+the CPU oracle on a bounded sample of the same workload (rank 0, N = 1
+only).
 """
 from __future__ import annotations
 
@@ -37,12 +39,16 @@ if ROOT not in sys.path:
 # reference level read and written, 8 B) plus 8 B per event.
 OPS_INTERIOR = 46
 OPS_LAST = 4
+# The two-splat warps: B splatted backward instead of gathered: two splats
+# (~14 each), two resolves (~2 each), blend ~5 and emission ~4.
+OPS_INTERIOR_TWO_SPLAT = 41
 BYTES_PER_PX = 40
 BYTES_PER_EVENT = 8
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # plain VALU lane-ops: 39.3 T/s
 HBM_PEAK_GBS = 8000.0
 
-KERNEL_SOURCES = ["evis_common.h", "evis_internal.h", "evis_sink.h", "evis_warp.h", "evis_tile.hip"]
+KERNEL_SOURCES = ["evis_common.h", "evis_internal.h", "evis_sink.h", "evis_warp.h", "evis_tile_kernel.h",
+                  "evis_tile.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_tile_step_mixed64.json")
 
 
@@ -64,6 +70,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
+    ap.add_argument("--warp-steps", type=int, default=10,
+                    help="timed steps of each two-splat warp (0 skips them)")
     ap.add_argument("--disc-steps", type=int, default=200,
                     help="steps of the 512-disc sustained run reported beside the metric (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -324,6 +332,34 @@ def main():
     roof["hbm_algorithmic_GBps"] = round(bytes_ / (tile_ms_avg / 1e3) / 1e9, 1)
     log(f"tile kernel {tile_ms_avg:.3f} ms; roofline {roof}")
 
+    # the two-splat warps on the same batch and tile shape
+    warps = None
+    if args.warp_steps > 0:
+        warps = {}
+        for name, mode in (("splat_b_primary", evis.EVIS_WARP_SPLAT | evis.EVIS_BLEND_B_PRIMARY),
+                           ("joint", evis.EVIS_WARP_JOINT)):
+            warr = evis.env_array(batch.env_dicts(dict(sensor, blend_mode=mode)))
+            for _ in range(2):
+                n_total.zero_()
+                evis.evis_step_batch(ctx, warr, out, n_total, K_used, 0)
+            torch.cuda.synchronize()
+            evis.evis_profile_enable(ctx, True)
+            n_total.zero_()
+            for _ in range(args.warp_steps):
+                evis.evis_step_batch(ctx, warr, out, n_total, K_used, 0)
+            torch.cuda.synchronize()
+            wms, wl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
+            evis.evis_profile_enable(ctx, False)
+            wms /= max(wl, 1)
+            wops = float((px * (OPS_INTERIOR_TWO_SPLAT * (Ks - 1) + OPS_LAST)).sum())
+            wach = wops / (wms / 1e3) / 1e12
+            warps[name] = dict(kernel_ms=round(wms, 4), value=round(mpix_substeps / (wms / 1e3), 1),
+                               events_per_step=round(int(n_total.item()) / max(wl, 1), 1),
+                               roofline=dict(bound="alu", achieved=round(wach, 3),
+                                             peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
+                                             frac=round(wach / ALU_PEAK_TOPS, 4)))
+            log(f"warp {name}: tile kernel {wms:.3f} ms")
+
     # per-env-launch plain form: every sub-frame to HBM, then the event model
     plain = None
     fused_per_env = None
@@ -390,7 +426,7 @@ def main():
         events_per_s=round(events_per_s, 1), events_per_step=round(events_total / args.steps, 1),
         per_env_plain=plain, per_env_fused=fused_per_env,
         batched_vs_plain=(round(value / plain["value"], 2) if plain else None),
-        roofline=roof, cpu_baseline=cpu, disc512_sustained=disc,
+        roofline=roof, cpu_baseline=cpu, two_splat_warps=warps, disc512_sustained=disc,
     )
     print(json.dumps(rec))
     ctx.close()

@@ -60,14 +60,14 @@ Readings of the paper taken here (each is restated where it is used):
       the previous and the current sample; integer microseconds, floor.
   R11 lerp(a, b, w) = a + w * (b - a); bilinear = two lerps along x, one
       along y; x1 = min(x0 + 1, W - 1).
-  R12 two-splat warp (WARP_SPLAT): B is splatted backward to
+  R18 two-splat warp (WARP_SPLAT): B is splatted backward to
       q_B = p + (1 - f) m_B(p) with Eq. 7 endpoints p_A = p + m_B(p),
       p_B = p (Z_A sampled bilinearly at p_A, clamped into the image), the
       same footprint, tie rule and visibility as A's splat, into a z-buffer
       of its own; B^ is L_B at B's winner (valid where a B source landed)
       and the blend is R2's.  With BLEND_B_PRIMARY this is the paper's
       fusion: B's splat is the result and A fills only B's holes.
-  R13 joint warp (WARP_JOINT): one z-buffer over the sources of both
+  R19 joint warp (WARP_JOINT): one z-buffer over the sources of both
       splats (Eq. 6 with X in {A, B}); at equal depth B wins (B is the
       primary keyframe), then the smaller index.  The winner's own
       intensity is the sub-frame; where nothing lands, R2's hole value.
@@ -89,12 +89,12 @@ N_MAX = 65535                 # R8: crossings per pixel-substep are capped here
 T_LAST_INIT = -(2 ** 30)      # "never fired": far enough back for any refractory period
 BLEND_TIME = 0
 BLEND_B_PRIMARY = 1
-# Warp of B, or'ed into the mode word next to the blend: R1, R12, R13.
+# Warp of B, or'ed into the mode word next to the blend: R1, R18, R19.
 WARP_GATHER = 0x00
 WARP_SPLAT = 0x10
 WARP_JOINT = 0x20
 WARP_MASK = 0x30
-A_TAG = np.uint64(0x8000_0000)    # R13: marks an A source in a joint key (B wins ties)
+A_TAG = np.uint64(0x8000_0000)    # R19: marks an A source in a joint key (B wins ties)
 REC709 = (0.2126, 0.7152, 0.0722)
 
 
@@ -250,11 +250,11 @@ def splat_forward(m_A, Z_A, Zend, f) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# backward splat of B (Eq. 5 q_B, Eq. 6, Eq. 7; R12, R13)
+# backward splat of B (Eq. 5 q_B, Eq. 6, Eq. 7; R18, R19)
 # ---------------------------------------------------------------------------
 
 def start_depth(Z_A: np.ndarray, m_B: np.ndarray) -> np.ndarray:
-    """Z_A at p_A = p + m_B(p), position clamped into the image (R12)."""
+    """Z_A at p_A = p + m_B(p), position clamped into the image (R18)."""
     H, W = Z_A.shape
     px, py = pixel_coords(H, W)
     sx = clamp_into(px + m_B[..., 0], W - 1)
@@ -277,7 +277,7 @@ def splat_keys_backward(m_B, Z_B, Zstart, f):
 
 
 def splat_backward(m_B, Z_B, Zstart, f) -> np.ndarray:
-    """Eq. 6 z-buffer of B splatted back to fraction f (R12)."""
+    """Eq. 6 z-buffer of B splatted back to fraction f (R18)."""
     H, W = Z_B.shape
     qx, qy, zt, key = splat_keys_backward(m_B, Z_B, Zstart, f)
     zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
@@ -286,7 +286,7 @@ def splat_backward(m_B, Z_B, Zstart, f) -> np.ndarray:
 
 
 def splat_joint(m_A, Z_A, Zend, m_B, Z_B, Zstart, f) -> np.ndarray:
-    """One z-buffer over the sources of both splats (R13): A keys carry
+    """One z-buffer over the sources of both splats (R19): A keys carry
     A_TAG in their low word, so B wins at equal depth."""
     H, W = Z_A.shape
     zbuf = np.full(H * W, EMPTY_KEY, dtype=np.uint64)
@@ -328,9 +328,9 @@ def resolve_gather_blend(zbuf, L_A, L_B, m_B, f, alpha):
 
 
 def resolve_two_splat(zA, zB, L_A, L_B, alpha):
-    """Intermediate log frame from the winners of the two splats (R12):
+    """Intermediate log frame from the winners of the two splats (R18):
     A^ = L_A at A's winner, B^ = L_B at B's winner, blend per R2.  Pass the
-    joint z-buffer as zA and None as zB for R13.  Returns (L_f, validA,
+    joint z-buffer as zA and None as zB for R19.  Returns (L_f, validA,
     validB)."""
     H, W = L_A.shape
     low = np.uint64(0xFFFF_FFFF)

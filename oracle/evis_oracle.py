@@ -26,6 +26,9 @@ in NVIDIA Isaac Sim".  Steps, in the paper's order:
                          reference update), Eq. 8 threshold mismatch, the
                          refractory period of Sec. "Sensor Calibration and
                          Non-idealities"
+  noise_events           leak events, shot noise and hot pixels of Sec.
+                         "Sensor Calibration and Non-idealities", drawn
+                         from a Philox4x32-10 counter-based generator
   pack_events            the (x, y, t, p) event tuple of Sec. "Problem
                          Formulation" as an 8-byte record
   step / interpolate     the whole per-pair path
@@ -67,6 +70,24 @@ Readings of the paper taken here (each is restated where it is used):
       of its own; B^ is L_B at B's winner (valid where a B source landed)
       and the blend is R2's.  With BLEND_B_PRIMARY this is the paper's
       fusion: B's splat is the result and A fills only B's holes.
+  R20 noise draws: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel
+      random numbers: as easy as 1, 2, 3", SC 2011), key = the 64-bit
+      seed (low word first), counter = (x | y << 11, j, pair index, kind);
+      kind 0 gives the three decisions of pixel-substep (x, y, j), kinds
+      1-3 the time (and polarity) of a leak / shot / hot event there,
+      kind 4 with j = pair = 0 the pixel's hot-pixel membership.  A word
+      w becomes the float32 uniform (w >> 8) 2^-24 in [0, 1).
+  R21 per substep of length Dt (float32 us; Dt_s = Dt * 1e-6 in float32):
+      P_leak = r_l Dt_s, P_shot = (r_s Dt_s)(1 - I), P_hot = r_h Dt_s; an
+      event fires when its uniform is < P (float32 compare).  I, the
+      normalised intensity, is clamp((L_j - L0) * inv_range) into [0, 1]
+      (NaN -> 0) of the current log sample: a per-camera affine map of log
+      intensity (the library carries log intensity only).
+  R22 a noise event's time is t0 + min(floor((j - 1 + u) Dt), span) with its
+      own uniform u; leak events are ON, shot and hot events take the
+      polarity bit 0 of their second word (1 = ON).
+  R23 noise events are extra: they do not move L_ref, ignore the
+      refractory period and leave t_last alone.
   R19 joint warp (WARP_JOINT): one z-buffer over the sources of both
       splats (Eq. 6 with X in {A, B}); at equal depth B wins (B is the
       primary keyframe), then the smaller index.  The winner's own
@@ -430,6 +451,7 @@ class Sensor:
     K: int = 8                                # > 0 fixed, <= 0 adaptive
     K_max: int = 64
     blend_mode: int = BLEND_TIME
+    noise: Optional["Noise"] = None           # leak / shot / hot-pixel events (R20-R23)
 
     def thresholds(self, H, W):
         on = self.theta_on if self.theta_on is not None else np.full((H, W), F32(self.C_on))
@@ -535,6 +557,90 @@ def emit_events(S_seq, t0_us, t1_us, sensor: Sensor, L_ref, t_last=None, env_id=
 
 
 # ---------------------------------------------------------------------------
+# noise events (Sec. "Sensor Calibration and Non-idealities"; R20-R23)
+# ---------------------------------------------------------------------------
+
+PHILOX_M = (np.uint64(0xD2511F53), np.uint64(0xCD9E8D57))   # round multipliers
+PHILOX_W = (np.uint64(0x9E3779B9), np.uint64(0xBB67AE85))   # key increments
+_M32 = np.uint64(0xFFFF_FFFF)
+
+
+def philox4x32(ctr, key, rounds: int = 10):
+    """Philox4x32-R of Salmon et al. (SC 2011), elementwise over numpy
+    arrays: ctr four uint32 words, key two; returns four uint32 arrays.
+    Round: (hi(M0 c0), lo(M0 c0)) and (hi(M1 c2), lo(M1 c2)); the new
+    counter is (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key grows by
+    the Weyl increments before every round after the first."""
+    c0, c1, c2, c3 = [np.asarray(c, np.uint64) & _M32 for c in ctr]
+    k0, k1 = [np.asarray(k, np.uint64) & _M32 for k in key]
+    for r in range(rounds):
+        if r > 0:
+            k0 = (k0 + PHILOX_W[0]) & _M32
+            k1 = (k1 + PHILOX_W[1]) & _M32
+        p0 = PHILOX_M[0] * c0            # < 2^64: exact in uint64
+        p1 = PHILOX_M[1] * c2
+        c0, c1, c2, c3 = ((p1 >> np.uint64(32)) ^ c1 ^ k0, p1 & _M32,
+                          (p0 >> np.uint64(32)) ^ c3 ^ k1, p0 & _M32)
+    return [c.astype(np.uint32) for c in (c0, c1, c2, c3)]
+
+
+def uniform24(w):
+    """R20: the top 24 bits of a uint32 word as a float32 in [0, 1)."""
+    return (np.asarray(w, np.uint32) >> np.uint32(8)).astype(F32) * F32(2.0 ** -24)
+
+
+@dataclass
+class Noise:
+    """Per-camera noise parameters (rates in events per second)."""
+    leak_rate_hz: float = 0.0
+    shot_rate_hz: float = 0.0
+    hot_rate_hz: float = 0.0
+    hot_fraction: float = 0.0
+    shot_L0: float = 0.0           # log intensity whose normalised intensity is 0
+    shot_inv_range: float = 1.0    # normalised intensity per unit of log intensity
+    seed: int = 0                  # 64-bit generator key
+    pair_index: int = 0            # which keyframe pair (a counter word)
+
+
+def hot_pixels(H, W, nz: Noise) -> np.ndarray:
+    """R20: the fixed hot-pixel set, one draw per pixel."""
+    ux, uy = pixel_coords(H, W)
+    xy = ux.astype(np.uint64) | (uy.astype(np.uint64) << np.uint64(11))
+    key = (nz.seed & 0xFFFF_FFFF, (nz.seed >> 32) & 0xFFFF_FFFF)
+    w = philox4x32((xy, 0, 0, 4), key)[0]
+    return uniform24(w) < F32(nz.hot_fraction)
+
+
+def noise_events(j, cur, Dt, t0_us, span, nz: Noise, env_id, log: EventLog, hot=None):
+    """Leak, shot and hot-pixel events of substep j (R20-R23); cur is the
+    log sample L_j.  Appends to log; touches no state."""
+    H, W = cur.shape
+    ux, uy = pixel_coords(H, W)
+    xy = ux.astype(np.uint64) | (uy.astype(np.uint64) << np.uint64(11))
+    key = (nz.seed & 0xFFFF_FFFF, (nz.seed >> 32) & 0xFFFF_FFFF)
+    w0, w1, w2, _ = philox4x32((xy, j, nz.pair_index, 0), key)
+    dts = F32(Dt) * F32(1e-6)
+    p_leak = F32(nz.leak_rate_hz) * dts
+    ibar = (cur - F32(nz.shot_L0)) * F32(nz.shot_inv_range)
+    ibar = np.where(ibar > 0, ibar, F32(0))
+    ibar = np.where(ibar < 1, ibar, F32(1)).astype(F32)
+    p_shot = (F32(nz.shot_rate_hz) * dts) * (F32(1) - ibar)
+    p_hot = F32(nz.hot_rate_hz) * dts
+    if hot is None:
+        hot = hot_pixels(H, W, nz)
+    fires = ((1, uniform24(w0) < p_leak), (2, uniform24(w1) < p_shot),
+             (3, hot & (uniform24(w2) < p_hot)))
+    for kind, fire in fires:
+        for flat in np.flatnonzero(fire):
+            y, x = divmod(int(flat), W)
+            e0, e1, _, _ = philox4x32((np.uint64(x | (y << 11)), j, nz.pair_index, kind), key)
+            v = (F32(j - 1) + uniform24(e0)) * F32(Dt)
+            t = t0_us + min(int(np.floor(v)), span)
+            pol = 1 if kind == 1 else int(e1) & 1
+            log.add(x, y, t, pol, env_id)
+
+
+# ---------------------------------------------------------------------------
 # The whole per-pair path
 # ---------------------------------------------------------------------------
 
@@ -557,9 +663,13 @@ def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0):
     span = pair.t1_us - pair.t0_us
     log = EventLog()
     prev = pair.L_A.astype(F32)
+    nz = sensor.noise
+    hot = hot_pixels(H, W, nz) if nz is not None else None
     for j, L, _ in substep_frames(pair, K, range(1, K + 1), sensor.blend_mode):
         emit_substep(j, prev, L, R, tl, on, off, sensor.refractory_us, pair.t0_us, Dt,
                      span, env_id, log, track)
+        if nz is not None:
+            noise_events(j, L, Dt, pair.t0_us, span, nz, env_id, log, hot)
         prev = L
     return log.array(), R, (tl.astype(np.int32) if track else None), K
 

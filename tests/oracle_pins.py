@@ -583,6 +583,103 @@ def pin_crossing_count_exact(o):
 
 
 # ---------------------------------------------------------------------------
+# noise events
+# ---------------------------------------------------------------------------
+
+def pin_philox_kat(o):
+    """The generator against its published known-answer vectors."""
+    n = 0
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            ctr, key, want = [[int(w, 16) for w in part.split()] for part in line.split("|")]
+            got = [int(v) for v in o.philox4x32(ctr, key)]
+            assert got == want, (ctr, key, [hex(v) for v in got])
+            n += 1
+    assert n == 3
+
+
+def _flat_pair(o, H, W, L, K, t1=16667):
+    pair = zero_motion_pair(o, np.full((H, W), F32(L)), np.full((H, W), F32(L)), t1=t1)
+    return pair
+
+
+def _binomial_ok(count, n, p, z=5.0):
+    mean = n * p
+    sd = math.sqrt(n * p * (1 - p))
+    return abs(count - mean) <= z * sd + 1, (count, mean, sd)
+
+
+def pin_leak_rate(o):
+    """Leak events alone on constant frames: ON only, inside the pair, and
+    their number a Binomial(pixels x substeps, r_l Dt) draw."""
+    H, W, K = 64, 64, 10
+    pair = _flat_pair(o, H, W, 0.5, K)
+    nz = o.Noise(leak_rate_hz=20.0, seed=0x1234_5678_9ABC_DEF0, pair_index=3)
+    ev, R, _, _ = o.step(pair, o.Sensor(K=K, noise=nz), pair.L_A.copy())
+    assert np.array_equal(R, pair.L_A)                     # R23: the reference stays
+    p = 20.0 * (16667 / K) * 1e-6
+    ok, info = _binomial_ok(len(ev), H * W * K, p)
+    assert ok, info
+    assert len(ev) > 50 and np.all(ev[:, 3] == 1)
+    assert ev[:, 2].min() >= 0 and ev[:, 2].max() <= 16667
+    # each substep holds its share: times fall in K equal bins about evenly
+    bins = np.bincount(np.minimum(ev[:, 2] * K // 16667, K - 1), minlength=K)
+    assert bins.min() > 0
+
+
+def pin_shot_darkness(o):
+    """Shot noise alone: none where the normalised intensity is 1, the full
+    rate where it is 0, polarity about even."""
+    H, W, K = 48, 64, 8
+    L = np.zeros((H, W), F32)
+    L[:, W // 2:] = 3.0                                       # normalised intensity 1 there
+    pair = zero_motion_pair(o, L, L.copy())
+    nz = o.Noise(shot_rate_hz=3000.0, shot_L0=0.0, shot_inv_range=1.0 / 3.0, seed=99)
+    ev, _, _, _ = o.step(pair, o.Sensor(K=K, noise=nz), L.copy())
+    assert np.all(ev[:, 0] < W // 2)
+    p = 3000.0 * (1000 / K) * 1e-6
+    ok, info = _binomial_ok(len(ev), H * (W // 2) * K, p)
+    assert ok, info
+    ok, info = _binomial_ok(int(ev[:, 3].sum()), len(ev), 0.5)
+    assert ok, info
+
+
+def pin_hot_pixels(o):
+    """Hot pixels alone: a fixed set of about the asked share of pixels,
+    every event on it, at the hot rate."""
+    H, W, K = 64, 80, 6
+    pair = _flat_pair(o, H, W, 1.0, K, t1=60000)
+    nz = o.Noise(hot_rate_hz=20.0, hot_fraction=0.05, seed=7)
+    hot = o.hot_pixels(H, W, nz)
+    ok, info = _binomial_ok(int(hot.sum()), H * W, 0.05)
+    assert ok, info
+    ev, _, _, _ = o.step(pair, o.Sensor(K=K, noise=nz), pair.L_A.copy())
+    assert len(ev) > 0 and np.all(hot[ev[:, 1], ev[:, 0]])
+    p = 20.0 * (60000 / K) * 1e-6
+    ok, info = _binomial_ok(len(ev), int(hot.sum()) * K, p)
+    assert ok, info
+
+
+def pin_noise_off_and_seeded(o):
+    """Zero rates add nothing; the same seed and pair index give the same
+    events, another pair index other events."""
+    pair = _random_pair(o, 43)
+    base, _, _, _ = o.step(pair, o.Sensor(K=5), pair.L_A.copy())
+    off, _, _, _ = o.step(pair, o.Sensor(K=5, noise=o.Noise(seed=5)), pair.L_A.copy())
+    assert np.array_equal(o.canonical(base), o.canonical(off))
+    nz = o.Noise(leak_rate_hz=40.0, shot_rate_hz=40.0, seed=5, pair_index=1)
+    a, _, _, _ = o.step(pair, o.Sensor(K=5, noise=nz), pair.L_A.copy())
+    b, _, _, _ = o.step(pair, o.Sensor(K=5, noise=nz), pair.L_A.copy())
+    nz2 = o.Noise(leak_rate_hz=40.0, shot_rate_hz=40.0, seed=5, pair_index=2)
+    c, _, _, _ = o.step(pair, o.Sensor(K=5, noise=nz2), pair.L_A.copy())
+    assert np.array_equal(o.canonical(a), o.canonical(b)) and len(a) > len(base)
+    assert not np.array_equal(o.canonical(a), o.canonical(c))
+
+
+# ---------------------------------------------------------------------------
 # event record
 # ---------------------------------------------------------------------------
 

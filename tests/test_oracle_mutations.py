@@ -193,6 +193,44 @@ def m_two_splat_b_everywhere(zA, zB, L_A, L_B, alpha):
     return o.__dict__["_orig_rts"](zA, zB, L_A, L_B, alpha)
 
 
+def m_philox_multipliers_swapped(ctr, key, rounds=10):
+    saved = o.PHILOX_M
+    o.PHILOX_M = (saved[1], saved[0])              # planted: multipliers swapped
+    try:
+        return o.__dict__["_orig_philox"](ctr, key, rounds)
+    finally:
+        o.PHILOX_M = saved
+
+
+def _noise_variant(dt_us=False, bright=False, leak_pol=False):
+    def noise(j, cur, Dt, t0_us, span, nz, env_id, log, hot=None):
+        H, W = cur.shape
+        ux, uy = o.pixel_coords(H, W)
+        xy = ux.astype(np.uint64) | (uy.astype(np.uint64) << np.uint64(11))
+        key = (nz.seed & 0xFFFF_FFFF, (nz.seed >> 32) & 0xFFFF_FFFF)
+        w0, w1, w2, _ = o.philox4x32((xy, j, nz.pair_index, 0), key)
+        dts = F32(Dt) if dt_us else F32(Dt) * F32(1e-6)       # planted: microseconds
+        ibar = (cur - F32(nz.shot_L0)) * F32(nz.shot_inv_range)
+        ibar = np.where(ibar > 0, ibar, F32(0))
+        ibar = np.where(ibar < 1, ibar, F32(1)).astype(F32)
+        shade = ibar if bright else (F32(1) - ibar)              # planted: brighter fires more
+        p_shot = (F32(nz.shot_rate_hz) * dts) * shade
+        if hot is None:
+            hot = o.hot_pixels(H, W, nz)
+        fires = ((1, o.uniform24(w0) < F32(nz.leak_rate_hz) * dts),
+                 (2, o.uniform24(w1) < p_shot),
+                 (3, hot & (o.uniform24(w2) < F32(nz.hot_rate_hz) * dts)))
+        for kind, fire in fires:
+            for flat in np.flatnonzero(fire):
+                y, x = divmod(int(flat), W)
+                e0, e1, _, _ = o.philox4x32((np.uint64(x | (y << 11)), j, nz.pair_index, kind), key)
+                v = (F32(j - 1) + o.uniform24(e0)) * F32(Dt)
+                t = t0_us + min(int(np.floor(v)), span)
+                pol = 1 if (kind == 1 and not leak_pol) else int(e1) & 1   # planted: random leak
+                log.add(x, y, t, pol, env_id)
+    return noise
+
+
 def m_pack_shift(ev):
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     word = ev[:, 0] | (ev[:, 1] << 12) | (ev[:, 3] << 22) | (ev[:, 4] << 23)   # planted
@@ -223,6 +261,10 @@ MUTANTS = [
     ("joint_a_wins_ties", "splat_joint", m_joint_a_first, P.pin_joint_priority),
     ("two_splat_b_everywhere", "resolve_two_splat", m_two_splat_b_everywhere,
      P.pin_two_splat_layers),
+    ("philox_multipliers_swapped", "philox4x32", m_philox_multipliers_swapped, P.pin_philox_kat),
+    ("noise_rate_in_microseconds", "noise_events", _noise_variant(dt_us=True), P.pin_leak_rate),
+    ("shot_noise_brighter_fires", "noise_events", _noise_variant(bright=True), P.pin_shot_darkness),
+    ("leak_random_polarity", "noise_events", _noise_variant(leak_pol=True), P.pin_leak_rate),
 ]
 
 
@@ -239,6 +281,7 @@ def test_pin_catches_mutant(monkeypatch, name, attr, mutant, pin):
     monkeypatch.setitem(o.__dict__, "_orig_cto", o.crossing_time_offset)
     monkeypatch.setitem(o.__dict__, "_orig_skb", o.splat_keys_backward)
     monkeypatch.setitem(o.__dict__, "_orig_rts", o.resolve_two_splat)
+    monkeypatch.setitem(o.__dict__, "_orig_philox", o.philox4x32)
     monkeypatch.setattr(o, attr, mutant)
     with pytest.raises((AssertionError, IndexError, ValueError)):
         pin(o)

@@ -15,7 +15,8 @@ per step / step time); events/s beside it; the per-env-launch plain form
 (interpolate every sub-frame to HBM, then emit, env by env) and the per-env
 fused form on the same GPU; the roofline of the fused tile kernel, timed
 live with HIP events; the same kernel with B splatted backward (the
-two-splat warps: own z-buffer with B primary, and one joint z-buffer);
+two-splat warps: own z-buffer with B primary, and one joint z-buffer) and
+with sensor noise (leak 0.1 Hz, shot 1 Hz, 0.1% hot pixels at 100 Hz);
 the CPU oracle on a bounded sample of the same workload (rank 0, N = 1
 only).
 """
@@ -42,6 +43,10 @@ OPS_LAST = 4
 # The two-splat warps: B splatted backward instead of gathered: two splats
 # (~14 each), two resolves (~2 each), blend ~5 and emission ~4.
 OPS_INTERIOR_TWO_SPLAT = 41
+# Sensor noise adds one Philox4x32-10 draw per pixel-substep (10 rounds of
+# two 32-bit high and low products, four xors and the key update, 98
+# lane-ops) and ~10 for the three decisions.
+OPS_NOISE = 108
 BYTES_PER_PX = 40
 BYTES_PER_EVENT = 8
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # plain VALU lane-ops: 39.3 T/s
@@ -71,7 +76,7 @@ def parse():
     ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
     ap.add_argument("--warp-steps", type=int, default=10,
-                    help="timed steps of each two-splat warp (0 skips them)")
+                    help="timed steps of each variant: two-splat warps, noise (0 skips them)")
     ap.add_argument("--disc-steps", type=int, default=200,
                     help="steps of the 512-disc sustained run reported beside the metric (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -332,13 +337,22 @@ def main():
     roof["hbm_algorithmic_GBps"] = round(bytes_ / (tile_ms_avg / 1e3) / 1e9, 1)
     log(f"tile kernel {tile_ms_avg:.3f} ms; roofline {roof}")
 
-    # the two-splat warps on the same batch and tile shape
+    # the two-splat warps, and the gather warp with sensor noise, on the same
+    # batch and tile shape
     warps = None
     if args.warp_steps > 0:
         warps = {}
-        for name, mode in (("splat_b_primary", evis.EVIS_WARP_SPLAT | evis.EVIS_BLEND_B_PRIMARY),
-                           ("joint", evis.EVIS_WARP_JOINT)):
-            warr = evis.env_array(batch.env_dicts(dict(sensor, blend_mode=mode)))
+        noise = dict(leak_rate_hz=0.1, shot_rate_hz=1.0, hot_rate_hz=100.0, hot_fraction=1e-3,
+                     shot_L0=-7.0, shot_inv_range=0.1)
+        for name, mode, nz in (("splat_b_primary", evis.EVIS_WARP_SPLAT | evis.EVIS_BLEND_B_PRIMARY,
+                                None),
+                               ("joint", evis.EVIS_WARP_JOINT, None),
+                               ("gather_with_noise", evis.EVIS_WARP_GATHER, noise)):
+            wenvs = batch.env_dicts(dict(sensor, blend_mode=mode))
+            if nz is not None:
+                for e, d in enumerate(wenvs):
+                    d["noise"] = dict(nz, seed=9000 + e)
+            warr = evis.env_array(wenvs)
             for _ in range(2):
                 n_total.zero_()
                 evis.evis_step_batch(ctx, warr, out, n_total, K_used, 0)
@@ -351,7 +365,10 @@ def main():
             wms, wl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
             evis.evis_profile_enable(ctx, False)
             wms /= max(wl, 1)
-            wops = float((px * (OPS_INTERIOR_TWO_SPLAT * (Ks - 1) + OPS_LAST)).sum())
+            if nz is None:
+                wops = float((px * (OPS_INTERIOR_TWO_SPLAT * (Ks - 1) + OPS_LAST)).sum())
+            else:
+                wops = float((px * ((OPS_INTERIOR + OPS_NOISE) * (Ks - 1) + OPS_LAST + OPS_NOISE)).sum())
             wach = wops / (wms / 1e3) / 1e12
             warps[name] = dict(kernel_ms=round(wms, 4), value=round(mpix_substeps / (wms / 1e3), 1),
                                events_per_step=round(int(n_total.item()) / max(wl, 1), 1),
@@ -426,7 +443,7 @@ def main():
         events_per_s=round(events_per_s, 1), events_per_step=round(events_total / args.steps, 1),
         per_env_plain=plain, per_env_fused=fused_per_env,
         batched_vs_plain=(round(value / plain["value"], 2) if plain else None),
-        roofline=roof, cpu_baseline=cpu, two_splat_warps=warps, disc512_sustained=disc,
+        roofline=roof, cpu_baseline=cpu, variants=warps, disc512_sustained=disc,
     )
     print(json.dumps(rec))
     ctx.close()

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define EVIS_ABI_VERSION 1
+#define EVIS_ABI_VERSION 2
 
 #define EVIS_MAX_DIM 2047
 #define EVIS_MAX_ENVS 512
@@ -125,6 +125,36 @@ typedef struct {
   int32_t blend_mode;                 /* EVIS_BLEND_* | EVIS_WARP_* */
 } evis_sensor;
 
+/* Sensor noise (Sec. "Sensor Calibration and Non-idealities": leak events,
+ * shot noise, hot pixels), added by evis_step_batch to the events of every
+ * substep j = 1..K of length Dt (Dt_s = Dt * 1e-6 s, float32):
+ *   leak  P = r_l Dt_s, ON events;
+ *   shot  P = (r_s Dt_s)(1 - I), I = clamp((L_j - shot_L0) * shot_inv_range)
+ *         into [0, 1] (NaN -> 0), L_j the pixel's current log sample;
+ *         random polarity;
+ *   hot   P = r_h Dt_s on a fixed set of about hot_fraction of the pixels;
+ *         random polarity.
+ * Every draw comes from Philox4x32-10 (Salmon et al., SC 2011) with key
+ * `seed` (low word first) and counter (x | y << 11, j, pair_index, kind):
+ * kind 0 holds the three decisions of a pixel-substep (words 0, 1, 2 as
+ * uniforms (w >> 8) 2^-24, an event when the uniform is < P), kinds 1-3 the
+ * time t0 + min(floor((j - 1 + u) Dt), t1 - t0) and polarity (bit 0 of
+ * word 1) of a leak, shot or hot event, kind 4 with j = pair = 0 the hot
+ * set (word 0's uniform < hot_fraction).  Noise events do not move L_ref,
+ * ignore the refractory period and leave t_last alone.  Give each env its
+ * own seed and advance pair_index once per keyframe pair. */
+typedef struct {
+  float leak_rate_hz;     /* r_l >= 0, per pixel */
+  float shot_rate_hz;     /* r_s >= 0, per pixel at normalised intensity 0 */
+  float hot_rate_hz;      /* r_h >= 0, per hot pixel */
+  float hot_fraction;     /* in [0, 1] */
+  float shot_L0;          /* log intensity of normalised intensity 0 */
+  float shot_inv_range;   /* normalised intensity per unit of log intensity (finite) */
+  uint64_t seed;
+  uint32_t pair_index;
+  uint32_t reserved;
+} evis_noise;
+
 /* Per-pixel state carried from pair to pair (caller-owned device arrays). */
 typedef struct {
   float *L_ref;     /* [H*W] reference log level of each pixel (Eq. 4) */
@@ -135,8 +165,9 @@ typedef struct {
   evis_pair pair;
   evis_sensor sensor;
   evis_state state;
-  int32_t env_id;     /* 0..EVIS_MAX_ENVS-1, written into each event */
+  int32_t env_id;             /* 0..EVIS_MAX_ENVS-1, written into each event */
   int32_t reserved;
+  const evis_noise *noise;    /* HOST pointer, or NULL: no noise events */
 } evis_env;
 
 typedef struct evis_ctx evis_ctx;

@@ -15,8 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libevis.so")
 
-SOURCES = ["evis_api.cpp", "evis_tile.hip", "evis_tile_splat.hip", "evis_events.hip",
-           "evis_soft.hip"]
+SOURCES = ["evis_api.cpp", "evis_tile.hip", "evis_tile_splat.hip", "evis_tile_noise.hip",
+           "evis_events.hip", "evis_soft.hip"]
 
 # -ffp-contract=off and correctly rounded division: every float32 operation of
 # the event path is one IEEE operation rounded to nearest, as written.

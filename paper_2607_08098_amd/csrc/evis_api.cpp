@@ -244,7 +244,20 @@ int check_events_out(evis_ctx* ctx, const evis_event* out, int64_t capacity, con
   return EVIS_OK;
 }
 
-EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st, int env_id) {
+int check_noise(evis_ctx* ctx, const evis_noise* nz, const char* who) {
+  if (!nz) return EVIS_OK;
+  auto rate_ok = [](float r) { return r >= 0.0f && std::isfinite(r); };
+  if (!rate_ok(nz->leak_rate_hz) || !rate_ok(nz->shot_rate_hz) || !rate_ok(nz->hot_rate_hz))
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": noise rates must be >= 0 and finite");
+  if (!(nz->hot_fraction >= 0.0f && nz->hot_fraction <= 1.0f))
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": noise hot_fraction must be in [0, 1]");
+  if (!std::isfinite(nz->shot_L0) || !std::isfinite(nz->shot_inv_range))
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": noise shot_L0 / shot_inv_range");
+  return EVIS_OK;
+}
+
+EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st, int env_id,
+                  const evis_noise* nz = nullptr) {
   EnvDesc d{};
   d.LA = p.L_A;
   d.LB = p.L_B;
@@ -270,6 +283,19 @@ EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st
   d.env_bits = (uint32_t)env_id << 23;
   d.t0 = p.t0_us;
   d.span = (int32_t)(p.t1_us - p.t0_us);
+  if (nz && (nz->leak_rate_hz > 0.0f || nz->shot_rate_hz > 0.0f ||
+             (nz->hot_rate_hz > 0.0f && nz->hot_fraction > 0.0f))) {
+    d.noise_on = 1;
+    d.leak_hz = nz->leak_rate_hz;
+    d.shot_hz = nz->shot_rate_hz;
+    d.hot_hz = nz->hot_rate_hz;
+    d.hot_frac = nz->hot_fraction;
+    d.shot_L0 = nz->shot_L0;
+    d.shot_inv = nz->shot_inv_range;
+    d.seed_lo = (uint32_t)(nz->seed & 0xFFFFFFFFull);
+    d.seed_hi = (uint32_t)(nz->seed >> 32);
+    d.pair_index = nz->pair_index;
+  }
   return d;
 }
 
@@ -359,6 +385,12 @@ Sched sched_ptrs(evis_ctx* ctx, int n) {
   return s;
 }
 
+bool plan_has_noise(const Plan& pl) {
+  for (const EnvDesc& d : pl.desc)
+    if (d.noise_on) return true;
+  return false;
+}
+
 // Enqueue reset, prep, queue and the tile kernel for the uploaded plan.
 int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileArgs ta,
                   int32_t* K_used, unsigned long long* reset_cursor, hipStream_t s) {
@@ -380,12 +412,13 @@ int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileA
   ta.queue = sc.queue;
   ta.n_items = sc.n_items;
   const int warp = pl.desc.empty() ? EVIS_WARP_GATHER : pl.desc[0].warp;   // one warp per plan
-  int occ = tile_occupancy(tw, th, mode, warp);
+  const bool noise = plan_has_noise(pl);
+  int occ = tile_occupancy(tw, th, mode, warp, noise);
   int per_cu = ctx->tuning.grid_mult > 0 ? std::min(ctx->tuning.grid_mult, occ) : occ;
   int grid = std::max(1, std::min(pl.items, per_cu * ctx->n_cu));
   {
     ProfScope ps(ctx, mode == MODE_STEP ? EVIS_KERNEL_STEP : EVIS_KERNEL_INTERP, s);
-    EVIS_HIP(launch_tile(tw, th, mode, warp, ta, grid, s), "k_tile");
+    EVIS_HIP(launch_tile(tw, th, mode, warp, noise, ta, grid, s), "k_tile");
   }
   return EVIS_OK;
 }
@@ -593,7 +626,9 @@ static int validate_envs(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, Pl
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": state.t_last");
     if (v.env_id < 0 || v.env_id >= EVIS_MAX_ENVS)
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": env_id");
-    pl.desc.push_back(make_desc(v.pair, v.sensor, v.state, v.env_id));
+    rc = check_noise(ctx, v.noise, who);
+    if (rc) return rc;
+    pl.desc.push_back(make_desc(v.pair, v.sensor, v.state, v.env_id, v.noise));
     if (pl.desc.back().warp != pl.desc[0].warp)
       return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": envs of one call need the same EVIS_WARP_*");
   }
@@ -620,7 +655,8 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
   std::snprintf(key, sizeof(key), "%d|%d|%d|%p|%lld|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d", (int)pl.desc.size(),
                 pl.src_total, pl.items, (void*)out, (long long)capacity, (void*)n_total,
                 (void*)K_used, flags & EVIS_FLAG_RESET_CURSOR, tu.tile_w, tu.tile_h, tu.grid_mult,
-                ta.list_cap, ta.static_tiles, (int)ctx->meta.bytes, pl.desc[0].warp);
+                ta.list_cap, ta.static_tiles, (int)ctx->meta.bytes,
+                pl.desc[0].warp | (plan_has_noise(pl) ? 0x100 : 0));
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
     if (ctx->graphs.size() >= 512) drop_graphs(ctx);

@@ -54,6 +54,10 @@ struct EnvDesc {
                                // Z_B - Zstart) per source, Zstart = Z_A at p + m_B(p), same
                                // layout as src
   float4* tbB;                 // two-splat warps only: bounds of -m_B per block
+  // sensor noise (evis_noise); noise_on = 0 when the env has none
+  int32_t noise_on;
+  float leak_hz, shot_hz, hot_hz, hot_frac, shot_L0, shot_inv;
+  uint32_t seed_lo, seed_hi, pair_index;
 };
 
 // Per-environment values computed on the device each step.
@@ -134,6 +138,27 @@ __device__ __forceinline__ float clamp_into(float v, float hi) {
 }
 
 __device__ __forceinline__ bool finite32(float v) { return fabsf(v) <= 3.402823466e38f; }
+
+// Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and
+// Shaw (SC 2011): ten rounds of two 32 x 32 -> 64-bit products mixed into
+// the counter with the key, the key advanced by the Weyl increments
+// between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// The top 24 bits of a word as a float in [0, 1) (exact).
+__device__ __forceinline__ float uniform24(uint32_t w) { return (float)(w >> 8) * 0x1p-24f; }
 
 // Exact substep count from the largest squared motion length M (float64):
 // the smallest K >= 1 with K*K >= M, at most K_max.

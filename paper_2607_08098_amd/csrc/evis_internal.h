@@ -87,10 +87,14 @@ hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_pref
 hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,
                         int32_t* xbegin, int32_t* env_order, int32_t* n_items,
                         int32_t* K_used, hipStream_t s);
-// warp: EVIS_WARP_* (the two-splat warps are launched from evis_tile_splat.hip)
-hipError_t launch_tile(int tile_w, int tile_h, int mode, int warp, const TileArgs& a, int grid,
-                       hipStream_t s);
-int tile_occupancy(int tile_w, int tile_h, int mode, int warp);
+// warp: EVIS_WARP_* (the two-splat warps are launched from evis_tile_splat.hip);
+// noise: the fused step with sensor-noise events (evis_tile_noise.hip)
+hipError_t launch_tile(int tile_w, int tile_h, int mode, int warp, bool noise, const TileArgs& a,
+                       int grid, hipStream_t s);
+int tile_occupancy(int tile_w, int tile_h, int mode, int warp, bool noise);
+hipError_t launch_tile_noise(int tile_w, int tile_h, int warp, const TileArgs& a, int grid,
+                             hipStream_t s);
+int tile_occupancy_noise(int tile_w, int tile_h, int warp);
 hipError_t launch_tile_two(int tile_w, int tile_h, int mode, int warp, const TileArgs& a, int grid,
                            hipStream_t s);
 int tile_occupancy_two(int tile_w, int tile_h, int mode, int warp);

@@ -296,6 +296,103 @@ __device__ __forceinline__ void emit_substep(
   }
 }
 
+// Noise parameters of one env for one keyframe pair (per substep
+// probabilities need the pair's substep length).
+struct NoiseCfg {
+  float p_leak, shot_scale, p_hot;   // r_l Dt_s, r_s Dt_s, r_h Dt_s
+  float shot_L0, shot_inv, hot_frac;
+  uint32_t k0, k1, pair;
+};
+
+__device__ __forceinline__ NoiseCfg noise_cfg(const EnvDesc& d, float Dt) {
+  const float dts = Dt * 1e-6f;
+  return NoiseCfg{d.leak_hz * dts, d.shot_hz * dts, d.hot_hz * dts, d.shot_L0, d.shot_inv,
+                  d.hot_frac, d.seed_lo, d.seed_hi, d.pair_index};
+}
+
+// Hot-pixel membership of this thread's pixels (bit k for slot k).
+template <int PPT>
+__device__ __forceinline__ uint32_t hot_bits(const NoiseCfg& nc, const PixAux& aux, uint32_t okbits) {
+  uint32_t hb = 0;
+  if (nc.p_hot > 0.0f) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const uint4 w = philox4x32_10(make_uint4(aux.xy_at(threadIdx.x + k * kBlock), 0u, 0u, 4u),
+                                    nc.k0, nc.k1);
+      hb |= (((okbits >> k) & 1u) && uniform24(w.x) < nc.hot_frac ? 1u : 0u) << k;
+    }
+  }
+  return hb;
+}
+
+// Leak, shot and hot-pixel events of substep j (Lj the current samples).
+// Call right after emit_substep of the same substep (every thread): the
+// events are staged like the crossings and share that emission's flush
+// request slot, so the sink's round accounting does not change.
+template <int PPT>
+__device__ __forceinline__ void emit_noise(int j, const float (&Lj)[PPT], const PixAux& aux,
+                                           uint32_t okbits, uint32_t hotbits, const NoiseCfg& nc,
+                                           long long t0, int span, float Dt, uint32_t env_bits,
+                                           const SinkShared& sh, const SinkOut& so,
+                                           const SinkRound& sr) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  uint32_t fired = 0;   // 3 bits per slot: leak, shot, hot
+  int m = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    if ((okbits >> k) & 1u) {
+      const uint4 w = philox4x32_10(
+          make_uint4(aux.xy_at(tid + k * kBlock), (uint32_t)j, nc.pair, 0u), nc.k0, nc.k1);
+      float ib = (Lj[k] - nc.shot_L0) * nc.shot_inv;
+      ib = (ib > 0.0f) ? ib : 0.0f;
+      ib = (ib < 1.0f) ? ib : 1.0f;
+      const float p_shot = nc.shot_scale * (1.0f - ib);
+      const uint32_t f = (uniform24(w.x) < nc.p_leak ? 1u : 0u) |
+                         (uniform24(w.y) < p_shot ? 2u : 0u) |
+                         (((hotbits >> k) & 1u) && uniform24(w.z) < nc.p_hot ? 4u : 0u);
+      fired |= f << (3 * k);
+      m += __builtin_popcount(f);
+    }
+  }
+  if (__ballot(m > 0) == 0ull) return;   // wave-uniform
+  const int incl = wave_inclusive_scan(m);
+  const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+  int lb = 0;
+  if (lane == kWave - 1) lb = atomicAdd(sh.cnt, wtot);
+  lb = __builtin_amdgcn_readlane(lb, kWave - 1);
+  const int n_lds = max(0, min(wtot, sh.cap - lb));
+  unsigned long long gbase_w = 0;
+  if (n_lds < wtot) {   // wave-uniform
+    unsigned long long g = 0;
+    if (lane == kWave - 1) g = atomicAdd(so.cursor, (unsigned long long)(wtot - n_lds));
+    gbase_w = __shfl(g, kWave - 1, kWave);
+  }
+  if (lane == kWave - 1 && lb + wtot > sh.cap - sh.cap / 4) lds_st(sh.req, (sr.round - 1) & 3, 1);
+  int widx = incl - m;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const uint32_t f = (fired >> (3 * k)) & 7u;
+    if (f) {
+      const uint32_t xy = aux.xy_at(tid + k * kBlock);
+      for (uint32_t kind = 1; kind <= 3; ++kind) {
+        if (!((f >> (kind - 1)) & 1u)) continue;
+        const uint4 e = philox4x32_10(make_uint4(xy, (uint32_t)j, nc.pair, kind), nc.k0, nc.k1);
+        const float v = ((float)(j - 1) + uniform24(e.x)) * Dt;
+        const int t = (int)(t0 + min((int)floorf(v), span));
+        const uint32_t pol = (kind == 1u) ? 1u : (e.y & 1u);
+        const uint32_t word = xy | (pol << 22) | env_bits;
+        if (widx < n_lds) {
+          lds_st(sh.buf, lb + widx, make_uint2(word, (uint32_t)t));
+        } else {
+          const unsigned long long idx = gbase_w + (unsigned long long)(widx - n_lds);
+          if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
+        }
+        ++widx;
+      }
+    }
+  }
+}
+
 // Write out whatever is still staged.  Every thread must call it.
 __device__ __forceinline__ void sink_flush(const SinkShared& sh, const SinkOut& so) {
   __syncthreads();

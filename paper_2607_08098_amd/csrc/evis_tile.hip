@@ -287,8 +287,9 @@ bool tile_shape_supported(int tw, int th) {
   return false;
 }
 
-hipError_t launch_tile(int tw, int th, int mode, int warp, const TileArgs& a, int grid,
+hipError_t launch_tile(int tw, int th, int mode, int warp, bool noise, const TileArgs& a, int grid,
                        hipStream_t s) {
+  if (noise && mode == MODE_STEP) return launch_tile_noise(tw, th, warp, a, grid, s);
   if (warp != EVIS_WARP_GATHER) return launch_tile_two(tw, th, mode, warp, a, grid, s);
 #define X(W_, H_) if (tw == W_ && th == H_) return launch_tile_shape<W_, H_>(mode, a, grid, s);
   EVIS_TILE_SHAPES(X)
@@ -296,7 +297,8 @@ hipError_t launch_tile(int tw, int th, int mode, int warp, const TileArgs& a, in
   return hipErrorInvalidValue;
 }
 
-int tile_occupancy(int tw, int th, int mode, int warp) {
+int tile_occupancy(int tw, int th, int mode, int warp, bool noise) {
+  if (noise && mode == MODE_STEP) return tile_occupancy_noise(tw, th, warp);
   if (warp != EVIS_WARP_GATHER) return tile_occupancy_two(tw, th, mode, warp);
   // Queried once per (shape, mode) and cached: no runtime query happens while
   // a launch sequence is being captured into a graph.

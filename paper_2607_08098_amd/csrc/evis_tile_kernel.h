@@ -30,7 +30,10 @@ namespace evis {
 // per pass into double buffers (A: j & 1, B: 2 + (j & 1)), which also
 // takes one barrier per substep: the splat of j + 2 comes after the
 // barrier that follows the splat of j + 1, by which time j is read.
-template <int TW, int TH, int MODE, int WARP = EVIS_WARP_GATHER>
+//
+// NOISE = 1 (fused step only) adds the sensor-noise events of every env that
+// has noise after each substep's crossings.
+template <int TW, int TH, int MODE, int WARP = EVIS_WARP_GATHER, int NOISE = 0>
 __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   constexpr int NPX = TW * TH;
   constexpr int PPT = NPX / kBlock;
@@ -142,6 +145,14 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
     const PixAux aux{(MODE == MODE_STEP && d.th_on) ? s_con : nullptr,
                      (MODE == MODE_STEP && d.th_off) ? s_coff : nullptr, s_tl, d.C_on, d.C_off,
                      Tx0, Ty0, TW, __builtin_ctz(TW), -1};
+    NoiseCfg ncfg{};
+    uint32_t hotb = 0;
+    if constexpr (NOISE != 0 && MODE == MODE_STEP) {
+      if (d.noise_on) {   // uniform
+        ncfg = noise_cfg(d, dy.Dt);
+        hotb = hot_bits<PPT>(ncfg, aux, okbits);
+      }
+    }
 
     // Candidate source tiles and their substep intervals.
     Window win{};
@@ -204,6 +215,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       if (MODE == MODE_STEP) {
         emit_substep<PPT>(jj, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.refr, d.env_bits,
                           sh, so, sr);
+        if constexpr (NOISE != 0) {
+          if (d.noise_on)
+            emit_noise<PPT>(jj, Lj, aux, okbits, hotb, ncfg, d.t0, d.span, dy.Dt, d.env_bits, sh,
+                            so, sr);
+        }
       } else if (MODE == MODE_INTERP) {
         const long long plane = (long long)H * W;
 #pragma unroll

@@ -53,9 +53,18 @@ class EvisState(ctypes.Structure):
     _fields_ = [("L_ref", ctypes.c_void_p), ("t_last", ctypes.c_void_p)]
 
 
+class EvisNoise(ctypes.Structure):
+    _fields_ = [("leak_rate_hz", ctypes.c_float), ("shot_rate_hz", ctypes.c_float),
+                ("hot_rate_hz", ctypes.c_float), ("hot_fraction", ctypes.c_float),
+                ("shot_L0", ctypes.c_float), ("shot_inv_range", ctypes.c_float),
+                ("seed", ctypes.c_uint64), ("pair_index", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class EvisEnv(ctypes.Structure):
     _fields_ = [("pair", EvisPair), ("sensor", EvisSensor), ("state", EvisState),
-                ("env_id", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("env_id", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("noise", ctypes.POINTER(EvisNoise))]
 
 
 class EvisSoftEnv(ctypes.Structure):
@@ -198,8 +207,28 @@ def make_state(d: dict) -> EvisState:
     return EvisState(_ptr(d["L_ref"]), _ptr(d.get("t_last")))
 
 
-def make_env(d: dict) -> EvisEnv:
-    return EvisEnv(make_pair(d), make_sensor(d), make_state(d), int(d.get("env_id", 0)), 0)
+def make_noise(nz: dict) -> EvisNoise:
+    """Sensor noise of one env: keys leak_rate_hz, shot_rate_hz, hot_rate_hz,
+    hot_fraction, shot_L0, shot_inv_range, seed, pair_index (missing = 0,
+    shot_inv_range 1)."""
+    return EvisNoise(float(nz.get("leak_rate_hz", 0.0)), float(nz.get("shot_rate_hz", 0.0)),
+                     float(nz.get("hot_rate_hz", 0.0)), float(nz.get("hot_fraction", 0.0)),
+                     float(nz.get("shot_L0", 0.0)), float(nz.get("shot_inv_range", 1.0)),
+                     int(nz.get("seed", 0)) & 0xFFFF_FFFF_FFFF_FFFF,
+                     int(nz.get("pair_index", 0)) & 0xFFFF_FFFF, 0)
+
+
+def make_env(d: dict, keep: Optional[list] = None) -> EvisEnv:
+    """d["noise"] (optional) is a make_noise dict; the EvisNoise it becomes
+    is appended to `keep`, which must outlive every call that uses the env."""
+    env = EvisEnv(make_pair(d), make_sensor(d), make_state(d), int(d.get("env_id", 0)), 0)
+    if d.get("noise") is not None:
+        nz = make_noise(d["noise"])
+        if keep is None:
+            raise ValueError("make_env: an env with noise needs a keep list")
+        keep.append(nz)
+        env.noise = ctypes.pointer(nz)
+    return env
 
 
 # ---------------------------------------------------------------------------
@@ -265,9 +294,11 @@ def evis_generate_events(ctx: Context, L_seq: torch.Tensor, t0: int, t1: int, se
 
 
 def env_array(envs: Sequence[dict]):
+    """Host array of env descriptors; noise structs stay alive with it."""
     arr = (EvisEnv * len(envs))()
+    arr._keep = []
     for i, d in enumerate(envs):
-        arr[i] = make_env(d)
+        arr[i] = make_env(d, arr._keep)
     return arr
 
 

@@ -39,15 +39,47 @@ def test_struct_layouts_match_the_header():
     assert ctypes.sizeof(evis.EvisPair) == 8 + 6 * 8 + 16
     assert ctypes.sizeof(evis.EvisSensor) == 8 + 16 + 16
     assert ctypes.sizeof(evis.EvisState) == 16
-    assert ctypes.sizeof(evis.EvisEnv) == ctypes.sizeof(evis.EvisPair) + 40 + 16 + 8
+    assert ctypes.sizeof(evis.EvisEnv) == ctypes.sizeof(evis.EvisPair) + 40 + 16 + 8 + 8
+    assert ctypes.sizeof(evis.EvisNoise) == 6 * 4 + 8 + 8
     assert ctypes.sizeof(evis.EvisTuning) == 24
     assert ctypes.sizeof(evis.EvisSoftEnv) == ctypes.sizeof(evis.EvisPair) + 7 * 8
+
+
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """Sizes and field offsets of every ctypes mirror equal what gcc makes
+    of include/evis.h."""
+    import shutil
+    import subprocess
+    from paper_2607_08098_amd import evis
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    mirrors = {"evis_pair": evis.EvisPair, "evis_sensor": evis.EvisSensor,
+               "evis_state": evis.EvisState, "evis_env": evis.EvisEnv, "evis_noise": evis.EvisNoise,
+               "evis_tuning": evis.EvisTuning, "evis_soft_env": evis.EvisSoftEnv}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "evis.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
 
 
 def test_null_context_is_rejected_without_touching_a_gpu():
     from paper_2607_08098_amd import evis
     lib = evis.load_library()
-    assert lib.evis_abi_version() == 1
+    assert lib.evis_abi_version() == 2
     assert lib.evis_step_batch(None, None, 0, None, 0, None, None, 0, None) == evis.EVIS_ERR_INVALID
     assert lib.evis_interpolate(None, None, 1, 0, 1, 0, None, None, None) == evis.EVIS_ERR_INVALID
     assert lib.evis_generate_events(None, None, 1, 1, 1, 0, 1, None, None, 0, None, 0, None, 0,

@@ -8,6 +8,9 @@ nothing from them.
 Paper: "EVIS: Real-Time Event Camera Simulation with Multimodal Supervision
 in NVIDIA Isaac Sim".  Steps, in the paper's order:
 
+  defocus                the optional defocus of Sec. "Sensor Calibration
+                         and Non-idealities": a separable Gaussian blur of
+                         the linear intensity before the log (R24)
   log_luminance          Sec. "HDR Event Formation Model", Eq. 3 and the
                          log-intensity definition that follows it
   adaptive_k             Sec. "Bidirectional Motion Vector Warping": K-1
@@ -86,6 +89,9 @@ Readings of the paper taken here (each is restated where it is used):
   R22 a noise event's time is t0 + min(floor((j - 1 + u) Dt), span) with its
       own uniform u; leak events are ON, shot and hot events take the
       polarity bit 0 of their second word (1 = ON).
+  R24 defocus: taps k = -r..r with r = ceil(3 sigma), weights
+      exp(-k^2 / (2 sigma^2)) normalised to sum 1, edge pixels repeated,
+      along x then along y (per channel of RGB input); float64 here.
   R23 noise events are extra: they do not move L_ref, ignore the
       refractory period and leave t_last alone.
   R19 joint warp (WARP_JOINT): one z-buffer over the sources of both
@@ -154,6 +160,38 @@ def clamp_into(v: np.ndarray, hi: int) -> np.ndarray:
     """Clamp into [0, hi]; NaN becomes 0."""
     v = np.where(v > 0, v, F32(0))
     return np.where(v < hi, v, F32(hi)).astype(F32)
+
+
+# ---------------------------------------------------------------------------
+# defocus (float64; R24)
+# ---------------------------------------------------------------------------
+
+def defocus_radius(sigma: float) -> int:
+    return int(math.ceil(3.0 * sigma))
+
+
+def defocus_weights(sigma: float) -> np.ndarray:
+    r = defocus_radius(sigma)
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-(k * k) / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def defocus(x, sigma: float) -> np.ndarray:
+    """Separable Gaussian blur of linear intensity [H][W] or [H][W][3]:
+    along x, then along y, edge pixels repeated (R24)."""
+    x = np.asarray(x, np.float64)
+    w = defocus_weights(sigma)
+    r = len(w) // 2
+    planes = x[..., None] if x.ndim == 2 else x
+    out = np.empty_like(planes)
+    H, W = planes.shape[:2]
+    for c in range(planes.shape[2]):
+        p = np.pad(planes[..., c], ((0, 0), (r, r)), mode="edge")
+        h = sum(w[i] * p[:, i:i + W] for i in range(2 * r + 1))
+        p = np.pad(h, ((r, r), (0, 0)), mode="edge")
+        out[..., c] = sum(w[i] * p[i:i + H, :] for i in range(2 * r + 1))
+    return out[..., 0] if x.ndim == 2 else out
 
 
 # ---------------------------------------------------------------------------

@@ -69,6 +69,43 @@ def pin_log_luminance(o):
 # substep count
 # ---------------------------------------------------------------------------
 
+def pin_defocus_library(o):
+    """The blur equals scipy's Gaussian filter (same radius, edge mode
+    'nearest') along both axes, for grey and RGB input."""
+    from scipy import ndimage
+    rng = np.random.default_rng(47)
+    for sigma, shape in ((0.3, (9, 14)), (1.7, (23, 19)), (4.0, (31, 40, 3))):
+        x = rng.uniform(0, 5, size=shape)
+        r = o.defocus_radius(sigma)
+        want = x
+        for ax in (1, 0):
+            want = ndimage.gaussian_filter1d(want, sigma, axis=ax, mode="nearest", radius=r)
+        assert np.allclose(o.defocus(x, sigma), want, rtol=0, atol=1e-12), sigma
+
+
+def pin_defocus_closed_forms(o):
+    """A constant image is unchanged; a linear ramp is unchanged away from
+    the edges (the kernel is symmetric); a point spreads into the outer
+    product of the 1-D Gaussian weights, whose variance is about sigma^2."""
+    sigma = 2.0
+    r = o.defocus_radius(sigma)
+    assert r == 6
+    c = np.full((20, 25), 3.25)
+    assert np.allclose(o.defocus(c, sigma), c, rtol=0, atol=1e-12)
+    yy, xx = np.mgrid[0:30, 0:40].astype(np.float64)
+    ramp = 0.5 + 0.25 * xx - 0.125 * yy
+    got = o.defocus(ramp, sigma)
+    assert np.allclose(got[r:-r, r:-r], ramp[r:-r, r:-r], rtol=0, atol=1e-12)
+    d = np.zeros((31, 31))
+    d[15, 15] = 1.0
+    k = np.arange(-r, r + 1)
+    g = np.exp(-k * k / (2 * sigma * sigma))
+    g /= g.sum()
+    assert np.allclose(o.defocus(d, sigma)[15 - r:16 + r, 15 - r:16 + r], np.outer(g, g), rtol=0, atol=1e-15)
+    var = float((k * k * g).sum())
+    assert abs(var - sigma * sigma) < 0.02 * sigma * sigma
+
+
 def _field(H, W, vec=None):
     m = np.zeros((H, W, 2), F32)
     if vec is not None:

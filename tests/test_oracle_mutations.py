@@ -231,6 +231,25 @@ def _noise_variant(dt_us=False, bright=False, leak_pol=False):
     return noise
 
 
+def m_defocus_zero_padding(x, sigma):
+    x = np.asarray(x, np.float64)
+    w = o.defocus_weights(sigma)
+    r = len(w) // 2
+    planes = x[..., None] if x.ndim == 2 else x
+    out = np.empty_like(planes)
+    H, W = planes.shape[:2]
+    for c in range(planes.shape[2]):
+        p = np.pad(planes[..., c], ((0, 0), (r, r)))          # planted: zeros past the edge
+        h = sum(w[i] * p[:, i:i + W] for i in range(2 * r + 1))
+        p = np.pad(h, ((r, r), (0, 0)))
+        out[..., c] = sum(w[i] * p[i:i + H, :] for i in range(2 * r + 1))
+    return out[..., 0] if x.ndim == 2 else out
+
+
+def m_defocus_radius(sigma):
+    return int(math.ceil(2.0 * sigma))                      # planted: 2 sigma
+
+
 def m_pack_shift(ev):
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     word = ev[:, 0] | (ev[:, 1] << 12) | (ev[:, 3] << 22) | (ev[:, 4] << 23)   # planted
@@ -265,6 +284,8 @@ MUTANTS = [
     ("noise_rate_in_microseconds", "noise_events", _noise_variant(dt_us=True), P.pin_leak_rate),
     ("shot_noise_brighter_fires", "noise_events", _noise_variant(bright=True), P.pin_shot_darkness),
     ("leak_random_polarity", "noise_events", _noise_variant(leak_pol=True), P.pin_leak_rate),
+    ("defocus_zero_padding", "defocus", m_defocus_zero_padding, P.pin_defocus_library),
+    ("defocus_radius_two_sigma", "defocus_radius", m_defocus_radius, P.pin_defocus_closed_forms),
 ]
 
 

@@ -17,6 +17,7 @@ fused form on the same GPU; the roofline of the fused tile kernel, timed
 live with HIP events; the same kernel with B splatted backward (the
 two-splat warps: own z-buffer with B primary, and one joint z-buffer) and
 with sensor noise (leak 0.1 Hz, shot 1 Hz, 0.1% hot pixels at 100 Hz);
+the defocus blur of every env's keyframe (sigma 0.5 px);
 the CPU oracle on a bounded sample of the same workload (rank 0, N = 1
 only).
 """
@@ -376,6 +377,51 @@ def main():
                                              peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
                                              frac=round(wach / ALU_PEAK_TOPS, 4)))
             log(f"warp {name}: tile kernel {wms:.3f} ms")
+
+    # defocus of every env's new keyframe (one launch per env, sigma 0.5 px):
+    # HBM-bound, 8 algorithmic bytes per pixel (one read, one write)
+    if args.warp_steps > 0:
+        blurred = torch.empty_like(batch.I_B)
+        views = [(batch.view(batch.I_B, e), batch.view(blurred, e)) for e in range(n_envs)]
+
+        def defocus_all():
+            for src, dst in views:
+                evis.evis_defocus(ctx, src, 0.5, out=dst)
+
+        defocus_all()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.warp_steps):
+            defocus_all()
+        e1.record()
+        torch.cuda.synchronize()
+        eager_ms = e0.elapsed_time(e1) / args.warp_steps
+        # the same 64 launches captured once into a HIP graph and replayed
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gs):
+            defocus_all()
+            gs.synchronize()
+            with torch.cuda.graph(graph, stream=gs):
+                defocus_all()
+        torch.cuda.current_stream().wait_stream(gs)
+        graph.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.warp_steps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        dms = e0.elapsed_time(e1) / args.warp_steps
+        gbs = 8.0 * float(px.sum()) / (dms / 1e3) / 1e9
+        warps["defocus_sigma0.5"] = dict(ms_per_step=round(dms, 4), eager_ms_per_step=round(eager_ms, 4),
+                                         launches=n_envs,
+                                         roofline=dict(bound="hbm", achieved=round(gbs, 1),
+                                                       peak=HBM_PEAK_GBS, unit="GB/s",
+                                                       frac=round(gbs / HBM_PEAK_GBS, 4)))
+        log(f"defocus: {dms:.3f} ms (graph), {eager_ms:.3f} ms (eager) for {n_envs} envs, {gbs:.0f} GB/s")
+        del blurred, views, graph
 
     # per-env-launch plain form: every sub-frame to HBM, then the event model
     plain = None

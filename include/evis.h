@@ -188,6 +188,20 @@ int evis_abi_version(void);
 int evis_log_luminance(evis_ctx *ctx, const float *x, int32_t channels, int64_t n, float eps,
                        float *L_out, void *stream);
 
+/* Defocus (Sec. "Sensor Calibration and Non-idealities": before event
+ * generation the linear intensity is convolved with a separable Gaussian):
+ * x and out are [H][W] (channels == 1) or [H][W][3] linear intensity,
+ * out must not overlap x.  Taps k = -r..r, r = ceil(3 sigma), weights
+ * exp(-k^2 / (2 sigma^2)) normalised to sum 1 (computed in double, used in
+ * float32), edge pixels repeated; along x, then along y, each sum taken
+ * in tap order in float32.  0 < sigma <= EVIS_MAX_DEFOCUS_SIGMA;
+ * 1 <= H, W <= EVIS_MAX_DEFOCUS_DIM.  Apply it to the radiance before
+ * evis_log_luminance. */
+#define EVIS_MAX_DEFOCUS_SIGMA 10.0f
+#define EVIS_MAX_DEFOCUS_DIM 16384
+int evis_defocus(evis_ctx *ctx, const float *x, int32_t H, int32_t W, int32_t channels, float sigma,
+                 float *out, void *stream);
+
 /* Initialise a pixel state from the first log frame: L_ref = L_first and,
  * when t_last is non-NULL, t_last = EVIS_T_LAST_INIT. */
 int evis_state_init(evis_ctx *ctx, const float *L_first, int32_t H, int32_t W,

@@ -489,6 +489,41 @@ int evis_log_luminance(evis_ctx* ctx, const float* x, int32_t channels, int64_t 
   return EVIS_OK;
 }
 
+int evis_defocus(evis_ctx* ctx, const float* x, int32_t H, int32_t W, int32_t channels, float sigma,
+                 float* out, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!x || !out || !aligned(x, 4) || !aligned(out, 4))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: null or misaligned pointer");
+  if (channels != 1 && channels != 3)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: channels must be 1 or 3");
+  if (H < 1 || W < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: H, W");
+  if (H > EVIS_MAX_DEFOCUS_DIM || W > EVIS_MAX_DEFOCUS_DIM)
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_defocus: H, W > 16384");
+  if (!(sigma > 0.0f && sigma <= EVIS_MAX_DEFOCUS_SIGMA))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: sigma must be in (0, 10]");
+  const size_t bytes = (size_t)H * W * channels * sizeof(float);
+  const char* xb = reinterpret_cast<const char*>(x);
+  const char* ob = reinterpret_cast<const char*>(out);
+  if (xb < ob + bytes && ob < xb + bytes)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: out overlaps x");
+  DefocusArgs a{};
+  a.x = x;
+  a.out = out;
+  a.H = H;
+  a.W = W;
+  a.C = channels;
+  a.r = (int)std::ceil(3.0 * (double)sigma);
+  double w[2 * kDefocusMaxR + 1], sum = 0.0;
+  for (int k = -a.r; k <= a.r; ++k) {
+    w[k + a.r] = std::exp(-(double)k * k / (2.0 * (double)sigma * (double)sigma));
+    sum += w[k + a.r];
+  }
+  for (int k = 0; k <= 2 * a.r; ++k) a.w[k] = (float)(w[k] / sum);
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  EVIS_HIP(launch_defocus(a, (hipStream_t)stream), "k_defocus");
+  return EVIS_OK;
+}
+
 int evis_state_init(evis_ctx* ctx, const float* L_first, int32_t H, int32_t W,
                     const evis_state* state, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;

@@ -136,11 +136,58 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   sink_flush(sh, so);
 }
 
+// Defocus: one workgroup per 64 x 16 output tile of one channel.  The
+// input tile with an apron of r pixels (edge pixels repeated) goes to LDS,
+// then the horizontal pass over all its rows into LDS, then the vertical
+// pass to the output; each output sums its 2r + 1 taps in order, k = -r..r.
+// HBM-bound: one read and one write of the image (plus the aprons).
+constexpr int kDefTW = 64, kDefTH = 16;
+
+__global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
+  extern __shared__ float smem[];
+  const int r = a.r, C = a.C, W = a.W, H = a.H, c = blockIdx.z;
+  const int inW = kDefTW + 2 * r, inH = kDefTH + 2 * r;
+  float* in = smem;                 // [inH][inW]
+  float* hb = smem + inW * inH;     // [inH][kDefTW]
+  const int x0 = blockIdx.x * kDefTW, y0 = blockIdx.y * kDefTH;
+  for (int i = threadIdx.x; i < inW * inH; i += kBlock) {
+    const int gx = min(max(x0 - r + i % inW, 0), W - 1);
+    const int gy = min(max(y0 - r + i / inW, 0), H - 1);
+    in[i] = a.x[((long long)gy * W + gx) * C + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kDefTW * inH; i += kBlock) {
+    const int col = i % kDefTW, row = i / kDefTW;
+    const float* src = in + row * inW + col;
+    float acc = 0.0f;
+    for (int k = 0; k <= 2 * r; ++k) acc = acc + a.w[k] * src[k];
+    hb[i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kDefTW * kDefTH; i += kBlock) {
+    const int col = i % kDefTW, row = i / kDefTW;
+    const int gx = x0 + col, gy = y0 + row;
+    if (gx >= W || gy >= H) continue;
+    const float* src = hb + row * kDefTW + col;
+    float acc = 0.0f;
+    for (int k = 0; k <= 2 * r; ++k) acc = acc + a.w[k] * src[k * kDefTW];
+    a.out[((long long)gy * W + gx) * C + c] = acc;
+  }
+}
+
 static int grid_for(long long n, int per_block) {
   long long g = (n + per_block - 1) / per_block;
   if (g < 1) g = 1;
   if (g > 65535LL * 16) g = 65535LL * 16;
   return (int)g;
+}
+
+hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s) {
+  const int inW = kDefTW + 2 * a.r, inH = kDefTH + 2 * a.r;
+  const size_t lds = (size_t)(inW * inH + kDefTW * inH) * sizeof(float);
+  hipLaunchKernelGGL(k_defocus, dim3((a.W + kDefTW - 1) / kDefTW, (a.H + kDefTH - 1) / kDefTH, a.C),
+                     dim3(kBlock), lds, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_log_luminance(const float* x, int channels, long long n, float eps, float* L,

@@ -102,6 +102,16 @@ bool tile_shape_supported(int tile_w, int tile_h);
 
 hipError_t launch_log_luminance(const float* x, int channels, long long n, float eps, float* L,
                                 hipStream_t s);
+
+// Defocus (separable Gaussian blur of linear intensity): taps w[0..2r].
+constexpr int kDefocusMaxR = 30;
+struct DefocusArgs {
+  const float* x;
+  float* out;
+  int32_t H, W, C, r;
+  float w[2 * kDefocusMaxR + 1];
+};
+hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s);
 hipError_t launch_state_init(const float* L_first, long long n, float* L_ref, int32_t* t_last,
                              hipStream_t s);
 hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, int span,

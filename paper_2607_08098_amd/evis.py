@@ -91,6 +91,8 @@ SIGNATURES = {
     "evis_last_error": (ctypes.c_char_p, [_VP]),
     "evis_log_luminance": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                           _VP, _VP]),
+    "evis_defocus": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_float, _VP, _VP]),
     "evis_state_init": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.POINTER(EvisState), _VP]),
     "evis_substep_count": (ctypes.c_int, [_VP, ctypes.POINTER(EvisPair), ctypes.c_int32, _VP, _VP]),
@@ -246,6 +248,17 @@ def evis_log_luminance(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=Non
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=x.device)
     ctx.check(ctx.lib.evis_log_luminance(ctx.handle, _ptr(x), channels, n, eps, _ptr(out), _stream(stream)))
+    return out
+
+
+def evis_defocus(ctx: Context, x: torch.Tensor, sigma: float, out=None, stream=None):
+    """x: [H, W] or [H, W, 3] float32 linear intensity on the device."""
+    channels = 3 if (x.dim() == 3 and x.shape[-1] == 3) else 1
+    H, W = x.shape[0], x.shape[1]
+    if out is None:
+        out = torch.empty_like(x)
+    ctx.check(ctx.lib.evis_defocus(ctx.handle, _ptr(x), H, W, channels, float(sigma), _ptr(out),
+                                   _stream(stream)))
     return out
 
 

@@ -13,6 +13,8 @@ in NVIDIA Isaac Sim".  Steps, in the paper's order:
                          the linear intensity before the log (R24)
   log_luminance          Sec. "HDR Event Formation Model", Eq. 3 and the
                          log-intensity definition that follows it
+  log_channels           the colour-event variant: each of R, G, B in place
+                         of the luminance (same section)
   adaptive_k             Sec. "Bidirectional Motion Vector Warping": K-1
                          intermediate frames per keyframe gap, K chosen so
                          that no pixel moves more than one px per substep
@@ -92,6 +94,10 @@ Readings of the paper taken here (each is restated where it is used):
   R24 defocus: taps k = -r..r with r = ceil(3 sigma), weights
       exp(-k^2 / (2 sigma^2)) normalised to sum 1, edge pixels repeated,
       along x then along y (per channel of RGB input); float64 here.
+  R25 over-render margin (the paper's optional border handling): with a
+      crop margin m the warp runs on the whole rendered frame and only the
+      inner pixels reach the event model (and the noise), in the cropped
+      frame's coordinates; the margin keeps its state untouched.
   R23 noise events are extra: they do not move L_ref, ignore the
       refractory period and leave t_last alone.
   R19 joint warp (WARP_JOINT): one z-buffer over the sources of both
@@ -207,6 +213,14 @@ def log_luminance(x, eps: float = 1e-3) -> np.ndarray:
     else:
         Y = x
     return np.log(Y + eps)
+
+
+def log_channels(x, eps: float = 1e-3) -> np.ndarray:
+    """Colour events (Sec. "HDR Event Formation Model"): each of R, G, B in
+    place of the luminance, L_c = ln(I_c + eps); [..., 3] -> [3, ...].
+    float64."""
+    x = np.asarray(x, np.float64)
+    return np.stack([np.log(x[..., c] + eps) for c in range(3)])
 
 
 # ---------------------------------------------------------------------------
@@ -688,27 +702,38 @@ def choose_k(pair: Pair, sensor: Sensor) -> int:
     return adaptive_k(pair.m_A, pair.m_B, sensor.K_max)
 
 
-def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0):
+def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0, crop_margin: int = 0):
     """One keyframe pair: K, sub-frames (splat, gather, blend) and events, streaming
-    over j.  Returns (events[N,5], L_ref', t_last', K)."""
+    over j.  Returns (events[N,5], L_ref', t_last', K).
+
+    crop_margin m > 0 (R25): the frames carry an over-rendered margin of m
+    pixels on every side; the warp uses all of it, the event model (and the
+    noise) only the inner (H - 2m) x (W - 2m) pixels, whose events are in
+    the cropped frame's coordinates; the margin's L_ref and t_last are left
+    as they are."""
     K = choose_k(pair, sensor)
     H, W = pair.shape
+    m = int(crop_margin)
+    inner = (slice(m, H - m), slice(m, W - m))
     on, off = sensor.thresholds(H, W)
+    on, off = on[inner], off[inner]
     R = np.array(L_ref, F32, copy=True)
     track = t_last is not None
     tl = np.array(t_last, np.int64, copy=True) if track else np.full((H, W), T_LAST_INIT, np.int64)
+    Rc, tlc = R[inner], tl[inner]                 # views: updated in place
     Dt = substep_dt(pair.t0_us, pair.t1_us, K)
     span = pair.t1_us - pair.t0_us
     log = EventLog()
-    prev = pair.L_A.astype(F32)
+    prev = pair.L_A.astype(F32)[inner]
     nz = sensor.noise
-    hot = hot_pixels(H, W, nz) if nz is not None else None
+    hot = hot_pixels(H - 2 * m, W - 2 * m, nz) if nz is not None else None
     for j, L, _ in substep_frames(pair, K, range(1, K + 1), sensor.blend_mode):
-        emit_substep(j, prev, L, R, tl, on, off, sensor.refractory_us, pair.t0_us, Dt,
+        Lc = L[inner]
+        emit_substep(j, prev, Lc, Rc, tlc, on, off, sensor.refractory_us, pair.t0_us, Dt,
                      span, env_id, log, track)
         if nz is not None:
-            noise_events(j, L, Dt, pair.t0_us, span, nz, env_id, log, hot)
-        prev = L
+            noise_events(j, Lc, Dt, pair.t0_us, span, nz, env_id, log, hot)
+        prev = Lc
     return log.array(), R, (tl.astype(np.int32) if track else None), K
 
 

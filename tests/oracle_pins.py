@@ -106,6 +106,19 @@ def pin_defocus_closed_forms(o):
     assert abs(var - sigma * sigma) < 0.02 * sigma * sigma
 
 
+def pin_log_channels(o):
+    """Colour events: each channel's own log, channel-major."""
+    x = np.array([[[1.0, 0.0, 100.0], [0.5, 2.0, 1e3]]])
+    got = o.log_channels(x)
+    assert got.shape == (3, 1, 2)
+    for c in range(3):
+        for i in range(2):
+            assert abs(float(got[c, 0, i]) - math.log(x[0, i, c] + 1e-3)) < 1e-12
+    # a grey pixel (R = G = B) has the luminance's log in every channel
+    g = np.full((2, 2, 3), 7.5)
+    assert np.allclose(o.log_channels(g), o.log_luminance(g)[None], rtol=0, atol=1e-12)
+
+
 def _field(H, W, vec=None):
     m = np.zeros((H, W, 2), F32)
     if vec is not None:
@@ -617,6 +630,45 @@ def pin_crossing_count_exact(o):
         assert o.crossing_count(a, c) == want, (float(a), float(c))
     assert o.crossing_count(F32(np.inf), F32(0.2)) == o.N_MAX
     assert o.crossing_count(F32(1e6), F32(0.01)) == o.N_MAX
+
+
+def pin_crop_margin(o):
+    """Content translating by an integer u per substep into view: with an
+    over-rendered margin of K|u| pixels every inner sub-frame is the exact
+    shifted texture, so the cropped events equal the event model run on the
+    exact inner frames (in cropped coordinates) and the margin's state is
+    untouched; without the margin the boundary pixels differ."""
+    rng = np.random.default_rng(53)
+    K, u, m = 4, (1, -1), 4
+    Hi, Wi = 14, 18                                    # inner size
+    big = rng.normal(0, 2, size=(Hi + 2 * m + 2 * K, Wi + 2 * m + 2 * K)).astype(F32)
+
+    def frame(j, mm):                                  # texture moving by j*u, frame with margin mm
+        oy, ox = K + m - mm - j * u[1], K + m - mm - j * u[0]
+        return big[oy:oy + Hi + 2 * mm, ox:ox + Wi + 2 * mm].copy()
+
+    def pair_for(mm):
+        H, W = Hi + 2 * mm, Wi + 2 * mm
+        mv = np.zeros((H, W, 2), F32)
+        mv[..., 0] = -K * u[0]
+        mv[..., 1] = -K * u[1]
+        Z = np.full((H, W), F32(2.0))
+        return o.Pair(frame(0, mm), frame(K, mm), mv, mv.copy(), Z, Z.copy(), 0, 16667)
+
+    s = o.Sensor(C_on=0.2, C_off=0.2, K=K)
+    p = pair_for(m)
+    L0 = p.L_A.copy()
+    t0 = np.full(p.shape, o.T_LAST_INIT, np.int32)
+    ev, R, tl, _ = o.step(p, s, L0, t0, env_id=2, crop_margin=m)
+    exact = [frame(j, 0) for j in range(K + 1)]
+    want, Rw, _ = o.emit_events(exact, 0, 16667, s, exact[0].copy(), np.full((Hi, Wi), o.T_LAST_INIT, np.int32), env_id=2)
+    assert len(ev) > 100 and np.array_equal(o.canonical(ev), o.canonical(want))
+    assert np.array_equal(R[m:-m, m:-m], Rw)
+    ring = np.ones(p.shape, bool)
+    ring[m:-m, m:-m] = False
+    assert np.array_equal(R[ring], L0[ring]) and np.all(tl[ring] == o.T_LAST_INIT)
+    ev0, _, _, _ = o.step(pair_for(0), s, frame(0, 0), None, env_id=2)
+    assert not np.array_equal(o.canonical(ev0), o.canonical(want))
 
 
 # ---------------------------------------------------------------------------

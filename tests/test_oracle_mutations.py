@@ -250,6 +250,16 @@ def m_defocus_radius(sigma):
     return int(math.ceil(2.0 * sigma))                      # planted: 2 sigma
 
 
+def m_crop_after_the_fact(pair, sensor, L_ref, t_last=None, env_id=0, crop_margin=0):
+    ev, R, tl, K = o.__dict__["_orig_step"](pair, sensor, L_ref, t_last, env_id)
+    m = crop_margin
+    H, W = pair.shape
+    if m and len(ev):                               # planted: full-frame events and state,
+        keep = (ev[:, 0] >= m) & (ev[:, 0] < W - m) & (ev[:, 1] >= m) & (ev[:, 1] < H - m)
+        ev = ev[keep]                               # coordinates not shifted
+    return ev, R, tl, K
+
+
 def m_pack_shift(ev):
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     word = ev[:, 0] | (ev[:, 1] << 12) | (ev[:, 3] << 22) | (ev[:, 4] << 23)   # planted
@@ -286,6 +296,7 @@ MUTANTS = [
     ("leak_random_polarity", "noise_events", _noise_variant(leak_pol=True), P.pin_leak_rate),
     ("defocus_zero_padding", "defocus", m_defocus_zero_padding, P.pin_defocus_library),
     ("defocus_radius_two_sigma", "defocus_radius", m_defocus_radius, P.pin_defocus_closed_forms),
+    ("crop_after_the_fact", "step", m_crop_after_the_fact, P.pin_crop_margin),
 ]
 
 
@@ -303,6 +314,7 @@ def test_pin_catches_mutant(monkeypatch, name, attr, mutant, pin):
     monkeypatch.setitem(o.__dict__, "_orig_skb", o.splat_keys_backward)
     monkeypatch.setitem(o.__dict__, "_orig_rts", o.resolve_two_splat)
     monkeypatch.setitem(o.__dict__, "_orig_philox", o.philox4x32)
+    monkeypatch.setitem(o.__dict__, "_orig_step", o.step)
     monkeypatch.setattr(o, attr, mutant)
     with pytest.raises((AssertionError, IndexError, ValueError)):
         pin(o)

@@ -166,7 +166,7 @@ typedef struct {
   evis_sensor sensor;
   evis_state state;
   int32_t env_id;             /* 0..EVIS_MAX_ENVS-1, written into each event */
-  int32_t reserved;
+  int32_t crop_margin;        /* over-render margin m >= 0 (0 = none), see evis_step_batch */
   const evis_noise *noise;    /* HOST pointer, or NULL: no noise events */
 } evis_env;
 
@@ -201,6 +201,16 @@ int evis_log_luminance(evis_ctx *ctx, const float *x, int32_t channels, int64_t 
 #define EVIS_MAX_DEFOCUS_DIM 16384
 int evis_defocus(evis_ctx *ctx, const float *x, int32_t H, int32_t W, int32_t channels, float sigma,
                  float *out, void *stream);
+
+/* Colour events (Sec. "HDR Event Formation Model": each of R, G, B in
+ * place of the luminance): x is [n][3] linear RGB, L_out is [3][n]
+ * (channel-major), L_c = ln(x_c + eps) with the library's own logarithm.
+ * Each channel plane is then the log frame of an env of its own (same
+ * motion vectors and depth; give each channel its own env_id, state and
+ * thresholds), so evis_step_batch emits the three colour streams in one
+ * launch.  eps > 0. */
+int evis_log_channels(evis_ctx *ctx, const float *x, int64_t n, float eps, float *L_out,
+                      void *stream);
 
 /* Initialise a pixel state from the first log frame: L_ref = L_first and,
  * when t_last is non-NULL, t_last = EVIS_T_LAST_INIT. */
@@ -249,7 +259,13 @@ int evis_generate_events(evis_ctx *ctx, const float *L_seq, int32_t H, int32_t W
  * (1..EVIS_MAX_ENVS; envs is a HOST array of descriptors) in one
  * persistent launch: substep count, sub-frames and events of every env,
  * all events appended to one stream.  All envs of a call use the same
- * EVIS_WARP_* (else EVIS_ERR_UNSUPPORTED); blends may differ.  K_used (device [n_envs], nullable)
+ * EVIS_WARP_* (else EVIS_ERR_UNSUPPORTED); blends may differ.  An env's
+ * crop_margin m (0 <= 2m < min(H, W)) marks an over-rendered margin of m
+ * pixels on every side (Sec. "Bidirectional Motion Vector Warping", last
+ * paragraph): the warp uses the whole frame, only the inner
+ * (H - 2m) x (W - 2m) pixels reach the event model and its noise, their
+ * events carry the cropped frame's coordinates, and L_ref / t_last of the
+ * margin are left untouched.  env.noise (nullable) adds sensor noise.  K_used (device [n_envs], nullable)
  * receives each env's K.  States are updated in place.  The launch
  * sequence is captured once into a HIP graph per (n_envs, out, cursor,
  * K_used, tuning) and replayed. */

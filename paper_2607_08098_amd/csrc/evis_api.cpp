@@ -489,6 +489,20 @@ int evis_log_luminance(evis_ctx* ctx, const float* x, int32_t channels, int64_t 
   return EVIS_OK;
 }
 
+int evis_log_channels(evis_ctx* ctx, const float* x, int64_t n, float eps, float* L_out,
+                      void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!x || !L_out || !aligned(x, 4) || !aligned(L_out, 4))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_log_channels: null or misaligned pointer");
+  if (n < 0) return fail(ctx, EVIS_ERR_INVALID, "evis_log_channels: n < 0");
+  if (!(eps > 0.0f) || !std::isfinite(eps))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_log_channels: eps must be > 0");
+  if (n == 0) return EVIS_OK;
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  EVIS_HIP(launch_log_channels(x, n, eps, L_out, (hipStream_t)stream), "k_log_channels");
+  return EVIS_OK;
+}
+
 int evis_defocus(evis_ctx* ctx, const float* x, int32_t H, int32_t W, int32_t channels, float sigma,
                  float* out, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;
@@ -663,7 +677,10 @@ static int validate_envs(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, Pl
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": env_id");
     rc = check_noise(ctx, v.noise, who);
     if (rc) return rc;
+    if (v.crop_margin < 0 || 2LL * v.crop_margin >= std::min(v.pair.H, v.pair.W))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": crop_margin must satisfy 0 <= 2m < min(H, W)");
     pl.desc.push_back(make_desc(v.pair, v.sensor, v.state, v.env_id, v.noise));
+    pl.desc.back().margin = v.crop_margin;
     if (pl.desc.back().warp != pl.desc[0].warp)
       return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": envs of one call need the same EVIS_WARP_*");
   }

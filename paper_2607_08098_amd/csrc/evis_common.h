@@ -50,6 +50,7 @@ struct EnvDesc {
   int64_t t0;
   int32_t span;                // t1 - t0 (us)
   int32_t warp;                // EVIS_WARP_*
+  int32_t margin;              // crop margin: only pixels m..W-m-1 x m..H-m-1 emit
   float4* srcB;                // two-splat warps only (else null): (-m_B.x, -m_B.y, Zstart,
                                // Z_B - Zstart) per source, Zstart = Z_A at p + m_B(p), same
                                // layout as src

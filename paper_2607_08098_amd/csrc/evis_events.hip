@@ -22,6 +22,18 @@ __global__ __launch_bounds__(kBlock) void k_log_luminance(const float* __restric
   }
 }
 
+// Colour events: each channel's own log, channel-major output.
+__global__ __launch_bounds__(kBlock) void k_log_channels(const float* __restrict__ x, long long n,
+                                                         float eps, float* __restrict__ L) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float r = x[3 * i], g = x[3 * i + 1], b = x[3 * i + 2];
+    L[i] = logf(r + eps);
+    L[n + i] = logf(g + eps);
+    L[2 * n + i] = logf(b + eps);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_state_init(const float* __restrict__ L, long long n,
                                                        float* __restrict__ Lref,
                                                        int32_t* __restrict__ tlast) {
@@ -187,6 +199,11 @@ hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s) {
   const size_t lds = (size_t)(inW * inH + kDefTW * inH) * sizeof(float);
   hipLaunchKernelGGL(k_defocus, dim3((a.W + kDefTW - 1) / kDefTW, (a.H + kDefTH - 1) / kDefTH, a.C),
                      dim3(kBlock), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_channels(const float* x, long long n, float eps, float* L, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_channels, dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, x, n, eps, L);
   return hipGetLastError();
 }
 

@@ -102,6 +102,7 @@ bool tile_shape_supported(int tile_w, int tile_h);
 
 hipError_t launch_log_luminance(const float* x, int channels, long long n, float eps, float* L,
                                 hipStream_t s);
+hipError_t launch_log_channels(const float* x, long long n, float eps, float* L, hipStream_t s);
 
 // Defocus (separable Gaussian blur of linear intensity): taps w[0..2r].
 constexpr int kDefocusMaxR = 30;

@@ -126,7 +126,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
       const int x = pix_x(k), y = pix_y(k);
-      const bool ok = (x <= Tx1) && (y <= Ty1);
+      // the fused step's event model covers only the pixels inside the crop
+      // margin (0 unless the env was rendered with one)
+      const int mg = (MODE == MODE_STEP) ? d.margin : 0;
+      const bool ok = (x <= Tx1) && (y <= Ty1) && x >= mg && y >= mg && x < W - mg && y < H - mg;
       const int qq = ok ? (y * W + x) : 0;
       okbits |= (ok ? 1u : 0u) << k;
       LAq[k] = ok ? ldg(d.LA, qq) : 0.0f;
@@ -144,7 +147,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
     }
     const PixAux aux{(MODE == MODE_STEP && d.th_on) ? s_con : nullptr,
                      (MODE == MODE_STEP && d.th_off) ? s_coff : nullptr, s_tl, d.C_on, d.C_off,
-                     Tx0, Ty0, TW, __builtin_ctz(TW), -1};
+                     Tx0 - (MODE == MODE_STEP ? d.margin : 0), Ty0 - (MODE == MODE_STEP ? d.margin : 0),
+                     TW, __builtin_ctz(TW), -1};   // event coordinates are the cropped frame's
     NoiseCfg ncfg{};
     uint32_t hotb = 0;
     if constexpr (NOISE != 0 && MODE == MODE_STEP) {

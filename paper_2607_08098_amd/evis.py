@@ -63,7 +63,7 @@ class EvisNoise(ctypes.Structure):
 
 class EvisEnv(ctypes.Structure):
     _fields_ = [("pair", EvisPair), ("sensor", EvisSensor), ("state", EvisState),
-                ("env_id", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("env_id", ctypes.c_int32), ("crop_margin", ctypes.c_int32),
                 ("noise", ctypes.POINTER(EvisNoise))]
 
 
@@ -91,6 +91,7 @@ SIGNATURES = {
     "evis_last_error": (ctypes.c_char_p, [_VP]),
     "evis_log_luminance": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                           _VP, _VP]),
+    "evis_log_channels": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_float, _VP, _VP]),
     "evis_defocus": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_float, _VP, _VP]),
     "evis_state_init": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32,
@@ -223,7 +224,8 @@ def make_noise(nz: dict) -> EvisNoise:
 def make_env(d: dict, keep: Optional[list] = None) -> EvisEnv:
     """d["noise"] (optional) is a make_noise dict; the EvisNoise it becomes
     is appended to `keep`, which must outlive every call that uses the env."""
-    env = EvisEnv(make_pair(d), make_sensor(d), make_state(d), int(d.get("env_id", 0)), 0)
+    env = EvisEnv(make_pair(d), make_sensor(d), make_state(d), int(d.get("env_id", 0)),
+                  int(d.get("crop_margin", 0)))
     if d.get("noise") is not None:
         nz = make_noise(d["noise"])
         if keep is None:
@@ -248,6 +250,15 @@ def evis_log_luminance(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=Non
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=x.device)
     ctx.check(ctx.lib.evis_log_luminance(ctx.handle, _ptr(x), channels, n, eps, _ptr(out), _stream(stream)))
+    return out
+
+
+def evis_log_channels(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=None, stream=None):
+    """x: [..., 3] linear RGB on the device -> [3, ...] per-channel log."""
+    n = x.numel() // 3
+    if out is None:
+        out = torch.empty((3,) + tuple(x.shape[:-1]), dtype=torch.float32, device=x.device)
+    ctx.check(ctx.lib.evis_log_channels(ctx.handle, _ptr(x), n, eps, _ptr(out), _stream(stream)))
     return out
 
 

@@ -36,6 +36,10 @@ in NVIDIA Isaac Sim".  Steps, in the paper's order:
                          from a Philox4x32-10 counter-based generator
   pack_events            the (x, y, t, p) event tuple of Sec. "Problem
                          Formulation" as an 8-byte record
+  voxel_grid             the per-polarity event voxel grid of the speed
+                         estimation experiment (128 temporal bins, linear
+                         interpolation in time, each bin divided by its
+                         maximum; R26)
   step / interpolate     the whole per-pair path
 
 Precision.  Everything from the log intensity onwards is float32, every
@@ -98,6 +102,15 @@ Readings of the paper taken here (each is restated where it is used):
       crop margin m the warp runs on the whole rendered frame and only the
       inner pixels reach the event model (and the noise), in the cropped
       frame's coordinates; the margin keeps its state untouched.
+  R26 voxel grid: events of one env with t0 <= t < t1 go to position
+      tau = (t - t0) * s, s = fl32(fl32(B - 1) / fl32(t1 - t0)) (float32),
+      b = floor(tau) (at most B - 1), weight of bin b + 1 q = floor((tau - b)
+      2^16) / 2^16 and of bin b 1 - q (bin B - 1 alone at tau >= B - 1): the
+      weights are 16-bit fixed point so that the sums are integers (exact,
+      order-free; uint32, modulo 2^32, so a voxel holds 65535 events); then
+      each (polarity, bin) plane is divided by its maximum in float32
+      (fl32(acc) / fl32(max), all zero when empty).  Layout [2][B][H][W],
+      polarity 0 = OFF first.
   R23 noise events are extra: they do not move L_ref, ignore the
       refractory period and leave t_last alone.
   R19 joint warp (WARP_JOINT): one z-buffer over the sources of both
@@ -765,3 +778,49 @@ def canonical(ev: np.ndarray) -> np.ndarray:
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     order = np.lexsort((ev[:, 3], ev[:, 0], ev[:, 1], ev[:, 2], ev[:, 4]))
     return ev[order]
+
+
+# ---------------------------------------------------------------------------
+# event voxel grid (R26)
+# ---------------------------------------------------------------------------
+
+VOXEL_ONE = 1 << 16      # one event's total weight in the fixed-point sums
+
+
+def voxel_weights(t, t0_us: int, t1_us: int, bins: int):
+    """Per event time: (bin b, fixed-point weight of b, of b + 1)."""
+    s = F32(F32(bins - 1) / F32(t1_us - t0_us))
+    tau = (np.asarray(t, np.int64) - t0_us).astype(F32) * s
+    b = np.floor(tau).astype(np.int64)
+    last = b >= bins - 1
+    b = np.where(last, bins - 1, b)
+    q1 = np.floor((tau - b.astype(F32)) * F32(VOXEL_ONE)).astype(np.int64)
+    q1 = np.where(last, 0, q1)
+    return b, VOXEL_ONE - q1, q1
+
+
+def voxel_counts(ev, env_id: int, H: int, W: int, t0_us: int, t1_us: int, bins: int = 128):
+    """Fixed-point sums [2][bins][H][W] (uint64 here; the grid keeps them
+    modulo 2^32)."""
+    ev = np.asarray(ev, np.int64).reshape(-1, 5)
+    sel = (ev[:, 4] == env_id) & (ev[:, 2] >= t0_us) & (ev[:, 2] < t1_us)
+    ev = ev[sel]
+    acc = np.zeros((2, bins, H, W), np.uint64)
+    b, q0, q1 = voxel_weights(ev[:, 2], t0_us, t1_us, bins)
+    x, y, p = ev[:, 0], ev[:, 1], ev[:, 3]
+    np.add.at(acc, (p, b, y, x), q0.astype(np.uint64))
+    nxt = q1 > 0
+    np.add.at(acc, (p[nxt], b[nxt] + 1, y[nxt], x[nxt]), q1[nxt].astype(np.uint64))
+    return acc
+
+
+def voxel_grid(ev, env_id: int, H: int, W: int, t0_us: int, t1_us: int, bins: int = 128):
+    """Normalised per-polarity voxel grid, float32 [2][bins][H][W] (R26)."""
+    acc = voxel_counts(ev, env_id, H, W, t0_us, t1_us, bins) & np.uint64(0xFFFF_FFFF)
+    mx = acc.reshape(2, bins, -1).max(axis=2)
+    out = np.zeros((2, bins, H, W), F32)
+    for p in range(2):
+        for b in range(bins):
+            if mx[p, b] > 0:
+                out[p, b] = acc[p, b].astype(F32) / F32(mx[p, b])
+    return out

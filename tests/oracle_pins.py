@@ -769,6 +769,51 @@ def pin_noise_off_and_seeded(o):
 
 
 # ---------------------------------------------------------------------------
+# voxel grid
+# ---------------------------------------------------------------------------
+
+def pin_voxel_closed_forms(o):
+    """Hand-worked cases on a dyadic time scale (s = 4 / 1024 = 2^-8 exact):
+    an event on a bin point fills that bin alone, one halfway splits evenly,
+    and every non-empty (polarity, bin) plane peaks at exactly 1."""
+    ev = np.array([[1, 2, 256, 1, 0],      # tau = 1.0   -> bin 1
+                   [3, 0, 384, 0, 0],      # tau = 1.5   -> bins 1, 2 halves
+                   [3, 0, 1023, 0, 0],     # tau = 3.996 -> bin 3 (and 4)
+                   [0, 0, 100, 1, 1],      # another env
+                   [0, 1, 1024, 1, 0],     # t = t1: outside the window
+                   [0, 1, -1, 1, 0]])      # before t0
+    acc = o.voxel_counts(ev, 0, 3, 4, 0, 1024, 5)
+    assert acc[1, 1, 2, 1] == 65536 and int(acc[1].sum()) == 65536
+    assert acc[0, 1, 0, 3] == 32768 and acc[0, 2, 0, 3] == 32768
+    q1 = int(np.floor((1023 / 256 - 3) * 65536))
+    assert acc[0, 3, 0, 3] == 65536 - q1 and acc[0, 4, 0, 3] == q1
+    v = o.voxel_grid(ev, 0, 3, 4, 0, 1024, 5)
+    assert v[1, 1, 2, 1] == 1.0 and v[0, 1, 0, 3] == 1.0 and v[0, 2, 0, 3] == 1.0
+    assert np.count_nonzero(v) == 5
+
+
+def pin_voxel_invariants(o):
+    """Random events: each event in the window adds exactly one unit of
+    weight, whose centroid is its exact time position to within 2/2^16; each
+    non-empty plane of the normalised grid has maximum 1."""
+    rng = np.random.default_rng(59)
+    n, H, W, B, t0, t1 = 3000, 9, 11, 128, 1000, 501000
+    ev = np.stack([rng.integers(0, W, n), rng.integers(0, H, n), rng.integers(t0 - 5000, t1 + 5000, n),
+                   rng.integers(0, 2, n), rng.integers(0, 2, n)], axis=1)
+    inside = (ev[:, 4] == 1) & (ev[:, 2] >= t0) & (ev[:, 2] < t1)
+    acc = o.voxel_counts(ev, 1, H, W, t0, t1, B).astype(np.int64)
+    assert int(acc.sum()) == int(inside.sum()) * 65536
+    bidx = np.arange(B).reshape(1, B, 1, 1)
+    cent = float((acc * bidx).sum())
+    want = float(((ev[inside, 2] - t0) * (B - 1) / (t1 - t0)).sum()) * 65536
+    assert abs(cent - want) <= 2.0 * inside.sum()
+    v = o.voxel_grid(ev, 1, H, W, t0, t1, B)
+    mx = v.reshape(2, B, -1).max(axis=2)
+    assert np.all((mx == 1.0) | (mx == 0.0)) and np.all(mx[acc.reshape(2, B, -1).max(axis=2) > 0] == 1.0)
+    assert v.min() >= 0.0
+
+
+# ---------------------------------------------------------------------------
 # event record
 # ---------------------------------------------------------------------------
 

@@ -260,6 +260,17 @@ def m_crop_after_the_fact(pair, sensor, L_ref, t_last=None, env_id=0, crop_margi
     return ev, R, tl, K
 
 
+def m_voxel_weights_swapped(t, t0_us, t1_us, bins):
+    b, q0, q1 = o.__dict__["_orig_vw"](t, t0_us, t1_us, bins)
+    return b, q1 + (q0 - q1) * (q1 == 0), q0 * (q1 != 0)    # planted: weights on the wrong bins
+
+
+def m_voxel_global_max(ev, env_id, H, W, t0_us, t1_us, bins=128):
+    acc = o.voxel_counts(ev, env_id, H, W, t0_us, t1_us, bins) & np.uint64(0xFFFF_FFFF)
+    mx = acc.max()                                          # planted: one maximum for all bins
+    return (acc.astype(F32) / F32(mx)) if mx > 0 else np.zeros(acc.shape, F32)
+
+
 def m_pack_shift(ev):
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     word = ev[:, 0] | (ev[:, 1] << 12) | (ev[:, 3] << 22) | (ev[:, 4] << 23)   # planted
@@ -297,6 +308,8 @@ MUTANTS = [
     ("defocus_zero_padding", "defocus", m_defocus_zero_padding, P.pin_defocus_library),
     ("defocus_radius_two_sigma", "defocus_radius", m_defocus_radius, P.pin_defocus_closed_forms),
     ("crop_after_the_fact", "step", m_crop_after_the_fact, P.pin_crop_margin),
+    ("voxel_weights_swapped", "voxel_weights", m_voxel_weights_swapped, P.pin_voxel_invariants),
+    ("voxel_global_max", "voxel_grid", m_voxel_global_max, P.pin_voxel_closed_forms),
 ]
 
 
@@ -315,6 +328,7 @@ def test_pin_catches_mutant(monkeypatch, name, attr, mutant, pin):
     monkeypatch.setitem(o.__dict__, "_orig_rts", o.resolve_two_splat)
     monkeypatch.setitem(o.__dict__, "_orig_philox", o.philox4x32)
     monkeypatch.setitem(o.__dict__, "_orig_step", o.step)
+    monkeypatch.setitem(o.__dict__, "_orig_vw", o.voxel_weights)
     monkeypatch.setattr(o, attr, mutant)
     with pytest.raises((AssertionError, IndexError, ValueError)):
         pin(o)

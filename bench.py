@@ -17,7 +17,8 @@ fused form on the same GPU; the roofline of the fused tile kernel, timed
 live with HIP events; the same kernel with B splatted backward (the
 two-splat warps: own z-buffer with B primary, and one joint z-buffer) and
 with sensor noise (leak 0.1 Hz, shot 1 Hz, 0.1% hot pixels at 100 Hz);
-the defocus blur of every env's keyframe (sigma 0.5 px);
+the defocus blur of every env's keyframe (sigma 0.5 px); the 128-bin
+voxel grid of one 1280x720 env from one step's event stream;
 the CPU oracle on a bounded sample of the same workload (rank 0, N = 1
 only).
 """
@@ -378,15 +379,14 @@ def main():
                                              frac=round(wach / ALU_PEAK_TOPS, 4)))
             log(f"warp {name}: tile kernel {wms:.3f} ms")
 
-    # defocus of every env's new keyframe (one launch per env, sigma 0.5 px):
+    # defocus of every env's new keyframe (one batched launch, sigma 0.5 px):
     # HBM-bound, 8 algorithmic bytes per pixel (one read, one write)
     if args.warp_steps > 0:
         blurred = torch.empty_like(batch.I_B)
         views = [(batch.view(batch.I_B, e), batch.view(blurred, e)) for e in range(n_envs)]
 
         def defocus_all():
-            for src, dst in views:
-                evis.evis_defocus(ctx, src, 0.5, out=dst)
+            evis.evis_defocus_batch(ctx, views, 0.5)
 
         defocus_all()
         torch.cuda.synchronize()
@@ -416,12 +416,40 @@ def main():
         dms = e0.elapsed_time(e1) / args.warp_steps
         gbs = 8.0 * float(px.sum()) / (dms / 1e3) / 1e9
         warps["defocus_sigma0.5"] = dict(ms_per_step=round(dms, 4), eager_ms_per_step=round(eager_ms, 4),
-                                         launches=n_envs,
+                                         images=n_envs, launches=(n_envs + 63) // 64,
                                          roofline=dict(bound="hbm", achieved=round(gbs, 1),
                                                        peak=HBM_PEAK_GBS, unit="GB/s",
                                                        frac=round(gbs / HBM_PEAK_GBS, 4)))
-        log(f"defocus: {dms:.3f} ms (graph), {eager_ms:.3f} ms (eager) for {n_envs} envs, {gbs:.0f} GB/s")
+        log(f"defocus: {dms:.3f} ms (graph), {eager_ms:.3f} ms (eager) for {n_envs} images, {gbs:.0f} GB/s")
         del blurred, views, graph
+
+    # voxel grid (128 bins per polarity) of one 1280x720 env from one step's
+    # stream: HBM-bound, 8 algorithmic bytes per event read and per voxel
+    # written
+    if args.warp_steps > 0:
+        n_total.zero_()
+        step()
+        torch.cuda.synchronize()
+        ve = n_envs - 1
+        vh, vw = batch.shapes[ve]
+        grid = torch.empty((2, 128, vh, vw), dtype=torch.float32, device="cuda")
+        evis.evis_voxel_grid(ctx, out, n_total, ve, vh, vw, 0, 16667, 128, out=grid)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.warp_steps):
+            evis.evis_voxel_grid(ctx, out, n_total, ve, vh, vw, 0, 16667, 128, out=grid)
+        e1.record()
+        torch.cuda.synchronize()
+        vms = e0.elapsed_time(e1) / args.warp_steps
+        nev = min(int(n_total.item()), out.shape[0])
+        vbytes = 8.0 * nev + 8.0 * grid.numel()
+        vgbs = vbytes / (vms / 1e3) / 1e9
+        warps["voxel_grid_128"] = dict(ms=round(vms, 4), env=f"{vw}x{vh}", stream_events=nev,
+                                       roofline=dict(bound="hbm", achieved=round(vgbs, 1),
+                                                     peak=HBM_PEAK_GBS, unit="GB/s",
+                                                     frac=round(vgbs / HBM_PEAK_GBS, 4)))
+        log(f"voxel grid: {vms:.3f} ms ({nev} events scanned), {vgbs:.0f} GB/s")
+        del grid
 
     # per-env-launch plain form: every sub-frame to HBM, then the event model
     plain = None

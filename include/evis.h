@@ -202,6 +202,17 @@ int evis_log_luminance(evis_ctx *ctx, const float *x, int32_t channels, int64_t 
 int evis_defocus(evis_ctx *ctx, const float *x, int32_t H, int32_t W, int32_t channels, float sigma,
                  float *out, void *stream);
 
+/* The same blur of n images (imgs a HOST array; each image's own H, W;
+ * the same channels and sigma), as few launches as possible (up to 64
+ * images share one), so that many small frames fill the GPU. */
+typedef struct {
+  const float *x;
+  float *out;
+  int32_t H, W;
+} evis_image;
+int evis_defocus_batch(evis_ctx *ctx, const evis_image *imgs, int32_t n, int32_t channels,
+                       float sigma, void *stream);
+
 /* Colour events (Sec. "HDR Event Formation Model": each of R, G, B in
  * place of the luminance): x is [n][3] linear RGB, L_out is [3][n]
  * (channel-major), L_c = ln(x_c + eps) with the library's own logarithm.
@@ -333,6 +344,22 @@ int evis_soft_count_forward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_
 int evis_soft_count_backward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n_envs, int32_t K,
                              float tau, int32_t blend_mode, const float *C, float *gC,
                              int32_t flags, void *stream);
+
+/* Event voxel grid (the per-polarity, 128-bin input of the paper's speed
+ * estimator): events[0 .. min(*n_events, capacity)) (n_events a DEVICE
+ * int64, e.g. the cursor of evis_step_batch) of env env_id with
+ * t0_us <= t < t1_us, at tau = (t - t0) * s with s = fl32(fl32(bins - 1) /
+ * fl32(t1 - t0)) (float32), add 1 - q to bin b = floor(tau) and q to bin
+ * b + 1, q = floor((tau - b) 2^16) / 2^16 (an event at tau >= bins - 1 goes
+ * to the last bin alone), summed in 16-bit fixed point as uint32 (exact,
+ * order-free; a voxel holds 65535 events, beyond which it wraps); then each
+ * (polarity, bin) plane is divided by its maximum in float32 (all zero
+ * when empty).  out is [2][bins][H][W] float32, polarity 0 (OFF) first;
+ * it is also the accumulator.  2 <= bins <= EVIS_MAX_VOXEL_BINS. */
+#define EVIS_MAX_VOXEL_BINS 1024
+int evis_voxel_grid(evis_ctx *ctx, const evis_event *events, const int64_t *n_events,
+                    int64_t capacity, int32_t env_id, int32_t H, int32_t W, int64_t t0_us,
+                    int64_t t1_us, int32_t bins, float *out, void *stream);
 
 /* Kernel timing.  While profiling is enabled, each call records HIP events
  * on its stream around its main kernel (the fused tile kernel of

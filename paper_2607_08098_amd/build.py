@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libevis.so")
 
 SOURCES = ["evis_api.cpp", "evis_tile.hip", "evis_tile_splat.hip", "evis_tile_noise.hip",
-           "evis_events.hip", "evis_soft.hip"]
+           "evis_events.hip", "evis_soft.hip", "evis_voxel.hip"]
 
 # -ffp-contract=off and correctly rounded division: every float32 operation of
 # the event path is one IEEE operation rounded to nearest, as written.

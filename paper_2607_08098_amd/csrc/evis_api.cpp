@@ -46,6 +46,7 @@ struct evis_ctx {
   DevBuf tbB;         // two-splat warps: bounds of -m_B per block
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
+  DevBuf voxmax;      // per-plane maxima of evis_voxel_grid
   std::vector<unsigned char> soft_shadow;
   // host staging of the descriptor block (pinned ring)
   void* stage[kStageSlots] = {};
@@ -460,7 +461,7 @@ void evis_destroy(evis_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   DevBuf* bufs[] = {&ctx->meta, &ctx->dyn,  &ctx->sched, &ctx->src, &ctx->tb,
-                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft};
+                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft, &ctx->voxmax};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {
@@ -503,28 +504,65 @@ int evis_log_channels(evis_ctx* ctx, const float* x, int64_t n, float eps, float
   return EVIS_OK;
 }
 
-int evis_defocus(evis_ctx* ctx, const float* x, int32_t H, int32_t W, int32_t channels, float sigma,
-                 float* out, void* stream) {
+int evis_voxel_grid(evis_ctx* ctx, const evis_event* events, const int64_t* n_events,
+                    int64_t capacity, int32_t env_id, int32_t H, int32_t W, int64_t t0_us,
+                    int64_t t1_us, int32_t bins, float* out, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;
-  if (!x || !out || !aligned(x, 4) || !aligned(out, 4))
-    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: null or misaligned pointer");
-  if (channels != 1 && channels != 3)
-    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: channels must be 1 or 3");
-  if (H < 1 || W < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: H, W");
-  if (H > EVIS_MAX_DEFOCUS_DIM || W > EVIS_MAX_DEFOCUS_DIM)
-    return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_defocus: H, W > 16384");
-  if (!(sigma > 0.0f && sigma <= EVIS_MAX_DEFOCUS_SIGMA))
-    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: sigma must be in (0, 10]");
-  const size_t bytes = (size_t)H * W * channels * sizeof(float);
-  const char* xb = reinterpret_cast<const char*>(x);
-  const char* ob = reinterpret_cast<const char*>(out);
-  if (xb < ob + bytes && ob < xb + bytes)
-    return fail(ctx, EVIS_ERR_INVALID, "evis_defocus: out overlaps x");
-  DefocusArgs a{};
-  a.x = x;
-  a.out = out;
+  if (!n_events || !aligned(n_events, 8)) return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: n_events");
+  if (capacity < 0 || (capacity > 0 && (!events || !aligned(events, 8))))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: events / capacity");
+  if (!out || !aligned(out, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: out");
+  if (H < 1 || W < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: H, W");
+  if (H > EVIS_MAX_DIM || W > EVIS_MAX_DIM)
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, "evis_voxel_grid: H, W > 2047");
+  if (bins < 2 || bins > EVIS_MAX_VOXEL_BINS)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: bins must be in 2..1024");
+  if (env_id < 0 || env_id >= EVIS_MAX_ENVS) return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: env_id");
+  if (t1_us <= t0_us || t0_us < INT32_MIN || t1_us > (int64_t)INT32_MAX + 1)
+    return fail(ctx, EVIS_ERR_INVALID, "evis_voxel_grid: need t0 < t1 within int32 time");
+  VoxelArgs a{};
+  a.events = events;
+  a.n_events = reinterpret_cast<const long long*>(n_events);
+  a.capacity = capacity;
+  a.acc = reinterpret_cast<uint32_t*>(out);
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  int rc = ensure(ctx, ctx->voxmax, (size_t)2 * bins * sizeof(uint32_t));
+  if (rc) return rc;
+  a.maxbuf = static_cast<uint32_t*>(ctx->voxmax.p);
+  a.t0 = t0_us;
+  a.t1 = t1_us;
+  a.scale = (float)(bins - 1) / (float)(t1_us - t0_us);
+  a.env_id = env_id;
   a.H = H;
   a.W = W;
+  a.bins = bins;
+  EVIS_HIP(launch_voxel(a, (hipStream_t)stream), "k_voxel");
+  return EVIS_OK;
+}
+
+int evis_defocus_batch(evis_ctx* ctx, const evis_image* imgs, int32_t n, int32_t channels,
+                       float sigma, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  const char* who = "evis_defocus";
+  if (!imgs || n < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": no images");
+  if (channels != 1 && channels != 3)
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": channels must be 1 or 3");
+  if (!(sigma > 0.0f && sigma <= EVIS_MAX_DEFOCUS_SIGMA))
+    return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": sigma must be in (0, 10]");
+  for (int i = 0; i < n; ++i) {
+    const evis_image& im = imgs[i];
+    if (!im.x || !im.out || !aligned(im.x, 4) || !aligned(im.out, 4))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": null or misaligned pointer");
+    if (im.H < 1 || im.W < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": H, W");
+    if (im.H > EVIS_MAX_DEFOCUS_DIM || im.W > EVIS_MAX_DEFOCUS_DIM)
+      return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": H, W > 16384");
+    const size_t bytes = (size_t)im.H * im.W * channels * sizeof(float);
+    const char* xb = reinterpret_cast<const char*>(im.x);
+    const char* ob = reinterpret_cast<const char*>(im.out);
+    if (xb < ob + bytes && ob < xb + bytes)
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": out overlaps x");
+  }
+  DefocusArgs a{};
   a.C = channels;
   a.r = (int)std::ceil(3.0 * (double)sigma);
   double w[2 * kDefocusMaxR + 1], sum = 0.0;
@@ -534,8 +572,26 @@ int evis_defocus(evis_ctx* ctx, const float* x, int32_t H, int32_t W, int32_t ch
   }
   for (int k = 0; k <= 2 * a.r; ++k) a.w[k] = (float)(w[k] / sum);
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  EVIS_HIP(launch_defocus(a, (hipStream_t)stream), "k_defocus");
+  for (int i0 = 0; i0 < n; i0 += kDefocusBatch) {   // up to kDefocusBatch images per launch
+    a.n = std::min(kDefocusBatch, n - i0);
+    int tiles = 0;
+    for (int i = 0; i < a.n; ++i) {
+      const evis_image& im = imgs[i0 + i];
+      a.img[i] = DefocusImage{im.x, im.out, im.H, im.W, 0, 0};
+      a.tile_prefix[i] = tiles;
+      tiles += defocus_tiles(im.H, im.W, &a.img[i].tiles_x);
+    }
+    a.tile_prefix[a.n] = tiles;
+    EVIS_HIP(launch_defocus(a, (hipStream_t)stream), "k_defocus");
+  }
   return EVIS_OK;
+}
+
+int evis_defocus(evis_ctx* ctx, const float* x, int32_t H, int32_t W, int32_t channels, float sigma,
+                 float* out, void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  const evis_image im{x, out, H, W};
+  return evis_defocus_batch(ctx, &im, 1, channels, sigma, stream);
 }
 
 int evis_state_init(evis_ctx* ctx, const float* L_first, int32_t H, int32_t W,

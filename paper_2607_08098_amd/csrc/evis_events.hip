@@ -148,31 +148,72 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   sink_flush(sh, so);
 }
 
-// Defocus: one workgroup per 64 x 16 output tile of one channel.  The
+// Defocus: one workgroup per 64 x 16 output tile of one channel of one
+// image of the batch (many small images fill the chip in one launch).  The
 // input tile with an apron of r pixels (edge pixels repeated) goes to LDS,
 // then the horizontal pass over all its rows into LDS, then the vertical
-// pass to the output; each output sums its 2r + 1 taps in order, k = -r..r.
-// HBM-bound: one read and one write of the image (plus the aprons).
+// pass to the output; each output sums its 2r + 1 taps in order, k = -r..r,
+// with the weights read from LDS.  HBM-bound: one read and one write of
+// each image (plus the aprons).
 constexpr int kDefTW = 64, kDefTH = 16;
+
+int defocus_tiles(int H, int W, int* tiles_x) {
+  *tiles_x = (W + kDefTW - 1) / kDefTW;
+  return *tiles_x * ((H + kDefTH - 1) / kDefTH);
+}
 
 __global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
   extern __shared__ float smem[];
-  const int r = a.r, C = a.C, W = a.W, H = a.H, c = blockIdx.z;
+  __shared__ float s_w[2 * kDefocusMaxR + 1];
+  const int r = a.r, C = a.C, c = blockIdx.y;
+  // image of this tile: the last one whose first tile is <= blockIdx.x
+  const int tile = blockIdx.x;
+  int lo = 0, hi = a.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.tile_prefix[mid] <= tile) lo = mid; else hi = mid - 1;
+  }
+  const DefocusImage im = a.img[lo];
+  const int lt = tile - a.tile_prefix[lo];
+  const int W = im.W, H = im.H;
   const int inW = kDefTW + 2 * r, inH = kDefTH + 2 * r;
   float* in = smem;                 // [inH][inW]
   float* hb = smem + inW * inH;     // [inH][kDefTW]
-  const int x0 = blockIdx.x * kDefTW, y0 = blockIdx.y * kDefTH;
-  for (int i = threadIdx.x; i < inW * inH; i += kBlock) {
-    const int gx = min(max(x0 - r + i % inW, 0), W - 1);
-    const int gy = min(max(y0 - r + i / inW, 0), H - 1);
-    in[i] = a.x[((long long)gy * W + gx) * C + c];
+  const int x0 = (lt % im.tiles_x) * kDefTW, y0 = (lt / im.tiles_x) * kDefTH;
+  for (int k = threadIdx.x; k <= 2 * r; k += kBlock) s_w[k] = a.w[k];
+  // the apron tile, all threads at once, four loads in flight per thread;
+  // element i sits at (i % inW, i / inW), stepped by kBlock incrementally
+  {
+    const int n = inW * inH;
+    const int dx = kBlock % inW, dy = kBlock / inW;
+    int lx = threadIdx.x % inW, ly = threadIdx.x / inW;
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * kBlock) {
+      float v[4];
+      int idx[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        idx[u] = i0 + u * kBlock;
+        const int gx = min(max(x0 - r + lx, 0), W - 1);
+        const int gy = min(max(y0 - r + ly, 0), H - 1);
+        v[u] = (idx[u] < n) ? im.x[((long long)gy * W + gx) * C + c] : 0.0f;
+        lx += dx;
+        ly += dy;
+        if (lx >= inW) {
+          lx -= inW;
+          ++ly;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (idx[u] < n) in[idx[u]] = v[u];
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kDefTW * inH; i += kBlock) {
     const int col = i % kDefTW, row = i / kDefTW;
     const float* src = in + row * inW + col;
     float acc = 0.0f;
-    for (int k = 0; k <= 2 * r; ++k) acc = acc + a.w[k] * src[k];
+    for (int k = 0; k <= 2 * r; ++k) acc = acc + s_w[k] * src[k];
     hb[i] = acc;
   }
   __syncthreads();
@@ -182,8 +223,8 @@ __global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
     if (gx >= W || gy >= H) continue;
     const float* src = hb + row * kDefTW + col;
     float acc = 0.0f;
-    for (int k = 0; k <= 2 * r; ++k) acc = acc + a.w[k] * src[k * kDefTW];
-    a.out[((long long)gy * W + gx) * C + c] = acc;
+    for (int k = 0; k <= 2 * r; ++k) acc = acc + s_w[k] * src[k * kDefTW];
+    im.out[((long long)gy * W + gx) * C + c] = acc;
   }
 }
 
@@ -197,8 +238,7 @@ static int grid_for(long long n, int per_block) {
 hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s) {
   const int inW = kDefTW + 2 * a.r, inH = kDefTH + 2 * a.r;
   const size_t lds = (size_t)(inW * inH + kDefTW * inH) * sizeof(float);
-  hipLaunchKernelGGL(k_defocus, dim3((a.W + kDefTW - 1) / kDefTW, (a.H + kDefTH - 1) / kDefTH, a.C),
-                     dim3(kBlock), lds, s, a);
+  hipLaunchKernelGGL(k_defocus, dim3(a.tile_prefix[a.n], a.C), dim3(kBlock), lds, s, a);
   return hipGetLastError();
 }
 

@@ -104,15 +104,40 @@ hipError_t launch_log_luminance(const float* x, int channels, long long n, float
                                 hipStream_t s);
 hipError_t launch_log_channels(const float* x, long long n, float eps, float* L, hipStream_t s);
 
-// Defocus (separable Gaussian blur of linear intensity): taps w[0..2r].
+// Event voxel grid: acc is the output grid [2][bins][H][W], used as uint32
+// sums before it is normalised in place.
+struct VoxelArgs {
+  const evis_event* events;
+  const long long* n_events;   // device cursor
+  long long capacity;
+  uint32_t* acc;
+  uint32_t* maxbuf;            // scratch [2 * bins]: per-plane maxima
+  long long t0, t1;
+  float scale;                 // fl32(fl32(bins - 1) / fl32(t1 - t0))
+  int32_t env_id, H, W, bins;
+};
+hipError_t launch_voxel(const VoxelArgs& a, hipStream_t s);
+
+// Defocus (separable Gaussian blur of linear intensity) of up to
+// kDefocusBatch images in one launch: taps w[0..2r]; image i owns output
+// tiles [tile_prefix[i], tile_prefix[i + 1]).
 constexpr int kDefocusMaxR = 30;
-struct DefocusArgs {
+constexpr int kDefocusBatch = 64;
+struct DefocusImage {
   const float* x;
   float* out;
-  int32_t H, W, C, r;
+  int32_t H, W;
+  int32_t tiles_x;   // 64-wide tiles per row
+  int32_t pad;
+};
+struct DefocusArgs {
+  DefocusImage img[kDefocusBatch];
+  int32_t tile_prefix[kDefocusBatch + 1];
+  int32_t n, C, r;
   float w[2 * kDefocusMaxR + 1];
 };
 hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s);
+int defocus_tiles(int H, int W, int* tiles_x);
 hipError_t launch_state_init(const float* L_first, long long n, float* L_ref, int32_t* t_last,
                              hipStream_t s);
 hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, int span,

@@ -1,0 +1,102 @@
+// Event voxel grid (the per-polarity, 128-bin representation of the
+// paper's speed-estimation experiment): events of one env in [t0, t1) are
+// spread over two neighbouring time bins by linear interpolation, in 16-bit
+// fixed point so that the sums are integers (uint32 atomics, exact and
+// independent of order), then each (polarity, bin) plane is divided by its
+// maximum.  HBM-bound: one pass over the event stream, a fill, a read for
+// the plane maxima and a read-write pass over the grid.
+#include "evis_internal.h"
+
+namespace evis {
+
+constexpr uint32_t kVoxelOne = 1u << 16;
+
+__global__ __launch_bounds__(kBlock) void k_voxel_fill(uint32_t* __restrict__ acc, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc[i] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_voxel_acc(const VoxelArgs a) {
+  const long long n = min((long long)*a.n_events, a.capacity);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long plane = (long long)a.H * a.W;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const evis_event e = a.events[i];
+    const uint32_t w = e.xyp;
+    if ((int)(w >> 23) != a.env_id) continue;
+    const long long t = e.t_us;
+    if (t < a.t0 || t >= a.t1) continue;
+    const int x = (int)(w & 0x7FFu), y = (int)((w >> 11) & 0x7FFu), p = (int)((w >> 22) & 1u);
+    if (x >= a.W || y >= a.H) continue;
+    const float tau = (float)(t - a.t0) * a.scale;
+    int b = (int)floorf(tau);
+    uint32_t q1 = 0u;
+    if (b >= a.bins - 1) {
+      b = a.bins - 1;
+    } else {
+      q1 = (uint32_t)floorf((tau - (float)b) * 65536.0f);
+    }
+    uint32_t* base = a.acc + ((long long)(p * a.bins + b) * plane + (long long)y * a.W + x);
+    atomicAdd(base, kVoxelOne - q1);
+    if (q1) atomicAdd(base + plane, q1);
+  }
+}
+
+// Per (polarity, bin) plane maximum: workgroup (chunk, plane) reduces a
+// chunk of the plane and raises the plane's maximum with one atomic.
+__global__ __launch_bounds__(kBlock) void k_voxel_max(const uint32_t* __restrict__ acc, long long plane,
+                                                      long long chunk, uint32_t* maxbuf) {
+  __shared__ uint32_t s_max[kWavesPerBlock];
+  const uint32_t* pl = acc + (long long)blockIdx.y * plane;
+  const long long i0 = (long long)blockIdx.x * chunk, i1 = min(plane, i0 + chunk);
+  uint32_t m = 0u;
+  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) m = max(m, pl[i]);
+  for (int off = kWave / 2; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t mx = 0u;
+    for (int k = 0; k < kWavesPerBlock; ++k) mx = max(mx, s_max[k]);
+    if (mx) atomicMax(maxbuf + blockIdx.y, mx);
+  }
+}
+
+// Each voxel divided by its plane's maximum, in place (uint32 sums in,
+// float32 out).
+__global__ __launch_bounds__(kBlock) void k_voxel_div(uint32_t* __restrict__ acc, long long plane,
+                                                      long long total, const uint32_t* maxbuf) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  float* out = reinterpret_cast<float*>(acc);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const uint32_t mx = maxbuf[i / plane];
+    const uint32_t v = acc[i];
+    out[i] = mx ? (float)v / (float)mx : 0.0f;
+  }
+}
+
+hipError_t launch_voxel(const VoxelArgs& a, hipStream_t s) {
+  const long long plane = (long long)a.H * a.W;
+  const long long total = 2LL * a.bins * plane;
+  const int fill_blocks = (int)std::min<long long>((total + kBlock - 1) / kBlock, 256LL * 8);
+  hipLaunchKernelGGL(k_voxel_fill, dim3(fill_blocks), dim3(kBlock), 0, s, a.acc, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_voxel_fill, dim3(1), dim3(kBlock), 0, s, a.maxbuf, 2LL * a.bins);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int acc_blocks = (int)std::max<long long>(1, std::min<long long>((a.capacity + kBlock - 1) / kBlock, 256LL * 8));
+  hipLaunchKernelGGL(k_voxel_acc, dim3(acc_blocks), dim3(kBlock), 0, s, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // enough workgroups to fill the chip: chunks of at least 16 K voxels
+  const long long chunk = std::max<long long>(16384, (plane + 7) / 8);
+  const int nchunks = (int)((plane + chunk - 1) / chunk);
+  hipLaunchKernelGGL(k_voxel_max, dim3(nchunks, 2 * a.bins), dim3(kBlock), 0, s, a.acc, plane, chunk,
+                     a.maxbuf);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_voxel_div, dim3(fill_blocks), dim3(kBlock), 0, s, a.acc, plane, total, a.maxbuf);
+  return hipGetLastError();
+}
+
+}  // namespace evis

@@ -92,6 +92,10 @@ SIGNATURES = {
     "evis_log_luminance": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
                                           _VP, _VP]),
     "evis_log_channels": (ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_float, _VP, _VP]),
+    "evis_voxel_grid": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                       _VP, _VP]),
+    "evis_defocus_batch": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _VP]),
     "evis_defocus": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_float, _VP, _VP]),
     "evis_state_init": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32,
@@ -260,6 +264,33 @@ def evis_log_channels(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=None
         out = torch.empty((3,) + tuple(x.shape[:-1]), dtype=torch.float32, device=x.device)
     ctx.check(ctx.lib.evis_log_channels(ctx.handle, _ptr(x), n, eps, _ptr(out), _stream(stream)))
     return out
+
+
+def evis_voxel_grid(ctx: Context, out_events: torch.Tensor, n_total: torch.Tensor, env_id: int,
+                    H: int, W: int, t0_us: int, t1_us: int, bins: int = 128, out=None, stream=None):
+    """Normalised per-polarity voxel grid [2, bins, H, W] of one env's events."""
+    if out is None:
+        out = torch.empty((2, bins, H, W), dtype=torch.float32, device=out_events.device)
+    ctx.check(ctx.lib.evis_voxel_grid(ctx.handle, _ptr(out_events), _ptr(n_total), out_events.shape[0],
+                                      env_id, H, W, t0_us, t1_us, bins, _ptr(out), _stream(stream)))
+    return out
+
+
+class EvisImage(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("out", ctypes.c_void_p), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32)]
+
+
+def evis_defocus_batch(ctx: Context, pairs, sigma: float, stream=None):
+    """pairs: sequence of (x, out) device tensors, each [H, W] or [H, W, 3]
+    (all with the same channel count)."""
+    arr = (EvisImage * len(pairs))()
+    channels = 1
+    for i, (x, out) in enumerate(pairs):
+        channels = 3 if (x.dim() == 3 and x.shape[-1] == 3) else 1
+        arr[i] = EvisImage(_ptr(x).value, _ptr(out).value, x.shape[0], x.shape[1])
+    ctx.check(ctx.lib.evis_defocus_batch(ctx.handle, arr, len(pairs), channels, float(sigma),
+                                         _stream(stream)))
 
 
 def evis_defocus(ctx: Context, x: torch.Tensor, sigma: float, out=None, stream=None):

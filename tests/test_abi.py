@@ -55,7 +55,8 @@ def test_struct_layouts_match_a_c_compiler(tmp_path):
         pytest.skip("no gcc")
     mirrors = {"evis_pair": evis.EvisPair, "evis_sensor": evis.EvisSensor,
                "evis_state": evis.EvisState, "evis_env": evis.EvisEnv, "evis_noise": evis.EvisNoise,
-               "evis_tuning": evis.EvisTuning, "evis_soft_env": evis.EvisSoftEnv}
+               "evis_tuning": evis.EvisTuning, "evis_soft_env": evis.EvisSoftEnv,
+               "evis_image": evis.EvisImage}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "evis.h"', "int main(void) {"]
     for cname, cls in mirrors.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -60,6 +60,32 @@ def test_defocus_full_frame(torch, ctx):
     check(torch, ctx, sc["I_A"], 0.5)
 
 
+def test_defocus_batch(torch, ctx):
+    """70 images of uneven size in batched launches (64, then 6), grey
+    and RGB, against the oracle one by one."""
+    from paper_2607_08098_amd import evis
+    rng = np.random.default_rng(5)
+    for ch in (1, 3):
+        xs, outs, pairs = [], [], []
+        for i in range(70):
+            H, W = int(rng.integers(1, 90)), int(rng.integers(1, 130))
+            shape = (H, W) if ch == 1 else (H, W, 3)
+            x = (10.0 ** rng.uniform(-2, 2, size=shape)).astype(F32)
+            xd = torch.from_numpy(x).cuda()
+            od = torch.empty_like(xd)
+            xs.append(x)
+            pairs.append((xd, od))
+        say("defocus batch of 70, channels", ch)
+        evis.evis_defocus_batch(ctx, pairs, 1.3)
+        torch.cuda.synchronize()
+        r = o.defocus_radius(1.3)
+        for x, (_, od) in zip(xs, pairs):
+            got = od.cpu().numpy().astype(np.float64)
+            want = o.defocus(x.astype(np.float64), 1.3)
+            tol = (4 * (2 * r + 1) + 4) * 2.0 ** -24 * float(np.abs(x).max())
+            assert float(np.abs(got - want).max()) <= tol, x.shape
+
+
 def test_defocus_argument_errors(torch, ctx):
     from paper_2607_08098_amd import evis
     x = torch.ones(8, 9, device="cuda")

@@ -403,6 +403,8 @@ int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileA
   Sched sc = sched_ptrs(ctx, n);
   EVIS_HIP(launch_reset(d_dyn, n, sc.queue, reset_cursor, s), "k_reset");
   EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n, pl.src_total, s), "k_prep");
+  if (!pl.desc.empty() && pl.desc[0].warp != EVIS_WARP_GATHER)   // one warp per plan
+    EVIS_HIP(launch_prep_b(d_desc, d_prefix, n, pl.src_total, s), "k_prep_b");
   EVIS_HIP(launch_queue(d_desc, d_dyn, n, tw, th, sc.xbegin, sc.env_order, sc.n_items, K_used, s),
            "k_queue");
   ta.envs = d_desc;

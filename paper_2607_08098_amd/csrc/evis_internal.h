@@ -84,6 +84,8 @@ hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
                         unsigned long long* cursor, hipStream_t s);   // queue: kXcd counters
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
                        int total_src_tiles, hipStream_t s);
+hipError_t launch_prep_b(const EnvDesc* envs, const int32_t* src_prefix, int n_envs,
+                         int total_src_tiles, hipStream_t s);   // two-splat warps' B records
 hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,
                         int32_t* xbegin, int32_t* env_order, int32_t* n_items,
                         int32_t* K_used, hipStream_t s);

@@ -41,10 +41,7 @@ __global__ void k_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
 // (m_A.x, m_A.y, Z_A, Zend - Z_A), block-major, so that the splat reads one
 // 16-byte value per source and a block's 16 records are contiguous; the
 // block's bounds of m_A over sources with a finite motion vector; and the
-// env's largest finite |m|^2.  For the two-splat warps also B's record
-// (-m_B.x, -m_B.y, Zstart, Z_B - Zstart), Zstart = Z_A at p + m_B(p)
-// (edge-clamped; Eq. 7 with p_A = p + m_B(p), p_B = p), and the block's
-// bounds of -m_B.
+// env's largest finite |m|^2.
 __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ envs, EnvDyn* dyn,
                                                  const int32_t* __restrict__ src_prefix,
                                                  int n_envs, int total) {
@@ -104,29 +101,6 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const EnvDesc& d = envs[e[u]];
-      if (d.warp != EVIS_WARP_GATHER) {   // wave-uniform
-        const float zb = ldg(d.ZB, p[u]);
-        const float sx = clamp_into((float)x[u] + mb[u].x, (float)(d.W - 1));
-        const float sy = clamp_into((float)y[u] + mb[u].y, (float)(d.H - 1));
-        const float zs = bilinear(d.ZA, d.H, d.W, sx, sy);
-        float mnx = inf, mxx = -inf, mny = inf, mxy = -inf;
-        if (in[u] && finite32(mb[u].x) && finite32(mb[u].y)) {
-          mnx = mxx = -mb[u].x;
-          mny = mxy = -mb[u].y;
-        }
-        if (has[u])
-          stg(d.srcB, blk[u] * kBlkPx + r,
-              in[u] ? make_float4(-mb[u].x, -mb[u].y, zs, zb - zs) : make_float4(0.f, 0.f, 0.f, 0.f));
-        mnx = row16_min(mnx);
-        mxx = row16_max(mxx);
-        mny = row16_min(mny);
-        mxy = row16_max(mxy);
-        if (r == 0 && has[u]) stg(d.tbB, blk[u], make_float4(mnx, mxx, mny, mxy));
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const EnvDesc& d = envs[e[u]];
       float mnx = inf, mxx = -inf, mny = inf, mxy = -inf;
       double msq = 0.0;
       if (in[u]) {
@@ -158,6 +132,56 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
     }
   }
   publish();
+}
+
+// Two-splat warps only: per 4x4 source block (a row of 16 lanes, four
+// blocks per wave), B's splat record (-m_B.x, -m_B.y, Zstart, Z_B -
+// Zstart), Zstart = Z_A at p + m_B(p) (edge-clamped; Eq. 7 with
+// p_A = p + m_B(p), p_B = p), and the block's bounds of -m_B over sources
+// with a finite motion vector.
+__global__ __launch_bounds__(kBlock) void k_prep_b(const EnvDesc* __restrict__ envs,
+                                                   const int32_t* __restrict__ src_prefix,
+                                                   int n_envs, int total) {
+  __shared__ int s_prefix[EVIS_MAX_ENVS + 1];
+  for (int i = threadIdx.x; i <= n_envs; i += kBlock) s_prefix[i] = src_prefix[i];
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int g = lane >> 4, r = lane & (kBlkPx - 1);
+  const int nwaves = (int)gridDim.x * kWavesPerBlock;
+  const float inf = __int_as_float(0x7f800000);
+  for (int gt = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave); gt < total; gt += nwaves) {
+    int lo = 0, hi = n_envs - 1;   // env of block group gt (wave-uniform)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_prefix[mid] <= gt) lo = mid; else hi = mid - 1;
+    }
+    const EnvDesc& d = envs[lo];
+    if (d.warp == EVIS_WARP_GATHER) continue;
+    const int blk = (gt - s_prefix[lo]) * 4 + g;
+    const bool has = blk < d.ntx_src * d.nty_src;
+    const int bx = has ? blk % d.ntx_src : 0, by = has ? blk / d.ntx_src : 0;
+    const int x = bx * kSrcBlk + (r & 3), y = by * kSrcBlk + (r >> 2);
+    const bool in = has && x < d.W && y < d.H;
+    const int p = in ? y * d.W + x : 0;
+    const float2 mb = ldg(d.mB, p);
+    const float zb = ldg(d.ZB, p);
+    const float sx = clamp_into((float)x + mb.x, (float)(d.W - 1));
+    const float sy = clamp_into((float)y + mb.y, (float)(d.H - 1));
+    const float zs = bilinear(d.ZA, d.H, d.W, sx, sy);
+    float mnx = inf, mxx = -inf, mny = inf, mxy = -inf;
+    if (in && finite32(mb.x) && finite32(mb.y)) {
+      mnx = mxx = -mb.x;
+      mny = mxy = -mb.y;
+    }
+    if (has)
+      stg(d.srcB, blk * kBlkPx + r,
+          in ? make_float4(-mb.x, -mb.y, zs, zb - zs) : make_float4(0.f, 0.f, 0.f, 0.f));
+    mnx = row16_min(mnx);
+    mxx = row16_max(mxx);
+    mny = row16_min(mny);
+    mxy = row16_max(mxy);
+    if (r == 0 && has) stg(d.tbB, blk, make_float4(mnx, mxx, mny, mxy));
+  }
 }
 
 // Single workgroup: each env's K (fixed or the exact adaptive count), its
@@ -240,6 +264,15 @@ hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_pref
   // a run of block groups per wave: 256 CUs x 8 workgroups at most
   const int blocks = std::min((total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
   hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kBlock), 0, s, envs, dyn, src_prefix, n_envs,
+                     total_src_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_b(const EnvDesc* envs, const int32_t* src_prefix, int n_envs,
+                         int total_src_tiles, hipStream_t s) {
+  if (total_src_tiles <= 0) return hipSuccess;
+  const int blocks = std::min((total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
+  hipLaunchKernelGGL(k_prep_b, dim3(blocks), dim3(kBlock), 0, s, envs, src_prefix, n_envs,
                      total_src_tiles);
   return hipGetLastError();
 }

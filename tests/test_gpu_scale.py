@@ -10,6 +10,8 @@ benchmark times (autotuned tile, one persistent graph-replayed launch):
   on the device: sampled envs at sampled steps against the oracle started
   from the device state of that step; stream size and capacity checks on
   every step;
+* the benchmark's variants on the same batch (two-splat warps, sensor
+  noise): sampled envs against the oracle;
 * a textured-plane scene at 640x480 seen by a random-walk camera (exact
   flow and depth, true occlusion), per-pixel threshold mismatch and a 100 us
   refractory period, three keyframe pairs chained through the state: every
@@ -84,6 +86,50 @@ def test_mixed64_full_size_sampled_parity(torch, ctx):
         say("mixed64 oracle env", e, s["L_A"].shape, "K", int(Ks[e]))
         pair = o.Pair(s["L_A"], s["L_B"], s["m_A"], s["m_B"], s["Z_A"], s["Z_B"], 0, 16667)
         want, R, _, K = o.step(pair, o.Sensor(C_on=0.2, C_off=0.2, K=0, K_max=64), s["L_ref"], None, e)
+        assert K == Ks[e]
+        got = env_events(ev, e)
+        assert U.same_multiset(got, want), (e, len(got), len(want), U.multiset_diff(got, want))
+        assert np.array_equal(host(envs[e]["L_ref"]).view(np.uint32), R.view(np.uint32))
+
+
+@pytest.mark.parametrize("variant", ["splat_b_primary", "joint", "gather_with_noise"])
+def test_mixed64_variants_sampled_parity(torch, ctx, variant):
+    """The benchmark's variants at full size in its launch configuration
+    (same batch, the tile shape it autotunes for the gather warp): every
+    event and reference level of sampled envs against the oracle."""
+    from paper_2607_08098_amd import evis, scenes, workloads
+    say("mixed64 variant", variant, ": build workload")
+    batch = workloads.mixed_batch(ctx, specs=scenes.mixed_batch_specs(3000))
+    mode = {"splat_b_primary": o.WARP_SPLAT | o.BLEND_B_PRIMARY, "joint": o.WARP_JOINT,
+            "gather_with_noise": o.WARP_GATHER}[variant]
+    sensor = dict(C_on=0.2, C_off=0.2, K=0, K_max=64, refractory_us=0, blend_mode=mode)
+    envs = batch.env_dicts(sensor)
+    noise = None
+    if variant == "gather_with_noise":
+        noise = dict(leak_rate_hz=0.1, shot_rate_hz=1.0, hot_rate_hz=100.0, hot_fraction=1e-3,
+                     shot_L0=-7.0, shot_inv_range=0.1)
+        for e, d in enumerate(envs):
+            d["noise"] = dict(noise, seed=9000 + e)
+    arr = evis.env_array(envs)
+    out, n = evis.event_buffer(1 << 28)
+    evis.evis_set_tuning(ctx, tile_w=32, tile_h=16)
+    samples = [0, 24] if variant == "splat_b_primary" else [0]
+    snap = {e: {k: host(v) for k, v in envs[e].items() if hasattr(v, "cpu")} for e in samples}
+    K_used = torch.zeros(len(envs), dtype=torch.int32, device="cuda")
+    say("mixed64 variant", variant, ": step")
+    n.zero_()
+    evis.evis_step_batch(ctx, arr, out, n, K_used, 0)
+    torch.cuda.synchronize()
+    assert 0 < int(n.item()) <= out.shape[0]
+    ev = evis.decode_events(out, n)
+    Ks = host(K_used)
+    for e in samples:
+        s = snap[e]
+        say("mixed64 variant", variant, "oracle env", e, s["L_A"].shape, "K", int(Ks[e]))
+        pair = o.Pair(s["L_A"], s["L_B"], s["m_A"], s["m_B"], s["Z_A"], s["Z_B"], 0, 16667)
+        nz = o.Noise(seed=9000 + e, **noise) if noise else None
+        sen = o.Sensor(C_on=0.2, C_off=0.2, K=0, K_max=64, blend_mode=mode, noise=nz)
+        want, R, _, K = o.step(pair, sen, s["L_ref"], None, e)
         assert K == Ks[e]
         got = env_events(ev, e)
         assert U.same_multiset(got, want), (e, len(got), len(want), U.multiset_diff(got, want))

@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
+    ap.add_argument("--variants", action="store_true",
+                    help="timed loop and the variants only (for profilers)")
     ap.add_argument("--warp-steps", type=int, default=10,
                     help="timed steps of each variant: two-splat warps, noise (0 skips them)")
     ap.add_argument("--disc-steps", type=int, default=200,
@@ -302,42 +304,44 @@ def main():
     value = mpix_substeps / (ms_step / 1e3)
     events_per_s = events_total / (ms_total / 1e3)
     log(f"batched: {ms_step:.3f} ms/step, {value:.0f} Mpix-substeps/s, {events_per_s:.3e} events/s")
-    if args.quick:
+    if args.quick and not args.variants:
         print(json.dumps(dict(ms_per_step=ms_step, value=value)))
         return
 
-    # the fused tile kernel alone, timed with HIP events on its own stream
-    evis.evis_profile_enable(ctx, True)
-    n_total.zero_()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    tile_ms, launches = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
-    evis.evis_profile_enable(ctx, False)
-    tile_ms_avg = tile_ms / max(launches, 1)
-    ev_per_launch = int(n_total.item()) / max(launches, 1)
-    ops = float((px * (OPS_INTERIOR * (Ks - 1) + OPS_LAST)).sum())
-    bytes_ = float(px.sum() * BYTES_PER_PX + BYTES_PER_EVENT * ev_per_launch)
-    t_alu = ops / (ALU_PEAK_TOPS * 1e12)
-    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("tuning") == [tuning["tile_w"], tuning["tile_h"]]:
-            traffic = tr.get("bytes_per_launch")
-    if t_alu >= t_hbm:
-        achieved = ops / (tile_ms_avg / 1e3) / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2),
-                    unit="Tops/s", frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=traffic)
-    else:
-        achieved = bytes_ / (tile_ms_avg / 1e3) / 1e9
-        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
-    roof["kernel"] = "k_tile(step)"
-    roof["kernel_ms"] = round(tile_ms_avg, 4)
-    roof["hbm_algorithmic_GBps"] = round(bytes_ / (tile_ms_avg / 1e3) / 1e9, 1)
-    log(f"tile kernel {tile_ms_avg:.3f} ms; roofline {roof}")
+    roof = None
+    if not args.variants:
+        # the fused tile kernel alone, timed with HIP events on its own stream
+        evis.evis_profile_enable(ctx, True)
+        n_total.zero_()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        tile_ms, launches = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
+        evis.evis_profile_enable(ctx, False)
+        tile_ms_avg = tile_ms / max(launches, 1)
+        ev_per_launch = int(n_total.item()) / max(launches, 1)
+        ops = float((px * (OPS_INTERIOR * (Ks - 1) + OPS_LAST)).sum())
+        bytes_ = float(px.sum() * BYTES_PER_PX + BYTES_PER_EVENT * ev_per_launch)
+        t_alu = ops / (ALU_PEAK_TOPS * 1e12)
+        t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            with open(TRAFFIC_FILE) as fh:
+                tr = json.load(fh)
+            if tr.get("kernel_hash") == kernel_hash() and tr.get("tuning") == [tuning["tile_w"], tuning["tile_h"]]:
+                traffic = tr.get("bytes_per_launch")
+        if t_alu >= t_hbm:
+            achieved = ops / (tile_ms_avg / 1e3) / 1e12
+            roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(ALU_PEAK_TOPS, 2),
+                        unit="Tops/s", frac=round(achieved / ALU_PEAK_TOPS, 4), traffic=traffic)
+        else:
+            achieved = bytes_ / (tile_ms_avg / 1e3) / 1e9
+            roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
+        roof["kernel"] = "k_tile(step)"
+        roof["kernel_ms"] = round(tile_ms_avg, 4)
+        roof["hbm_algorithmic_GBps"] = round(bytes_ / (tile_ms_avg / 1e3) / 1e9, 1)
+        log(f"tile kernel {tile_ms_avg:.3f} ms; roofline {roof}")
 
     # the two-splat warps, and the gather warp with sensor noise, on the same
     # batch and tile shape
@@ -450,6 +454,10 @@ def main():
                                                      frac=round(vgbs / HBM_PEAK_GBS, 4)))
         log(f"voxel grid: {vms:.3f} ms ({nev} events scanned), {vgbs:.0f} GB/s")
         del grid
+
+    if args.variants:
+        print(json.dumps(dict(ms_per_step=ms_step, value=value, variants=warps)))
+        return
 
     # per-env-launch plain form: every sub-frame to HBM, then the event model
     plain = None

@@ -62,15 +62,17 @@ __global__ __launch_bounds__(kBlock) void k_voxel_max(const uint32_t* __restrict
 }
 
 // Each voxel divided by its plane's maximum, in place (uint32 sums in,
-// float32 out).
+// float32 out); workgroup (chunk, plane) as for the maxima.
 __global__ __launch_bounds__(kBlock) void k_voxel_div(uint32_t* __restrict__ acc, long long plane,
-                                                      long long total, const uint32_t* maxbuf) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  float* out = reinterpret_cast<float*>(acc);
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-    const uint32_t mx = maxbuf[i / plane];
-    const uint32_t v = acc[i];
-    out[i] = mx ? (float)v / (float)mx : 0.0f;
+                                                      long long chunk, const uint32_t* maxbuf) {
+  uint32_t* pl = acc + (long long)blockIdx.y * plane;
+  float* out = reinterpret_cast<float*>(pl);
+  const uint32_t mx = maxbuf[blockIdx.y];
+  const float fm = (float)mx;
+  const long long i0 = (long long)blockIdx.x * chunk, i1 = min(plane, i0 + chunk);
+  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
+    const uint32_t v = pl[i];
+    out[i] = mx ? (float)v / fm : 0.0f;
   }
 }
 
@@ -95,7 +97,8 @@ hipError_t launch_voxel(const VoxelArgs& a, hipStream_t s) {
                      a.maxbuf);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_voxel_div, dim3(fill_blocks), dim3(kBlock), 0, s, a.acc, plane, total, a.maxbuf);
+  hipLaunchKernelGGL(k_voxel_div, dim3(nchunks, 2 * a.bins), dim3(kBlock), 0, s, a.acc, plane, chunk,
+                     a.maxbuf);
   return hipGetLastError();
 }
 

@@ -26,10 +26,10 @@ namespace evis {
 // the B gather by B's backward splat: both directions' candidates share
 // one list, both are splatted, and the winners give A^ and B^.  JOINT
 // splats pairs into one z-buffer set as above (the winner's tag tells A
-// from B); SPLAT needs a z-buffer per direction and so splats one substep
-// per pass into double buffers (A: j & 1, B: 2 + (j & 1)), which also
-// takes one barrier per substep: the splat of j + 2 comes after the
-// barrier that follows the splat of j + 1, by which time j is read.
+// from B); SPLAT needs a z-buffer per direction, so it splats each pair
+// into two buffers per direction (A: j & 1, B: 2 + (j & 1)) and takes a
+// second barrier after the pair's second resolve, before the next pair's
+// splat reuses them (two barriers per pair, as many as substeps).
 //
 // NOISE = 1 (fused step only) adds the sensor-noise events of every env that
 // has noise after each substep's crossings.
@@ -274,21 +274,22 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       float cAh[PPT], cBh[PPT];
       uint32_t chb[PPT];
       unsigned long long* zb = zbuf + (kOwnB ? (j & 1) : (j & 3)) * ZN;
-      const bool pair_start = kOwnB || ((j - j_first) & 1) == 0;   // uniform
+      const bool pair_start = ((j - j_first) & 1) == 0;   // uniform
       if constexpr (!kGather) {
         // two-splat warps: (2) splat A forward and B backward for j and j + 1
         unsigned long long* const zbB = kOwnB ? zbuf + (2 + (j & 1)) * ZN : zb;
-        if constexpr (kOwnB) {
-          const float fs[1] = {f};
-          unsigned long long* const zs[1] = {zb};
-          unsigned long long* const zsB[1] = {zbB};
-          splat_candidates<TW, 1, DIR_A>(d, list, nlist, overflow, win, K, j, 1, fs, Tx0, Tx1,
+        if (kOwnB && pair_start) {
+          const int nf = (j + 1 <= j_int_last) ? 2 : 1;
+          const float fs[2] = {f, (float)(j + 1) / (float)K};
+          unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 1) * ZN};
+          unsigned long long* const zsB[2] = {zbB, zbuf + (2 + ((j + 1) & 1)) * ZN};
+          splat_candidates<TW, 2, DIR_A>(d, list, nlist, overflow, win, K, j, nf, fs, Tx0, Tx1,
                                          Ty0, Ty1, s_wl[wave], zs);
-          splat_candidates<TW, 1, DIR_B>(d, list, nlistB, overflow, win, K, j, 1, fs, Tx0, Tx1,
+          splat_candidates<TW, 2, DIR_B>(d, list, nlistB, overflow, win, K, j, nf, fs, Tx0, Tx1,
                                          Ty0, Ty1, s_wl[wave], zsB, lcap - 1, -1);
           __syncthreads();
           if (MODE == MODE_STEP) sink_check(sh, so, sr);
-        } else if (pair_start) {
+        } else if (!kOwnB && pair_start) {
           const int nf = (j + 1 <= j_int_last) ? 2 : 1;
           const float fs[2] = {f, (float)(j + 1) / (float)K};
           unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 3) * ZN};
@@ -327,6 +328,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
             }
           }
           chb[k] = (vA ? 0u : 1u) | (vB ? 0u : 2u);
+        }
+        if (kOwnB && !pair_start) {   // both buffer pairs read and cleared
+          __syncthreads();
+          if (MODE == MODE_STEP) sink_check(sh, so, sr);
         }
       } else if (!is_static) {
         // (1) B-gather loads of substep j

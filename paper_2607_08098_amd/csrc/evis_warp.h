@@ -125,8 +125,10 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
     sx[c] = bx * kSrcBlk + (r & 3);
     sy[c] = by * kSrcBlk + (r >> 2);
     const bool ok = e != 0u && sx[c] < d.W && sy[c] < d.H;
-    src[c] = ok ? sy[c] * d.W + sx[c] : -1;
-    rec[c] = ldg(recs, ok ? (by * d.ntx_src + bx) * kBlkPx + r : 0);
+    // 24-bit products (full-rate v_mul_u32_u24): rows, columns and block
+    // counts are below 2^12
+    src[c] = ok ? (int)__umul24((unsigned)sy[c], (unsigned)d.W) + sx[c] : -1;
+    rec[c] = ldg(recs, ok ? ((int)__umul24((unsigned)by, (unsigned)d.ntx_src) + bx) * kBlkPx + r : 0);
   }
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
@@ -186,10 +188,12 @@ __device__ __forceinline__ BTaps b_taps(const EnvDesc& d, int x, int y, float2 m
   const int x1 = min(x0 + 1, d.W - 1), y1 = min(y0 + 1, d.H - 1);
   t.a = t.b = t.c = t.d = 0.0f;
   if (t.v) {
-    t.a = ldg(d.LB, y0 * d.W + x0);
-    t.b = ldg(d.LB, y0 * d.W + x1);
-    t.c = ldg(d.LB, y1 * d.W + x0);
-    t.d = ldg(d.LB, y1 * d.W + x1);
+    const int r0 = (int)__umul24((unsigned)y0, (unsigned)d.W);   // y, W < 2^12: 24-bit products
+    const int r1 = (int)__umul24((unsigned)y1, (unsigned)d.W);
+    t.a = ldg(d.LB, r0 + x0);
+    t.b = ldg(d.LB, r0 + x1);
+    t.c = ldg(d.LB, r1 + x0);
+    t.d = ldg(d.LB, r1 + x1);
   }
   return t;
 }

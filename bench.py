@@ -18,7 +18,9 @@ live with HIP events; the same kernel with B splatted backward (the
 two-splat warps: own z-buffer with B primary, and one joint z-buffer) and
 with sensor noise (leak 0.1 Hz, shot 1 Hz, 0.1% hot pixels at 100 Hz);
 the defocus blur of every env's keyframe (sigma 0.5 px); the 128-bin
-voxel grid of one 1280x720 env from one step's event stream;
+voxel grid of one 1280x720 env from one step's event stream; the
+HBM-bound forms (the event model over one env's materialised frames, the
+fused step at K = 2);
 the CPU oracle on a bounded sample of the same workload (rank 0, N = 1
 only).
 """
@@ -454,6 +456,60 @@ def main():
                                                      frac=round(vgbs / HBM_PEAK_GBS, 4)))
         log(f"voxel grid: {vms:.3f} ms ({nev} events scanned), {vgbs:.0f} GB/s")
         del grid
+
+    # the HBM-bound forms: the event model over materialised frames (one
+    # 1280x720 env, its K + 1 sub-frames written by evis_interpolate first),
+    # and the fused step with K = 2 (one warped substep)
+    if args.warp_steps > 0:
+        ve = n_envs - 1
+        vh, vw = batch.shapes[ve]
+        Kv = int(Ks[ve])
+        frames = torch.empty((Kv + 1, vh, vw), dtype=torch.float32, device="cuda")
+        dv = envs[ve]
+        pair_v = dict(L_A=dv["L_A"], L_B=dv["L_B"], m_A=dv["m_A"], m_B=dv["m_B"], Z_A=dv["Z_A"],
+                      Z_B=dv["Z_B"], t0=0, t1=16667)
+        evis.evis_interpolate(ctx, pair_v, Kv, 0, Kv + 1, evis.EVIS_BLEND_TIME, L_out=frames,
+                              want_holes=False)
+        lref = dv["L_ref"].clone()
+        st_v = dict(L_ref=lref)
+        evis.evis_profile_enable(ctx, True)
+        n_total.zero_()
+        for _ in range(args.warp_steps):
+            lref.copy_(dv["L_A"])
+            evis.evis_generate_events(ctx, frames, 0, 16667, sensor, st_v, ve, out, n_total, flags=0)
+        torch.cuda.synchronize()
+        gms, gl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_EVENTS)
+        evis.evis_profile_enable(ctx, False)
+        gms /= max(gl, 1)
+        gev = int(n_total.item()) / max(gl, 1)
+        gbytes = 4.0 * (Kv + 1) * vh * vw + 8.0 * vh * vw + 8.0 * gev
+        ggbs = gbytes / (gms / 1e3) / 1e9
+        warps["generate_events_1280x720"] = dict(
+            kernel_ms=round(gms, 4), K=Kv, events=round(gev),
+            roofline=dict(bound="hbm", achieved=round(ggbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(ggbs / HBM_PEAK_GBS, 4)))
+        log(f"generate_events: {gms:.3f} ms, {ggbs:.0f} GB/s")
+        del frames
+        k2 = evis.env_array(batch.env_dicts(dict(sensor, K=2)))
+        for _ in range(2):
+            n_total.zero_()
+            evis.evis_step_batch(ctx, k2, out, n_total, K_used, 0)
+        torch.cuda.synchronize()
+        evis.evis_profile_enable(ctx, True)
+        n_total.zero_()
+        for _ in range(args.warp_steps):
+            evis.evis_step_batch(ctx, k2, out, n_total, K_used, 0)
+        torch.cuda.synchronize()
+        kms, kl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
+        evis.evis_profile_enable(ctx, False)
+        kms /= max(kl, 1)
+        kev = int(n_total.item()) / max(kl, 1)
+        kbytes = float(px.sum()) * BYTES_PER_PX + BYTES_PER_EVENT * kev
+        kgbs = kbytes / (kms / 1e3) / 1e9
+        warps["fused_K2"] = dict(kernel_ms=round(kms, 4), events=round(kev),
+                                 roofline=dict(bound="hbm", achieved=round(kgbs, 1), peak=HBM_PEAK_GBS,
+                                               unit="GB/s", frac=round(kgbs / HBM_PEAK_GBS, 4)))
+        log(f"fused K=2: {kms:.3f} ms, {kgbs:.0f} GB/s")
 
     if args.variants:
         print(json.dumps(dict(ms_per_step=ms_step, value=value, variants=warps)))

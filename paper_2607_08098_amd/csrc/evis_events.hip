@@ -104,7 +104,11 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   const int tid = threadIdx.x;
   const long long plane = (long long)a.H * a.W;
   const long long base = (long long)blockIdx.x * (kBlock * PPT);
-  float R[PPT], Lp[PPT], Lj[PPT], Ln[PPT];
+  // Frames are read kAhead substeps ahead of their use (a ring of registers
+  // shifted by one each substep), so that enough loads are in flight to keep
+  // HBM busy: the substep loop is otherwise one dependent load per step.
+  constexpr int kAhead = 4;
+  float R[PPT], Lp[PPT], Lj[PPT], Ln[kAhead][PPT];
   uint32_t okbits = 0;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
@@ -117,7 +121,9 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
     if (a.th_on) s_con[i] = ok ? a.th_on[q] : 1.0f;
     if (a.th_off) s_coff[i] = ok ? a.th_off[q] : 1.0f;
     Lp[k] = ok ? a.L_seq[q] : 0.0f;
-    Ln[k] = ok ? a.L_seq[plane + q] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < kAhead; ++u)
+      Ln[u][k] = (ok && u + 1 <= a.K) ? a.L_seq[(long long)(u + 1) * plane + q] : 0.0f;
   }
   const PixAux aux{a.th_on ? s_con : nullptr, a.th_off ? s_coff : nullptr, s_tl, a.C_on, a.C_off,
                    0, 0, a.W, 0, base};
@@ -127,10 +133,12 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   for (int j = 1; j <= a.K; ++j) {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      Lj[k] = Ln[k];
-      if (j < a.K)
-        Ln[k] = ((okbits >> k) & 1u) ? a.L_seq[(long long)(j + 1) * plane + base + tid + k * kBlock]
-                                     : 0.0f;
+      Lj[k] = Ln[0][k];
+#pragma unroll
+      for (int u = 0; u + 1 < kAhead; ++u) Ln[u][k] = Ln[u + 1][k];
+      Ln[kAhead - 1][k] = (((okbits >> k) & 1u) && j + kAhead <= a.K)
+                              ? a.L_seq[(long long)(j + kAhead) * plane + base + tid + k * kBlock]
+                              : 0.0f;
     }
     emit_substep<PPT>(j, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.refr, a.env_bits, sh, so,
                       sr);

@@ -12,7 +12,7 @@ namespace evis {
 
 enum Mode { MODE_STEP = 0, MODE_INTERP = 1, MODE_SOFT_FWD = 2, MODE_SOFT_BWD = 3 };
 
-constexpr int kListCapMax = 1024;   // per-tile candidate source tiles held in LDS
+constexpr int kListCapMax = 1024;   // per-tile candidate source blocks held in LDS
 constexpr int kEventBuf = 1024;     // events staged in LDS per workgroup
 constexpr int kXcd = 8;             // work queues: one per accelerator complex die
 constexpr int kQueueStride = 64;    // queue counters 256 bytes apart (own cache lines)
@@ -83,9 +83,9 @@ hipError_t launch_soft_zero(const SoftPtrs* ptrs, const EnvDesc* envs, int n_env
 hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
                         unsigned long long* cursor, hipStream_t s);   // queue: kXcd counters
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
-                       int total_src_tiles, hipStream_t s);
+                       int total_groups, hipStream_t s);
 hipError_t launch_prep_b(const EnvDesc* envs, const int32_t* src_prefix, int n_envs,
-                         int total_src_tiles, hipStream_t s);   // two-splat warps' B records
+                         int total_groups, hipStream_t s);   // two-splat warps' B records
 hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,
                         int32_t* xbegin, int32_t* env_order, int32_t* n_items,
                         int32_t* K_used, hipStream_t s);

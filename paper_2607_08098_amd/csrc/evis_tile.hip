@@ -259,21 +259,21 @@ hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue, unsigned l
 }
 
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
-                       int total_src_tiles, hipStream_t s) {
-  if (total_src_tiles <= 0) return hipSuccess;
+                       int total_groups, hipStream_t s) {
+  if (total_groups <= 0) return hipSuccess;
   // a run of block groups per wave: 256 CUs x 8 workgroups at most
-  const int blocks = std::min((total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
+  const int blocks = std::min((total_groups + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
   hipLaunchKernelGGL(k_prep, dim3(blocks), dim3(kBlock), 0, s, envs, dyn, src_prefix, n_envs,
-                     total_src_tiles);
+                     total_groups);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_b(const EnvDesc* envs, const int32_t* src_prefix, int n_envs,
-                         int total_src_tiles, hipStream_t s) {
-  if (total_src_tiles <= 0) return hipSuccess;
-  const int blocks = std::min((total_src_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
+                         int total_groups, hipStream_t s) {
+  if (total_groups <= 0) return hipSuccess;
+  const int blocks = std::min((total_groups + kWavesPerBlock - 1) / kWavesPerBlock, 256 * 8);
   hipLaunchKernelGGL(k_prep_b, dim3(blocks), dim3(kBlock), 0, s, envs, src_prefix, n_envs,
-                     total_src_tiles);
+                     total_groups);
   return hipGetLastError();
 }
 

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       }
     }
 
-    // Candidate source tiles and their substep intervals.
+    // Candidate source blocks and their substep intervals.
     Window win{};
     int nlist = 0, nlistB = 0;
     bool overflow = false;

@@ -1,5 +1,5 @@
 // Warp building blocks shared by the fused tile kernel and the surrogate
-// kernels (gfx950): the candidate source tiles of a target tile, the
+// kernels (gfx950): the candidate 4x4 source blocks of a target tile, the
 // depth-tested splat of those sources into an LDS z-buffer (Eq. 5 q_A,
 // bilinear footprint, Eq. 6, Eq. 7) and the bilinear gather of B at
 // s = q - (1 - f) m_B(q).
@@ -22,11 +22,11 @@ constexpr uint32_t kATag = 0x80000000u;   // tag bit in the low word of a key
 namespace evis {
 
 // ---------------------------------------------------------------------------
-// candidate source tiles
+// candidate source blocks
 // ---------------------------------------------------------------------------
 
-// Conservative interval of substeps during which some source of the 8x8
-// tile [Sx0,Sx1]x[Sy0,Sy1] with motion bounds b can put a footprint corner
+// Conservative interval of substeps during which some source of the 4x4
+// block [Sx0,Sx1]x[Sy0,Sy1] with motion bounds b can put a footprint corner
 // into the target tile [Tx0,Tx1]x[Ty0,Ty1].  A corner lies in [Tx0,Tx1]
 // only if q_x = p_x - f m_x is in [Tx0 - 1, Tx1 + 1); over the tile q_x lies
 // in [Sx0 - f max m_x, Sx1 - f min m_x].

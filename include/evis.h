@@ -265,6 +265,14 @@ int evis_generate_events(evis_ctx *ctx, const float *L_seq, int32_t H, int32_t W
                          int64_t t0_us, int64_t t1_us, const evis_sensor *sensor,
                          const evis_state *state, int32_t env_id, evis_event *out,
                          int64_t capacity, int64_t *n_total, int32_t flags, void *stream);
+/* The same with sensor noise (evis_noise, a HOST pointer; NULL = none),
+ * drawn exactly as in evis_step_batch with this call's Dt and the pixel's
+ * own coordinates. */
+int evis_generate_events_noise(evis_ctx *ctx, const float *L_seq, int32_t H, int32_t W, int32_t K,
+                               int64_t t0_us, int64_t t1_us, const evis_sensor *sensor,
+                               const evis_state *state, int32_t env_id, const evis_noise *noise,
+                               evis_event *out, int64_t capacity, int64_t *n_total,
+                               int32_t flags, void *stream);
 
 /* Fused step -- one keyframe pair for each of n_envs environments
  * (1..EVIS_MAX_ENVS; envs is a HOST array of descriptors) in one

@@ -615,9 +615,13 @@ def emit_events(S_seq, t0_us, t1_us, sensor: Sensor, L_ref, t_last=None, env_id=
     Dt = substep_dt(t0_us, t1_us, K)
     span = t1_us - t0_us
     log = EventLog()
+    nz = sensor.noise
+    hot = hot_pixels(H, W, nz) if nz is not None else None
     for j in range(1, K + 1):
         emit_substep(j, S_seq[j - 1], S_seq[j], R, tl, on, off, sensor.refractory_us,
                      t0_us, Dt, span, env_id, log, track)
+        if nz is not None:
+            noise_events(j, S_seq[j], Dt, t0_us, span, nz, env_id, log, hot)
     return log.array(), R, (tl.astype(np.int32) if track else None)
 
 

@@ -675,6 +675,15 @@ int evis_generate_events(evis_ctx* ctx, const float* L_seq, int32_t H, int32_t W
                          int64_t t0_us, int64_t t1_us, const evis_sensor* sensor,
                          const evis_state* state, int32_t env_id, evis_event* out,
                          int64_t capacity, int64_t* n_total, int32_t flags, void* stream) {
+  return evis_generate_events_noise(ctx, L_seq, H, W, K, t0_us, t1_us, sensor, state, env_id,
+                                    nullptr, out, capacity, n_total, flags, stream);
+}
+
+int evis_generate_events_noise(evis_ctx* ctx, const float* L_seq, int32_t H, int32_t W, int32_t K,
+                               int64_t t0_us, int64_t t1_us, const evis_sensor* sensor,
+                               const evis_state* state, int32_t env_id, const evis_noise* noise,
+                               evis_event* out, int64_t capacity, int64_t* n_total,
+                               int32_t flags, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;
   if (!L_seq || !aligned(L_seq, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: L_seq");
   if (H < 1 || W < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: H, W");
@@ -697,15 +706,30 @@ int evis_generate_events(evis_ctx* ctx, const float* L_seq, int32_t H, int32_t W
     return fail(ctx, EVIS_ERR_INVALID, "evis_generate_events: env_id");
   rc = check_events_out(ctx, out, capacity, n_total, "evis_generate_events");
   if (rc) return rc;
+  rc = check_noise(ctx, noise, "evis_generate_events");
+  if (rc) return rc;
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const int span = (int)(t1_us - t0_us);
   const float Dt = (float)span / (float)K;
+  // the same per-substep probabilities as the fused step's (host float32
+  // arithmetic in the same order)
+  NoiseCfg nc{};
+  const bool noisy = noise && (noise->leak_rate_hz > 0.0f || noise->shot_rate_hz > 0.0f ||
+                               (noise->hot_rate_hz > 0.0f && noise->hot_fraction > 0.0f));
+  if (noisy) {
+    const float dts = Dt * 1e-6f;
+    nc = NoiseCfg{noise->leak_rate_hz * dts, noise->shot_rate_hz * dts, noise->hot_rate_hz * dts,
+                  noise->shot_L0, noise->shot_inv_range, noise->hot_fraction,
+                  (uint32_t)(noise->seed & 0xFFFFFFFFull), (uint32_t)(noise->seed >> 32),
+                  noise->pair_index};
+  }
   ProfScope ps(ctx, EVIS_KERNEL_EVENTS, (hipStream_t)stream);
   EVIS_HIP(launch_events(L_seq, H, W, K, t0_us, span, Dt, sensor->C_on, sensor->C_off,
                          sensor->theta_on, sensor->theta_off, sensor->refractory_us,
                          (uint32_t)env_id << 23, state->L_ref, state->t_last, out, capacity,
                          reinterpret_cast<unsigned long long*>(n_total),
-                         (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0, (hipStream_t)stream),
+                         (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0, noisy ? &nc : nullptr,
+                         (hipStream_t)stream),
            "k_events");
   return EVIS_OK;
 }

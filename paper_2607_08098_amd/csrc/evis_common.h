@@ -61,6 +61,14 @@ struct EnvDesc {
   uint32_t seed_lo, seed_hi, pair_index;
 };
 
+// Noise parameters of one env for one keyframe pair (per substep
+// probabilities need the pair's substep length).
+struct NoiseCfg {
+  float p_leak, shot_scale, p_hot;   // r_l Dt_s, r_s Dt_s, r_h Dt_s
+  float shot_L0, shot_inv, hot_frac;
+  uint32_t k0, k1, pair;
+};
+
 // Per-environment values computed on the device each step.
 struct EnvDyn {
   unsigned long long msq_bits;   // max over finite |m|^2 (float64 bits, >= 0)

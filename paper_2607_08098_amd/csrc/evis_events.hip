@@ -90,9 +90,10 @@ struct EventArgs {
   evis_event* out;
   long long capacity;
   unsigned long long* cursor;
+  NoiseCfg noise;   // used by the NOISE instantiation only
 };
 
-template <int PPT>
+template <int PPT, int NOISE>
 __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   __shared__ uint2 evbuf[kEventBuf];
   __shared__ int s_evn, s_req[4];
@@ -127,6 +128,8 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   }
   const PixAux aux{a.th_on ? s_con : nullptr, a.th_off ? s_coff : nullptr, s_tl, a.C_on, a.C_off,
                    0, 0, a.W, 0, base};
+  uint32_t hotb = 0;
+  if constexpr (NOISE != 0) hotb = hot_bits<PPT>(a.noise, aux, okbits);
   SinkRound sr;
   sink_init(sh);
   __syncthreads();
@@ -142,6 +145,8 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
     }
     emit_substep<PPT>(j, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.refr, a.env_bits, sh, so,
                       sr);
+    if constexpr (NOISE != 0)
+      emit_noise<PPT>(j, Lj, aux, okbits, hotb, a.noise, a.t0, a.span, a.Dt, a.env_bits, sh, so, sr);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) Lp[k] = Lj[k];
   }
@@ -282,18 +287,26 @@ hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, 
                          float Dt, float C_on, float C_off, const float* th_on,
                          const float* th_off, int refr, uint32_t env_bits, float* L_ref,
                          int32_t* t_last, evis_event* out, long long capacity,
-                         unsigned long long* cursor, int reset_cursor, hipStream_t s) {
+                         unsigned long long* cursor, int reset_cursor, const NoiseCfg* noise,
+                         hipStream_t s) {
   if (reset_cursor) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, cursor);
   EventArgs a{L_seq, H, W, K, t0, span, Dt, C_on, C_off, th_on, th_off, refr, env_bits,
-              L_ref, t_last, out, capacity, cursor};
+              L_ref, t_last, out, capacity, cursor, noise ? *noise : NoiseCfg{}};
   const long long n = (long long)H * W;
   // Enough workgroups to cover the chip: 4 px per thread on large frames.
-  if (n >= 4LL * kBlock * 1024) {
-    hipLaunchKernelGGL((k_events<4>), dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, a);
+  if (noise) {
+    if (n >= 4LL * kBlock * 1024)
+      hipLaunchKernelGGL((k_events<4, 1>), dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, a);
+    else if (n >= 2LL * kBlock * 512)
+      hipLaunchKernelGGL((k_events<2, 1>), dim3(grid_for(n, kBlock * 2)), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_events<1, 1>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a);
+  } else if (n >= 4LL * kBlock * 1024) {
+    hipLaunchKernelGGL((k_events<4, 0>), dim3(grid_for(n, kBlock * 4)), dim3(kBlock), 0, s, a);
   } else if (n >= 2LL * kBlock * 512) {
-    hipLaunchKernelGGL((k_events<2>), dim3(grid_for(n, kBlock * 2)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_events<2, 0>), dim3(grid_for(n, kBlock * 2)), dim3(kBlock), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_events<1>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_events<1, 0>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();
 }

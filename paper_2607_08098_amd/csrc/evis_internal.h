@@ -146,7 +146,8 @@ hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, 
                          float Dt, float C_on, float C_off, const float* th_on,
                          const float* th_off, int refr, uint32_t env_bits, float* L_ref,
                          int32_t* t_last, evis_event* out, long long capacity,
-                         unsigned long long* cursor, int reset_cursor, hipStream_t s);
+                         unsigned long long* cursor, int reset_cursor,
+                         const NoiseCfg* noise /* host copy, or null: no noise */, hipStream_t s);
 hipError_t launch_substep_count(const float2* mA, const float2* mB, long long n, int K_max,
                                 unsigned long long* msq_scratch, int32_t* K_out, hipStream_t s);
 

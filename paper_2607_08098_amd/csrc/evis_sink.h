@@ -296,14 +296,6 @@ __device__ __forceinline__ void emit_substep(
   }
 }
 
-// Noise parameters of one env for one keyframe pair (per substep
-// probabilities need the pair's substep length).
-struct NoiseCfg {
-  float p_leak, shot_scale, p_hot;   // r_l Dt_s, r_s Dt_s, r_h Dt_s
-  float shot_L0, shot_inv, hot_frac;
-  uint32_t k0, k1, pair;
-};
-
 __device__ __forceinline__ NoiseCfg noise_cfg(const EnvDesc& d, float Dt) {
   const float dts = Dt * 1e-6f;
   return NoiseCfg{d.leak_hz * dts, d.shot_hz * dts, d.hot_hz * dts, d.shot_L0, d.shot_inv,

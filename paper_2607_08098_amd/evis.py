@@ -107,6 +107,11 @@ SIGNATURES = {
                                             ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(EvisSensor),
                                             ctypes.POINTER(EvisState), ctypes.c_int32, _VP,
                                             ctypes.c_int64, _VP, ctypes.c_int32, _VP]),
+    "evis_generate_events_noise": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.POINTER(EvisSensor), ctypes.POINTER(EvisState),
+                                                  ctypes.c_int32, ctypes.POINTER(EvisNoise), _VP,
+                                                  ctypes.c_int64, _VP, ctypes.c_int32, _VP]),
     "evis_step_batch": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
                                        _VP, _VP, ctypes.c_int32, _VP]),
     "evis_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
@@ -337,14 +342,23 @@ def evis_interpolate(ctx: Context, pair: dict, K: int, j_begin: int, j_end: int,
 
 def evis_generate_events(ctx: Context, L_seq: torch.Tensor, t0: int, t1: int, sensor: dict,
                          state: dict, env_id: int, out: torch.Tensor, n_total: torch.Tensor,
-                         flags: int = EVIS_FLAG_RESET_CURSOR, stream=None):
+                         flags: int = EVIS_FLAG_RESET_CURSOR, stream=None, noise: Optional[dict] = None):
+    """noise: a make_noise dict (evis_generate_events_noise), or None."""
     K = L_seq.shape[0] - 1
     H, W = L_seq.shape[-2:]
     s = make_sensor(sensor)
     st = make_state(state)
-    ctx.check(ctx.lib.evis_generate_events(ctx.handle, _ptr(L_seq), H, W, K, int(t0), int(t1),
-                                           ctypes.byref(s), ctypes.byref(st), env_id, _ptr(out),
-                                           out.shape[0], _ptr(n_total), flags, _stream(stream)))
+    if noise is None:
+        ctx.check(ctx.lib.evis_generate_events(ctx.handle, _ptr(L_seq), H, W, K, int(t0), int(t1),
+                                               ctypes.byref(s), ctypes.byref(st), env_id, _ptr(out),
+                                               out.shape[0], _ptr(n_total), flags, _stream(stream)))
+    else:
+        nz = make_noise(noise)
+        ctx.check(ctx.lib.evis_generate_events_noise(ctx.handle, _ptr(L_seq), H, W, K, int(t0),
+                                                     int(t1), ctypes.byref(s), ctypes.byref(st),
+                                                     env_id, ctypes.byref(nz), _ptr(out),
+                                                     out.shape[0], _ptr(n_total), flags,
+                                                     _stream(stream)))
     return n_total
 
 

@@ -159,3 +159,33 @@ def test_noise_argument_errors(torch, ctx):
         assert ei.value.code == evis.EVIS_ERR_INVALID and "noise" in str(ei.value), bad
     torch.cuda.synchronize()
     assert int(n.item()) == 0
+
+
+@pytest.mark.parametrize("shape,K,scale", [((64, 80), 5, 1.0), ((600, 500), 3, 0.1),
+                                           ((1100, 1000), 2, 0.01)])
+def test_generate_events_noise(torch, ctx, shape, K, scale):
+    """The event model over caller-supplied frames with sensor noise (every
+    pixels-per-thread variant of the kernel), mismatch and refractory."""
+    from paper_2607_08098_amd import evis, scenes
+    H, W = shape
+    pair = U.oracle_pair(U.blob_scene(H, W, 700 + H, flow="rotate", omega=6.0))
+    frames, _ = o.interpolate(pair, K, 0, K + 1)
+    on, off = scenes.mismatch_thresholds(H, W, 0.25, 0.03, 0.01, scenes.rng_for(77))
+    nz = noise(4242 + H, pair_index=7, scale=scale)
+    s = o.Sensor(theta_on=on, theta_off=off, refractory_us=80, K=K, noise=nz)
+    tl = np.full((H, W), o.T_LAST_INIT, np.int32)
+    want, R, wtl = o.emit_events(list(frames), 1000, 17667, s, pair.L_A.copy(), tl.copy(), env_id=9)
+    Ls = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+    sensor = dict(C_on=0.2, C_off=0.2, theta_on=torch.from_numpy(on).cuda(),
+                  theta_off=torch.from_numpy(off).cuda(), refractory_us=80)
+    state = dict(L_ref=torch.from_numpy(pair.L_A.copy()).cuda(), t_last=torch.from_numpy(tl).cuda())
+    out, n = evis.event_buffer(1 << 23)
+    say("generate_events with noise", shape, "K", K)
+    evis.evis_generate_events(ctx, Ls, 1000, 17667, sensor, state, 9, out, n,
+                              noise=dataclasses.asdict(nz))
+    torch.cuda.synchronize()
+    ev = evis.decode_events(out, n)
+    assert int(n.item()) == len(want)
+    assert U.same_multiset(ev, want), U.multiset_diff(ev, want)
+    assert np.array_equal(state["L_ref"].cpu().numpy().view(np.uint32), R.view(np.uint32))
+    assert np.array_equal(state["t_last"].cpu().numpy(), wtl)

@@ -161,14 +161,14 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   sink_flush(sh, so);
 }
 
-// Defocus: one workgroup per 64 x 16 output tile of one channel of one
+// Defocus: one workgroup per 64 x 32 output tile of one channel of one
 // image of the batch (many small images fill the chip in one launch).  The
 // input tile with an apron of r pixels (edge pixels repeated) goes to LDS,
 // then the horizontal pass over all its rows into LDS, then the vertical
 // pass to the output; each output sums its 2r + 1 taps in order, k = -r..r,
 // with the weights read from LDS.  HBM-bound: one read and one write of
 // each image (plus the aprons).
-constexpr int kDefTW = 64, kDefTH = 16;
+constexpr int kDefTW = 64, kDefTH = 32;
 
 int defocus_tiles(int H, int W, int* tiles_x) {
   *tiles_x = (W + kDefTW - 1) / kDefTW;

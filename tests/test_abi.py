@@ -86,3 +86,22 @@ def test_null_context_is_rejected_without_touching_a_gpu():
     assert lib.evis_generate_events(None, None, 1, 1, 1, 0, 1, None, None, 0, None, 0, None, 0,
                                     None) == evis.EVIS_ERR_INVALID
     assert lib.evis_last_error(None) == b"no context"
+
+
+def test_binding_constants_match_the_header():
+    """Every EVIS_* constant the binding defines equals the header's."""
+    from paper_2607_08098_amd import evis
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {}
+    for name, val in re.findall(r"#define\s+(EVIS_\w+)\s+\(?(-?\w+)\)?", text):
+        vals[name] = val
+    for name, val in re.findall(r"(EVIS_\w+)\s*=\s*(-?\w+)", text):
+        vals[name] = val
+    checked = 0
+    for name in dir(evis):
+        if name.startswith("EVIS_") and name in vals and isinstance(getattr(evis, name), int):
+            v = vals[name]
+            want = int(v, 16) if v.lower().startswith(("0x", "-0x")) else int(v.rstrip("f"))
+            assert getattr(evis, name) == want, name
+            checked += 1
+    assert checked >= 12

@@ -279,15 +279,6 @@ __device__ __forceinline__ float wave_max(float v) {
                      __int_as_float(__builtin_amdgcn_readlane(b, 48))));
 }
 
-__device__ __forceinline__ int wave_max_i(int v) {
-  v = max(v, dpp_i<kDppQuadSwap1>(v));
-  v = max(v, dpp_i<kDppQuadSwap2>(v));
-  v = max(v, dpp_i<kDppHalfMirror>(v));
-  v = max(v, dpp_i<kDppRowMirror>(v));
-  return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
 // Largest of non-negative doubles (their bit patterns order like their
 // values): a 64-bit unsigned max on (hi, lo) halves.
 template <int CTRL>

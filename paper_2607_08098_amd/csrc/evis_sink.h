@@ -197,7 +197,7 @@ __device__ __forceinline__ void emit_substep(
         if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
       }
     };
-    if (refr == 0 && wave_max_i(m) <= 4) {
+    if (refr == 0 && __ballot(m > 4) == 0ull) {   // no lane has more than four
       // Few events per lane: each lane writes its own, in order.
       int widx = excl;
 #pragma unroll

@@ -150,19 +150,15 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
       const bool bx = qx > fx0, by = qy > fy0;   // corners of strictly positive weight
       const uint32_t low = (DIR == DIR_A_TAGGED) ? ((uint32_t)src[c] | kATag) : (uint32_t)src[c];
       const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | low;
-      // Corner (x0, y0) always; a corner of zero weight repeats it instead
-      // (the same key twice into one cell changes nothing), so the four
+      // All four corners of the cell from one address; a corner of zero
+      // weight gets the empty key, which changes nothing, so the four
       // atomics need no branches.
       constexpr int ZS = zrow<TW>();
-      const int c00 = zcell<TW>((int)fx0 - Tx0, (int)fy0 - Ty0);
-      const int c01 = bx ? c00 + 1 : c00;
-      const int c10 = by ? c00 + ZS : c00;
-      const int c11 = (bx && by) ? c00 + ZS + 1 : c00;
-      unsigned long long* zb = zs[t];
-      atomicMin(zb + c00, key);
-      atomicMin(zb + c01, key);
-      atomicMin(zb + c10, key);
-      atomicMin(zb + c11, key);
+      unsigned long long* zb = zs[t] + zcell<TW>((int)fx0 - Tx0, (int)fy0 - Ty0);
+      atomicMin(zb, key);
+      atomicMin(zb + 1, bx ? key : kEmptyKey);
+      atomicMin(zb + ZS, by ? key : kEmptyKey);
+      atomicMin(zb + ZS + 1, (bx && by) ? key : kEmptyKey);
     }
   }
 }

@@ -130,6 +130,9 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
     src[c] = ok ? (int)__umul24((unsigned)sy[c], (unsigned)d.W) + sx[c] : -1;
     rec[c] = ldg(recs, ok ? ((int)__umul24((unsigned)by, (unsigned)d.ntx_src) + bx) * kBlkPx + r : 0);
   }
+  // image pixel (x, y) has z-buffer cell y ZS + x - corg (the apron's first
+  // cell is pixel (Tx0 - 1, Ty0 - 1))
+  const int corg = (Ty0 - 1) * zrow<TW>() + (Tx0 - 1);
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
     if (src[c] < 0) continue;
@@ -152,9 +155,10 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
       const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | low;
       // All four corners of the cell from one address; a corner of zero
       // weight gets the empty key, which changes nothing, so the four
-      // atomics need no branches.
+      // atomics need no branches.  y0 ZS + x0 is formed in float, exactly
+      // (|x0|, |y0| <= 2^12, so it is an integer below 2^24).
       constexpr int ZS = zrow<TW>();
-      unsigned long long* zb = zs[t] + zcell<TW>((int)fx0 - Tx0, (int)fy0 - Ty0);
+      unsigned long long* zb = zs[t] + ((int)fmaf(fy0, (float)ZS, fx0) - corg);
       atomicMin(zb, key);
       atomicMin(zb + 1, bx ? key : kEmptyKey);
       atomicMin(zb + ZS, by ? key : kEmptyKey);

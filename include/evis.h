@@ -50,7 +50,9 @@ extern "C" {
 #define EVIS_MAX_DIM 2047
 #define EVIS_MAX_ENVS 512
 #define EVIS_MAX_K 128
-#define EVIS_MAX_CROSSINGS 65535       /* crossings per pixel and substep (cap) */
+#define EVIS_MAX_CROSSINGS 65535       /* library limit: crossings counted per pixel and
+                                          substep (Eq. 4 has no bound; an infinite |dL|
+                                          counts as this many) */
 #define EVIS_MAX_SPAN_US (1 << 24)
 #define EVIS_T_LAST_INIT (-1073741824) /* "never fired" refractory state */
 
@@ -354,16 +356,21 @@ int evis_soft_count_backward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n
                              int32_t flags, void *stream);
 
 /* Event voxel grid (the per-polarity, 128-bin input of the paper's speed
- * estimator): events[0 .. min(*n_events, capacity)) (n_events a DEVICE
+ * estimator, Sec. "Sim-to-Real Rotational Speed Estimation" and its
+ * appendix): events[0 .. min(*n_events, capacity)) (n_events a DEVICE
  * int64, e.g. the cursor of evis_step_batch) of env env_id with
- * t0_us <= t < t1_us, at tau = (t - t0) * s with s = fl32(fl32(bins - 1) /
- * fl32(t1 - t0)) (float32), add 1 - q to bin b = floor(tau) and q to bin
- * b + 1, q = floor((tau - b) 2^16) / 2^16 (an event at tau >= bins - 1 goes
- * to the last bin alone), summed in 16-bit fixed point as uint32 (exact,
- * order-free; a voxel holds 65535 events, beyond which it wraps); then each
- * (polarity, bin) plane is divided by its maximum in float32 (all zero
- * when empty).  out is [2][bins][H][W] float32, polarity 0 (OFF) first;
- * it is also the accumulator.  2 <= bins <= EVIS_MAX_VOXEL_BINS. */
+ * t0_us <= t < t1_us sit at tau = (t - t0)(bins - 1)/(t1 - t0) on the axis
+ * of bin centres and are spread over bins floor(tau) and floor(tau) + 1 by
+ * linear interpolation in time; each (polarity, bin) plane is then divided
+ * by its maximum (all zero when empty).
+ * Number format (the library's, within a derived bound of the real-valued
+ * grid): tau from the float32 scale fl32(fl32(bins - 1) / fl32(t1 - t0)),
+ * the fraction q floored to 16 bits, 1 - q and q summed as uint32 fixed
+ * point (exact and independent of event order), one float32 division per
+ * voxel.  Limit: a voxel holds at most 65535 full-weight events per call
+ * (beyond that its uint32 sum wraps).
+ * out is [2][bins][H][W] float32, polarity 0 (OFF) first; it is also the
+ * accumulator.  2 <= bins <= EVIS_MAX_VOXEL_BINS. */
 #define EVIS_MAX_VOXEL_BINS 1024
 int evis_voxel_grid(evis_ctx *ctx, const evis_event *events, const int64_t *n_events,
                     int64_t capacity, int32_t env_id, int32_t H, int32_t W, int64_t t0_us,

@@ -65,7 +65,10 @@ Readings of the paper taken here (each is restated where it is used):
   R6  Eq. 7 endpoints: p_A = p, p_B = p - m_A(p); Z_B is sampled bilinearly
       with the position clamped into the image.
   R7  a source is invisible unless its intermediate depth is > 0 (NaN too).
-  R8  crossing count n = floor(|dL| / C) exactly, capped at N_MAX.
+  R8  crossing count n = floor(|dL| / C) of the exact real quotient, with
+      no upper bound; an infinite |dL| has no count (ValueError).  An
+      implementation that bounds the crossings of one pixel-substep states
+      its bound, and a test of that bound passes it as ``count_limit``.
   R9  the reference moves by fl(n * C) after all n crossings, also for
       crossings the refractory period suppresses.
   R10 crossing k of a substep is timed by linear interpolation of L between
@@ -102,15 +105,14 @@ Readings of the paper taken here (each is restated where it is used):
       crop margin m the warp runs on the whole rendered frame and only the
       inner pixels reach the event model (and the noise), in the cropped
       frame's coordinates; the margin keeps its state untouched.
-  R26 voxel grid: events of one env with t0 <= t < t1 go to position
-      tau = (t - t0) * s, s = fl32(fl32(B - 1) / fl32(t1 - t0)) (float32),
-      b = floor(tau) (at most B - 1), weight of bin b + 1 q = floor((tau - b)
-      2^16) / 2^16 and of bin b 1 - q (bin B - 1 alone at tau >= B - 1): the
-      weights are 16-bit fixed point so that the sums are integers (exact,
-      order-free; uint32, modulo 2^32, so a voxel holds 65535 events); then
-      each (polarity, bin) plane is divided by its maximum in float32
-      (fl32(acc) / fl32(max), all zero when empty).  Layout [2][B][H][W],
-      polarity 0 = OFF first.
+  R26 voxel grid: events of one env with t0 <= t < t1 sit at the real
+      position tau = (t - t0) (B - 1) / (t1 - t0) on the axis of the B bin
+      centres; linear interpolation in time gives bin b the weight
+      max(0, 1 - |tau - b|), i.e. 1 - (tau - floor(tau)) to floor(tau) and
+      tau - floor(tau) to the bin after it.  Sums and the division of each
+      (polarity, bin) plane by its maximum (all zero when empty) are
+      float64 with no bound on the events per voxel.  Layout
+      [2][B][H][W], polarity 0 = OFF first.
   R23 noise events are extra: they do not move L_ref, ignore the
       refractory period and leave t_last alone.
   R19 joint warp (WARP_JOINT): one z-buffer over the sources of both
@@ -131,7 +133,7 @@ import numpy as np
 
 F32 = np.float32
 EMPTY_KEY = np.uint64(0xFFFF_FFFF_FFFF_FFFF)
-N_MAX = 65535                 # R8: crossings per pixel-substep are capped here
+ENUMERATE_MAX = 10 ** 7       # more crossings than this in one pixel-substep: refuse to list them
 T_LAST_INIT = -(2 ** 30)      # "never fired": far enough back for any refractory period
 BLEND_TIME = 0
 BLEND_B_PRIMARY = 1
@@ -524,13 +526,21 @@ class Sensor:
         return on.astype(F32), off.astype(F32)
 
 
-def crossing_count(a, c) -> int:
-    """Eq. 4: n = floor(a / c) of the exact real quotient of float32 a >= c > 0,
-    capped at N_MAX (R8); an infinite a gives N_MAX."""
+def crossing_count(a, c, count_limit: Optional[int] = None) -> int:
+    """Eq. 4: n = floor(a / c) of the exact real quotient of float32 a >= c > 0
+    (R8).  An infinite a has no finite count and raises ValueError.
+
+    ``count_limit`` is not the paper's: it models an implementation that
+    bounds the crossings of one pixel-substep (n = min(n, limit), an infinite
+    a counting as the limit); tests of such a bound pass it explicitly."""
     if not math.isfinite(float(a)):
-        return N_MAX
-    n = Fraction(float(a)) // Fraction(float(c))
-    return int(min(n, N_MAX))
+        if count_limit is None:
+            raise ValueError("Eq. 4 gives no finite crossing count for an infinite |dL|")
+        return int(count_limit)
+    n = int(Fraction(float(a)) // Fraction(float(c)))
+    if count_limit is not None:
+        n = min(n, int(count_limit))
+    return n
 
 
 def crossing_time_offset(j, k, R, c, positive, prev, cur, Dt, span) -> int:
@@ -577,8 +587,10 @@ class EventLog:
 
 
 def emit_substep(j, prev, cur, R, tl, on, off, refractory_us, t0_us, Dt, span,
-                 env_id, log: EventLog, track_t_last: bool = True):
-    """Eq. 4 at substep j for every pixel; R and tl are updated in place."""
+                 env_id, log: EventLog, track_t_last: bool = True,
+                 count_limit: Optional[int] = None):
+    """Eq. 4 at substep j for every pixel; R and tl are updated in place
+    (count_limit: see crossing_count)."""
     H, W = cur.shape
     d = cur - R
     positive = d > 0
@@ -589,7 +601,9 @@ def emit_substep(j, prev, cur, R, tl, on, off, refractory_us, t0_us, Dt, span,
         y, x = divmod(int(flat), W)
         pos = bool(positive[y, x])
         cc = c[y, x]
-        n = crossing_count(a[y, x], cc)
+        n = crossing_count(a[y, x], cc, count_limit)
+        if n > ENUMERATE_MAX:
+            raise ValueError(f"{n} crossings in one pixel-substep: too many to list")
         r0 = R[y, x]
         for k in range(1, n + 1):
             t = t0_us + crossing_time_offset(j, k, r0, cc, pos, prev[y, x], cur[y, x], Dt, span)
@@ -601,10 +615,11 @@ def emit_substep(j, prev, cur, R, tl, on, off, refractory_us, t0_us, Dt, span,
         R[y, x] = r0 + nc if pos else r0 - nc
 
 
-def emit_events(S_seq, t0_us, t1_us, sensor: Sensor, L_ref, t_last=None, env_id=0):
+def emit_events(S_seq, t0_us, t1_us, sensor: Sensor, L_ref, t_last=None, env_id=0,
+                count_limit: Optional[int] = None):
     """Events from caller-supplied frames S_seq[0..K] (S_seq[0] is the
     previous sample; events come from j = 1..K).  Returns (events[N,5] as
-    x, y, t, p, env; L_ref'; t_last')."""
+    x, y, t, p, env; L_ref'; t_last').  count_limit: see crossing_count."""
     S_seq = [np.asarray(s, F32) for s in S_seq]
     K = len(S_seq) - 1
     H, W = S_seq[0].shape
@@ -619,7 +634,7 @@ def emit_events(S_seq, t0_us, t1_us, sensor: Sensor, L_ref, t_last=None, env_id=
     hot = hot_pixels(H, W, nz) if nz is not None else None
     for j in range(1, K + 1):
         emit_substep(j, S_seq[j - 1], S_seq[j], R, tl, on, off, sensor.refractory_us,
-                     t0_us, Dt, span, env_id, log, track)
+                     t0_us, Dt, span, env_id, log, track, count_limit)
         if nz is not None:
             noise_events(j, S_seq[j], Dt, t0_us, span, nz, env_id, log, hot)
     return log.array(), R, (tl.astype(np.int32) if track else None)
@@ -719,7 +734,8 @@ def choose_k(pair: Pair, sensor: Sensor) -> int:
     return adaptive_k(pair.m_A, pair.m_B, sensor.K_max)
 
 
-def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0, crop_margin: int = 0):
+def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0, crop_margin: int = 0,
+         count_limit: Optional[int] = None):
     """One keyframe pair: K, sub-frames (splat, gather, blend) and events, streaming
     over j.  Returns (events[N,5], L_ref', t_last', K).
 
@@ -727,7 +743,7 @@ def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0, crop_m
     pixels on every side; the warp uses all of it, the event model (and the
     noise) only the inner (H - 2m) x (W - 2m) pixels, whose events are in
     the cropped frame's coordinates; the margin's L_ref and t_last are left
-    as they are."""
+    as they are.  count_limit: see crossing_count."""
     K = choose_k(pair, sensor)
     H, W = pair.shape
     m = int(crop_margin)
@@ -747,7 +763,7 @@ def step(pair: Pair, sensor: Sensor, L_ref, t_last=None, env_id: int = 0, crop_m
     for j, L, _ in substep_frames(pair, K, range(1, K + 1), sensor.blend_mode):
         Lc = L[inner]
         emit_substep(j, prev, Lc, Rc, tlc, on, off, sensor.refractory_us, pair.t0_us, Dt,
-                     span, env_id, log, track)
+                     span, env_id, log, track, count_limit)
         if nz is not None:
             noise_events(j, Lc, Dt, pair.t0_us, span, nz, env_id, log, hot)
         prev = Lc
@@ -788,43 +804,43 @@ def canonical(ev: np.ndarray) -> np.ndarray:
 # event voxel grid (R26)
 # ---------------------------------------------------------------------------
 
-VOXEL_ONE = 1 << 16      # one event's total weight in the fixed-point sums
-
-
 def voxel_weights(t, t0_us: int, t1_us: int, bins: int):
-    """Per event time: (bin b, fixed-point weight of b, of b + 1)."""
-    s = F32(F32(bins - 1) / F32(t1_us - t0_us))
-    tau = (np.asarray(t, np.int64) - t0_us).astype(F32) * s
+    """Per event time: its position tau = (t - t0)(B - 1)/(t1 - t0) on the
+    axis of bin centres (float64), the bin b = floor(tau) below it, and the
+    linear-interpolation weights 1 - (tau - b) of bin b and tau - b of bin
+    b + 1 (R26)."""
+    tau = (np.asarray(t, np.int64) - t0_us).astype(np.float64) * float(bins - 1) \
+        / float(t1_us - t0_us)
     b = np.floor(tau).astype(np.int64)
-    last = b >= bins - 1
+    last = b >= bins - 1                  # only t = t1 would land here; kept for safety
     b = np.where(last, bins - 1, b)
-    q1 = np.floor((tau - b.astype(F32)) * F32(VOXEL_ONE)).astype(np.int64)
-    q1 = np.where(last, 0, q1)
-    return b, VOXEL_ONE - q1, q1
+    w1 = np.where(last, 0.0, tau - b)
+    return b, 1.0 - w1, w1
 
 
 def voxel_counts(ev, env_id: int, H: int, W: int, t0_us: int, t1_us: int, bins: int = 128):
-    """Fixed-point sums [2][bins][H][W] (uint64 here; the grid keeps them
-    modulo 2^32)."""
+    """Weight sums [2][bins][H][W] (float64, no bound on the events per voxel)
+    of one env's events with t0 <= t < t1."""
     ev = np.asarray(ev, np.int64).reshape(-1, 5)
     sel = (ev[:, 4] == env_id) & (ev[:, 2] >= t0_us) & (ev[:, 2] < t1_us)
     ev = ev[sel]
-    acc = np.zeros((2, bins, H, W), np.uint64)
-    b, q0, q1 = voxel_weights(ev[:, 2], t0_us, t1_us, bins)
+    acc = np.zeros((2, bins, H, W), np.float64)
+    b, w0, w1 = voxel_weights(ev[:, 2], t0_us, t1_us, bins)
     x, y, p = ev[:, 0], ev[:, 1], ev[:, 3]
-    np.add.at(acc, (p, b, y, x), q0.astype(np.uint64))
-    nxt = q1 > 0
-    np.add.at(acc, (p[nxt], b[nxt] + 1, y[nxt], x[nxt]), q1[nxt].astype(np.uint64))
+    np.add.at(acc, (p, b, y, x), w0)
+    nxt = w1 > 0
+    np.add.at(acc, (p[nxt], b[nxt] + 1, y[nxt], x[nxt]), w1[nxt])
     return acc
 
 
 def voxel_grid(ev, env_id: int, H: int, W: int, t0_us: int, t1_us: int, bins: int = 128):
-    """Normalised per-polarity voxel grid, float32 [2][bins][H][W] (R26)."""
-    acc = voxel_counts(ev, env_id, H, W, t0_us, t1_us, bins) & np.uint64(0xFFFF_FFFF)
+    """Normalised per-polarity voxel grid, float64 [2][bins][H][W] (R26):
+    every (polarity, bin) plane divided by its own maximum."""
+    acc = voxel_counts(ev, env_id, H, W, t0_us, t1_us, bins)
     mx = acc.reshape(2, bins, -1).max(axis=2)
-    out = np.zeros((2, bins, H, W), F32)
+    out = np.zeros((2, bins, H, W), np.float64)
     for p in range(2):
         for b in range(bins):
             if mx[p, b] > 0:
-                out[p, b] = acc[p, b].astype(F32) / F32(mx[p, b])
+                out[p, b] = acc[p, b] / mx[p, b]
     return out

@@ -11,6 +11,7 @@ from __future__ import annotations
 import math
 import os
 from decimal import Decimal, getcontext
+from fractions import Fraction
 
 import numpy as np
 
@@ -628,8 +629,20 @@ def pin_crossing_count_exact(o):
     for a, c in cases:
         want = int((Decimal(float(a)) / Decimal(float(c))).to_integral_value(rounding="ROUND_FLOOR"))
         assert o.crossing_count(a, c) == want, (float(a), float(c))
-    assert o.crossing_count(F32(np.inf), F32(0.2)) == o.N_MAX
-    assert o.crossing_count(F32(1e6), F32(0.01)) == o.N_MAX
+    # no cap: a count far above any implementation's per-substep bound is exact
+    for a, c in ((F32(1e6), F32(0.01)), (F32(20000.0), F32(0.2)), (F32(13107.25), F32(0.2))):
+        want = int((Decimal(float(a)) / Decimal(float(c))).to_integral_value(rounding="ROUND_FLOOR"))
+        assert want > 65535 and o.crossing_count(a, c) == want, (float(a), float(c))
+    # an infinite difference has no count; a stated limit bounds it
+    try:
+        o.crossing_count(F32(np.inf), F32(0.2))
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("an infinite |dL| must have no crossing count")
+    assert o.crossing_count(F32(np.inf), F32(0.2), count_limit=7) == 7
+    assert o.crossing_count(F32(3.0), F32(0.1), count_limit=7) == 7
+    assert o.crossing_count(F32(0.6), F32(0.2), count_limit=7) == 3   # 3 * 0.2f < 0.6f
 
 
 def pin_crop_margin(o):
@@ -773,9 +786,11 @@ def pin_noise_off_and_seeded(o):
 # ---------------------------------------------------------------------------
 
 def pin_voxel_closed_forms(o):
-    """Hand-worked cases on a dyadic time scale (s = 4 / 1024 = 2^-8 exact):
-    an event on a bin point fills that bin alone, one halfway splits evenly,
-    and every non-empty (polarity, bin) plane peaks at exactly 1."""
+    """Hand-worked cases on a dyadic time scale ((B - 1) / (t1 - t0) = 4 / 1024
+    = 2^-8, exact): an event on a bin centre fills that bin alone, one halfway
+    between two centres gives each 1/2, one at tau = 1023/256 gives bin 3 the
+    weight 1/256 and bin 4 the rest; other envs and times outside [t0, t1)
+    add nothing; every non-empty (polarity, bin) plane peaks at exactly 1."""
     ev = np.array([[1, 2, 256, 1, 0],      # tau = 1.0   -> bin 1
                    [3, 0, 384, 0, 0],      # tau = 1.5   -> bins 1, 2 halves
                    [3, 0, 1023, 0, 0],     # tau = 3.996 -> bin 3 (and 4)
@@ -783,30 +798,59 @@ def pin_voxel_closed_forms(o):
                    [0, 1, 1024, 1, 0],     # t = t1: outside the window
                    [0, 1, -1, 1, 0]])      # before t0
     acc = o.voxel_counts(ev, 0, 3, 4, 0, 1024, 5)
-    assert acc[1, 1, 2, 1] == 65536 and int(acc[1].sum()) == 65536
-    assert acc[0, 1, 0, 3] == 32768 and acc[0, 2, 0, 3] == 32768
-    q1 = int(np.floor((1023 / 256 - 3) * 65536))
-    assert acc[0, 3, 0, 3] == 65536 - q1 and acc[0, 4, 0, 3] == q1
+    assert acc[1, 1, 2, 1] == 1.0 and acc[1].sum() == 1.0
+    assert acc[0, 1, 0, 3] == 0.5 and acc[0, 2, 0, 3] == 0.5
+    assert acc[0, 3, 0, 3] == 1.0 / 256.0 and acc[0, 4, 0, 3] == 255.0 / 256.0
+    assert acc.sum() == 3.0
     v = o.voxel_grid(ev, 0, 3, 4, 0, 1024, 5)
     assert v[1, 1, 2, 1] == 1.0 and v[0, 1, 0, 3] == 1.0 and v[0, 2, 0, 3] == 1.0
+    assert v[0, 3, 0, 3] == 1.0 and v[0, 4, 0, 3] == 1.0
     assert np.count_nonzero(v) == 5
+
+
+def pin_voxel_brute_force(o):
+    """Linear interpolation in time written as the hat function: bin b of a
+    voxel gets max(0, 1 - |tau - b|) from each event at real position tau
+    (exact rationals, one event at a time), then each plane is divided by its
+    maximum.  Agrees with the grid to float64 rounding on random events,
+    including many events in one voxel (no bound on the count)."""
+    rng = np.random.default_rng(83)
+    n, H, W, B, t0, t1 = 400, 3, 4, 7, 5000, 91000
+    ev = np.stack([rng.integers(0, W, n), rng.integers(0, H, n), rng.integers(t0 - 900, t1 + 900, n),
+                   rng.integers(0, 2, n), rng.integers(0, 2, n)], axis=1)
+    ev[:150, 0:2] = (1, 2)                  # a crowded voxel
+    ev[:150, 4] = 1
+    want = np.zeros((2, B, H, W))
+    for x, y, t, p, e in ev.tolist():
+        if e != 1 or not (t0 <= t < t1):
+            continue
+        tau = Fraction(t - t0) * (B - 1) / (t1 - t0)
+        for b in range(B):
+            w = 1 - abs(tau - b)
+            if w > 0:
+                want[p, b, y, x] += float(w)
+    acc = o.voxel_counts(ev, 1, H, W, t0, t1, B)
+    assert np.allclose(acc, want, rtol=1e-12, atol=1e-12)
+    mx = want.reshape(2, B, -1).max(axis=2)
+    norm = np.where(mx[:, :, None, None] > 0, want / np.where(mx > 0, mx, 1)[:, :, None, None], 0.0)
+    assert np.allclose(o.voxel_grid(ev, 1, H, W, t0, t1, B), norm, rtol=1e-12, atol=1e-12)
 
 
 def pin_voxel_invariants(o):
     """Random events: each event in the window adds exactly one unit of
-    weight, whose centroid is its exact time position to within 2/2^16; each
-    non-empty plane of the normalised grid has maximum 1."""
+    weight, whose centroid is its exact time position; each non-empty plane
+    of the normalised grid has maximum 1."""
     rng = np.random.default_rng(59)
     n, H, W, B, t0, t1 = 3000, 9, 11, 128, 1000, 501000
     ev = np.stack([rng.integers(0, W, n), rng.integers(0, H, n), rng.integers(t0 - 5000, t1 + 5000, n),
                    rng.integers(0, 2, n), rng.integers(0, 2, n)], axis=1)
     inside = (ev[:, 4] == 1) & (ev[:, 2] >= t0) & (ev[:, 2] < t1)
-    acc = o.voxel_counts(ev, 1, H, W, t0, t1, B).astype(np.int64)
-    assert int(acc.sum()) == int(inside.sum()) * 65536
+    acc = o.voxel_counts(ev, 1, H, W, t0, t1, B)
+    assert abs(acc.sum() - inside.sum()) <= 1e-9 * inside.sum()
     bidx = np.arange(B).reshape(1, B, 1, 1)
     cent = float((acc * bidx).sum())
-    want = float(((ev[inside, 2] - t0) * (B - 1) / (t1 - t0)).sum()) * 65536
-    assert abs(cent - want) <= 2.0 * inside.sum()
+    want = float(sum(Fraction(int(t) - t0) * (B - 1) / (t1 - t0) for t in ev[inside, 2]))
+    assert abs(cent - want) <= 1e-9 * want
     v = o.voxel_grid(ev, 1, H, W, t0, t1, B)
     mx = v.reshape(2, B, -1).max(axis=2)
     assert np.all((mx == 1.0) | (mx == 0.0)) and np.all(mx[acc.reshape(2, B, -1).max(axis=2) > 0] == 1.0)

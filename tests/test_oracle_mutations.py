@@ -97,8 +97,8 @@ def m_adaptive_floor(m_A, m_B, K_max):
     return int(min(max(int(math.floor(math.sqrt(best))), 1), K_max))   # planted: floor
 
 
-def m_rounded_quotient(a, c):
-    return int(min(math.floor(F32(a) / F32(c)), o.N_MAX))   # planted: floor of fl32(a/c)
+def m_rounded_quotient(a, c, count_limit=None):
+    return int(math.floor(F32(a) / F32(c)))               # planted: floor of fl32(a/c)
 
 
 def m_time_shift(j, k, R, c, positive, prev, cur, Dt, span):
@@ -107,7 +107,7 @@ def m_time_shift(j, k, R, c, positive, prev, cur, Dt, span):
 
 def _emit_variant(drop_residual=False, flip=False, refr_keeps_ref=False):
     def emit(j, prev, cur, R, tl, on, off, refractory_us, t0_us, Dt, span, env_id, log,
-             track_t_last=True):
+             track_t_last=True, count_limit=None):
         H, W = cur.shape
         d = cur - R
         positive = d > 0
@@ -118,7 +118,7 @@ def _emit_variant(drop_residual=False, flip=False, refr_keeps_ref=False):
             y, x = divmod(int(flat), W)
             pos = bool(positive[y, x])
             cc = c[y, x]
-            n = o.crossing_count(a[y, x], cc)
+            n = o.crossing_count(a[y, x], cc, count_limit)
             r0 = R[y, x]
             kept = 0
             for k in range(1, n + 1):
@@ -261,14 +261,20 @@ def m_crop_after_the_fact(pair, sensor, L_ref, t_last=None, env_id=0, crop_margi
 
 
 def m_voxel_weights_swapped(t, t0_us, t1_us, bins):
-    b, q0, q1 = o.__dict__["_orig_vw"](t, t0_us, t1_us, bins)
-    return b, q1 + (q0 - q1) * (q1 == 0), q0 * (q1 != 0)    # planted: weights on the wrong bins
+    b, w0, w1 = o.__dict__["_orig_vw"](t, t0_us, t1_us, bins)
+    return b, np.where(w1 == 0, w0, w1), np.where(w1 == 0, 0.0, w0)   # planted: wrong bins
 
 
 def m_voxel_global_max(ev, env_id, H, W, t0_us, t1_us, bins=128):
-    acc = o.voxel_counts(ev, env_id, H, W, t0_us, t1_us, bins) & np.uint64(0xFFFF_FFFF)
+    acc = o.voxel_counts(ev, env_id, H, W, t0_us, t1_us, bins)
     mx = acc.max()                                          # planted: one maximum for all bins
-    return (acc.astype(F32) / F32(mx)) if mx > 0 else np.zeros(acc.shape, F32)
+    return (acc / mx) if mx > 0 else np.zeros(acc.shape)
+
+
+def m_voxel_nearest_bin(t, t0_us, t1_us, bins):
+    b, w0, w1 = o.__dict__["_orig_vw"](t, t0_us, t1_us, bins)
+    up = w1 >= 0.5                                          # planted: nearest bin, no interpolation
+    return np.where(up, b + 1, b), np.ones_like(w0), np.zeros_like(w1)
 
 
 def m_pack_shift(ev):
@@ -310,6 +316,7 @@ MUTANTS = [
     ("crop_after_the_fact", "step", m_crop_after_the_fact, P.pin_crop_margin),
     ("voxel_weights_swapped", "voxel_weights", m_voxel_weights_swapped, P.pin_voxel_invariants),
     ("voxel_global_max", "voxel_grid", m_voxel_global_max, P.pin_voxel_closed_forms),
+    ("voxel_nearest_bin", "voxel_weights", m_voxel_nearest_bin, P.pin_voxel_brute_force),
 ]
 
 

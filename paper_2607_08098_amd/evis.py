@@ -154,14 +154,50 @@ class EvisError(RuntimeError):
         self.code = code
 
 
-def _ptr(t: Optional[torch.Tensor]):
+def _is_device(t: torch.Tensor) -> bool:
+    return t.is_cuda
+
+
+def _ptr(t: Optional[torch.Tensor], name: str = "tensor", dtype: Optional[torch.dtype] = None,
+         numel: Optional[int] = None, device=None, min_numel: Optional[int] = None):
+    """Device pointer of a contiguous tensor, after checking what the kernel
+    will assume of it: dtype, exact (numel) or least (min_numel) element
+    count, and device.  A mismatch raises ValueError before anything is
+    enqueued (a wrong size would otherwise become an out-of-bounds access)."""
     if t is None:
         return None
-    if not t.is_cuda:
-        raise ValueError("libevis takes device tensors")
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements (shape {tuple(t.shape)}), expected {numel}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements (shape {tuple(t.shape)}), "
+                         f"expected at least {min_numel}")
     if not t.is_contiguous():
-        raise ValueError("libevis takes contiguous tensors")
+        raise ValueError(f"{name}: libevis takes contiguous tensors")
+    if not _is_device(t):
+        raise ValueError(f"{name}: libevis takes device tensors")
+    if device is not None and t.device != torch.device(device):
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _hw(t: torch.Tensor, name: str):
+    """(H, W) of a [..., H, W] plane."""
+    if not isinstance(t, torch.Tensor) or t.dim() < 2:
+        raise ValueError(f"{name}: expected a tensor of shape [..., H, W]")
+    return int(t.shape[-2]), int(t.shape[-1])
+
+
+def _events_ptrs(out: torch.Tensor, n_total: torch.Tensor, device=None):
+    """Event buffer [capacity, 2] int32 and its int64 cursor (8-byte atomics)."""
+    if not isinstance(out, torch.Tensor) or out.dim() != 2 or out.shape[1] != 2:
+        raise ValueError("out: expected an event buffer of shape [capacity, 2]")
+    dev = device if device is not None else out.device
+    return (_ptr(out, "out", torch.int32, device=dev),
+            _ptr(n_total, "n_total", torch.int64, min_numel=1, device=dev))
 
 
 def _stream(stream=None):
@@ -203,20 +239,34 @@ class Context:
 
 
 def make_pair(d: dict) -> EvisPair:
-    H, W = int(d["L_A"].shape[-2]), int(d["L_A"].shape[-1])
-    return EvisPair(H, W, _ptr(d["L_A"]), _ptr(d["L_B"]), _ptr(d["m_A"]), _ptr(d["m_B"]),
-                    _ptr(d["Z_A"]), _ptr(d["Z_B"]), int(d.get("t0", 0)), int(d.get("t1", 16667)))
+    """L_A, L_B, Z_A, Z_B float32 [H, W]; m_A, m_B float32 [H, W, 2]; one device."""
+    H, W = _hw(d["L_A"], "L_A")
+    dev = d["L_A"].device
+    f32 = torch.float32
+    plane = lambda k: _ptr(d[k], k, f32, numel=H * W, device=dev)
+    field = lambda k: _ptr(d[k], k, f32, numel=H * W * 2, device=dev)
+    for k in ("m_A", "m_B"):
+        if d[k].shape[-1] != 2:
+            raise ValueError(f"{k}: expected shape [H, W, 2], got {tuple(d[k].shape)}")
+    return EvisPair(H, W, plane("L_A"), plane("L_B"), field("m_A"), field("m_B"),
+                    plane("Z_A"), plane("Z_B"), int(d.get("t0", 0)), int(d.get("t1", 16667)))
 
 
-def make_sensor(d: dict) -> EvisSensor:
+def make_sensor(d: dict, H: Optional[int] = None, W: Optional[int] = None, device=None) -> EvisSensor:
+    """theta_on / theta_off (optional): float32 [H, W] per-pixel thresholds."""
+    n = None if H is None else H * W
     return EvisSensor(float(d.get("C_on", 0.2)), float(d.get("C_off", 0.2)),
-                      _ptr(d.get("theta_on")), _ptr(d.get("theta_off")),
+                      _ptr(d.get("theta_on"), "theta_on", torch.float32, numel=n, device=device),
+                      _ptr(d.get("theta_off"), "theta_off", torch.float32, numel=n, device=device),
                       int(d.get("refractory_us", 0)), int(d.get("K", 0)), int(d.get("K_max", 64)),
                       int(d.get("blend_mode", EVIS_BLEND_TIME)))
 
 
-def make_state(d: dict) -> EvisState:
-    return EvisState(_ptr(d["L_ref"]), _ptr(d.get("t_last")))
+def make_state(d: dict, H: Optional[int] = None, W: Optional[int] = None, device=None) -> EvisState:
+    """L_ref float32 [H, W]; t_last (optional) int32 [H, W]."""
+    n = None if H is None else H * W
+    return EvisState(_ptr(d["L_ref"], "L_ref", torch.float32, numel=n, device=device),
+                     _ptr(d.get("t_last"), "t_last", torch.int32, numel=n, device=device))
 
 
 def make_noise(nz: dict) -> EvisNoise:
@@ -233,8 +283,10 @@ def make_noise(nz: dict) -> EvisNoise:
 def make_env(d: dict, keep: Optional[list] = None) -> EvisEnv:
     """d["noise"] (optional) is a make_noise dict; the EvisNoise it becomes
     is appended to `keep`, which must outlive every call that uses the env."""
-    env = EvisEnv(make_pair(d), make_sensor(d), make_state(d), int(d.get("env_id", 0)),
-                  int(d.get("crop_margin", 0)))
+    pair = make_pair(d)
+    dev = d["L_A"].device
+    env = EvisEnv(pair, make_sensor(d, pair.H, pair.W, dev), make_state(d, pair.H, pair.W, dev),
+                  int(d.get("env_id", 0)), int(d.get("crop_margin", 0)))
     if d.get("noise") is not None:
         nz = make_noise(d["noise"])
         if keep is None:
@@ -258,16 +310,22 @@ def evis_log_luminance(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=Non
     shape = x.shape[:-1] if channels == 3 else x.shape
     if out is None:
         out = torch.empty(shape, dtype=torch.float32, device=x.device)
-    ctx.check(ctx.lib.evis_log_luminance(ctx.handle, _ptr(x), channels, n, eps, _ptr(out), _stream(stream)))
+    xp = _ptr(x, "x", torch.float32)
+    op = _ptr(out, "out", torch.float32, numel=n, device=x.device)
+    ctx.check(ctx.lib.evis_log_luminance(ctx.handle, xp, channels, n, eps, op, _stream(stream)))
     return out
 
 
 def evis_log_channels(ctx: Context, x: torch.Tensor, eps: float = 1e-3, out=None, stream=None):
     """x: [..., 3] linear RGB on the device -> [3, ...] per-channel log."""
+    if x.dim() < 1 or x.shape[-1] != 3:
+        raise ValueError("x: expected linear RGB of shape [..., 3]")
     n = x.numel() // 3
     if out is None:
         out = torch.empty((3,) + tuple(x.shape[:-1]), dtype=torch.float32, device=x.device)
-    ctx.check(ctx.lib.evis_log_channels(ctx.handle, _ptr(x), n, eps, _ptr(out), _stream(stream)))
+    xp = _ptr(x, "x", torch.float32)
+    op = _ptr(out, "out", torch.float32, numel=3 * n, device=x.device)
+    ctx.check(ctx.lib.evis_log_channels(ctx.handle, xp, n, eps, op, _stream(stream)))
     return out
 
 
@@ -276,8 +334,10 @@ def evis_voxel_grid(ctx: Context, out_events: torch.Tensor, n_total: torch.Tenso
     """Normalised per-polarity voxel grid [2, bins, H, W] of one env's events."""
     if out is None:
         out = torch.empty((2, bins, H, W), dtype=torch.float32, device=out_events.device)
-    ctx.check(ctx.lib.evis_voxel_grid(ctx.handle, _ptr(out_events), _ptr(n_total), out_events.shape[0],
-                                      env_id, H, W, t0_us, t1_us, bins, _ptr(out), _stream(stream)))
+    ep, npt = _events_ptrs(out_events, n_total)
+    op = _ptr(out, "out", torch.float32, numel=2 * bins * H * W, device=out_events.device)
+    ctx.check(ctx.lib.evis_voxel_grid(ctx.handle, ep, npt, out_events.shape[0],
+                                      env_id, H, W, t0_us, t1_us, bins, op, _stream(stream)))
     return out
 
 
@@ -290,10 +350,18 @@ def evis_defocus_batch(ctx: Context, pairs, sigma: float, stream=None):
     """pairs: sequence of (x, out) device tensors, each [H, W] or [H, W, 3]
     (all with the same channel count)."""
     arr = (EvisImage * len(pairs))()
-    channels = 1
+    channels = None
     for i, (x, out) in enumerate(pairs):
-        channels = 3 if (x.dim() == 3 and x.shape[-1] == 3) else 1
-        arr[i] = EvisImage(_ptr(x).value, _ptr(out).value, x.shape[0], x.shape[1])
+        c = 3 if (x.dim() == 3 and x.shape[-1] == 3) else 1
+        if x.dim() != (3 if c == 3 else 2):
+            raise ValueError(f"image {i}: expected [H, W] or [H, W, 3], got {tuple(x.shape)}")
+        if channels is not None and c != channels:
+            raise ValueError("evis_defocus_batch: every image needs the same channel count")
+        channels = c
+        xp = _ptr(x, f"x[{i}]", torch.float32)
+        op = _ptr(out, f"out[{i}]", torch.float32, numel=x.numel(), device=x.device)
+        arr[i] = EvisImage(xp.value, op.value, x.shape[0], x.shape[1])
+    channels = channels or 1
     ctx.check(ctx.lib.evis_defocus_batch(ctx.handle, arr, len(pairs), channels, float(sigma),
                                          _stream(stream)))
 
@@ -301,19 +369,26 @@ def evis_defocus_batch(ctx: Context, pairs, sigma: float, stream=None):
 def evis_defocus(ctx: Context, x: torch.Tensor, sigma: float, out=None, stream=None):
     """x: [H, W] or [H, W, 3] float32 linear intensity on the device."""
     channels = 3 if (x.dim() == 3 and x.shape[-1] == 3) else 1
+    if x.dim() != (3 if channels == 3 else 2):
+        raise ValueError(f"x: expected [H, W] or [H, W, 3], got {tuple(x.shape)}")
     H, W = x.shape[0], x.shape[1]
     if out is None:
         out = torch.empty_like(x)
-    ctx.check(ctx.lib.evis_defocus(ctx.handle, _ptr(x), H, W, channels, float(sigma), _ptr(out),
+    xp = _ptr(x, "x", torch.float32)
+    op = _ptr(out, "out", torch.float32, numel=x.numel(), device=x.device)
+    ctx.check(ctx.lib.evis_defocus(ctx.handle, xp, H, W, channels, float(sigma), op,
                                    _stream(stream)))
     return out
 
 
 def evis_state_init(ctx: Context, L_first: torch.Tensor, L_ref: torch.Tensor,
                     t_last: Optional[torch.Tensor] = None, stream=None):
-    st = EvisState(_ptr(L_ref), _ptr(t_last))
-    H, W = L_first.shape[-2:]
-    ctx.check(ctx.lib.evis_state_init(ctx.handle, _ptr(L_first), H, W, ctypes.byref(st), _stream(stream)))
+    H, W = _hw(L_first, "L_first")
+    dev = L_first.device
+    lp = _ptr(L_first, "L_first", torch.float32, numel=H * W)
+    st = EvisState(_ptr(L_ref, "L_ref", torch.float32, numel=H * W, device=dev),
+                   _ptr(t_last, "t_last", torch.int32, numel=H * W, device=dev))
+    ctx.check(ctx.lib.evis_state_init(ctx.handle, lp, H, W, ctypes.byref(st), _stream(stream)))
 
 
 def evis_substep_count(ctx: Context, pair: dict, K_max: int, K_out: Optional[torch.Tensor] = None,
@@ -321,22 +396,26 @@ def evis_substep_count(ctx: Context, pair: dict, K_max: int, K_out: Optional[tor
     if K_out is None:
         K_out = torch.zeros(1, dtype=torch.int32, device=pair["L_A"].device)
     p = make_pair(pair)
-    ctx.check(ctx.lib.evis_substep_count(ctx.handle, ctypes.byref(p), K_max, _ptr(K_out), _stream(stream)))
+    kp = _ptr(K_out, "K_out", torch.int32, min_numel=1, device=pair["L_A"].device)
+    ctx.check(ctx.lib.evis_substep_count(ctx.handle, ctypes.byref(p), K_max, kp, _stream(stream)))
     return K_out
 
 
 def evis_interpolate(ctx: Context, pair: dict, K: int, j_begin: int, j_end: int,
                      blend_mode: int = EVIS_BLEND_TIME, L_out=None, hole_mask=None,
                      want_holes: bool = True, stream=None):
-    H, W = pair["L_A"].shape[-2:]
+    H, W = _hw(pair["L_A"], "L_A")
     dev = pair["L_A"].device
     if L_out is None:
         L_out = torch.empty((j_end - j_begin, H, W), dtype=torch.float32, device=dev)
     if hole_mask is None and want_holes:
         hole_mask = torch.empty((j_end - j_begin, H, W), dtype=torch.uint8, device=dev)
     p = make_pair(pair)
+    n = max(0, j_end - j_begin) * H * W
+    lo = _ptr(L_out, "L_out", torch.float32, min_numel=n, device=dev)
+    hm = _ptr(hole_mask, "hole_mask", torch.uint8, min_numel=n, device=dev)
     ctx.check(ctx.lib.evis_interpolate(ctx.handle, ctypes.byref(p), K, j_begin, j_end, blend_mode,
-                                       _ptr(L_out), _ptr(hole_mask), _stream(stream)))
+                                       lo, hm, _stream(stream)))
     return L_out, hole_mask
 
 
@@ -344,20 +423,25 @@ def evis_generate_events(ctx: Context, L_seq: torch.Tensor, t0: int, t1: int, se
                          state: dict, env_id: int, out: torch.Tensor, n_total: torch.Tensor,
                          flags: int = EVIS_FLAG_RESET_CURSOR, stream=None, noise: Optional[dict] = None):
     """noise: a make_noise dict (evis_generate_events_noise), or None."""
+    if not isinstance(L_seq, torch.Tensor) or L_seq.dim() != 3:
+        raise ValueError("L_seq: expected float32 samples of shape [K + 1, H, W]")
     K = L_seq.shape[0] - 1
-    H, W = L_seq.shape[-2:]
-    s = make_sensor(sensor)
-    st = make_state(state)
+    H, W = _hw(L_seq, "L_seq")
+    dev = L_seq.device
+    lp = _ptr(L_seq, "L_seq", torch.float32)
+    s = make_sensor(sensor, H, W, dev)
+    st = make_state(state, H, W, dev)
+    op, npt = _events_ptrs(out, n_total, dev)
     if noise is None:
-        ctx.check(ctx.lib.evis_generate_events(ctx.handle, _ptr(L_seq), H, W, K, int(t0), int(t1),
-                                               ctypes.byref(s), ctypes.byref(st), env_id, _ptr(out),
-                                               out.shape[0], _ptr(n_total), flags, _stream(stream)))
+        ctx.check(ctx.lib.evis_generate_events(ctx.handle, lp, H, W, K, int(t0), int(t1),
+                                               ctypes.byref(s), ctypes.byref(st), env_id, op,
+                                               out.shape[0], npt, flags, _stream(stream)))
     else:
         nz = make_noise(noise)
-        ctx.check(ctx.lib.evis_generate_events_noise(ctx.handle, _ptr(L_seq), H, W, K, int(t0),
+        ctx.check(ctx.lib.evis_generate_events_noise(ctx.handle, lp, H, W, K, int(t0),
                                                      int(t1), ctypes.byref(s), ctypes.byref(st),
-                                                     env_id, ctypes.byref(nz), _ptr(out),
-                                                     out.shape[0], _ptr(n_total), flags,
+                                                     env_id, ctypes.byref(nz), op,
+                                                     out.shape[0], npt, flags,
                                                      _stream(stream)))
     return n_total
 
@@ -376,8 +460,10 @@ def evis_step_batch(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor
                     stream=None):
     """envs: a sequence of env dicts or a prebuilt env_array()."""
     arr = envs if isinstance(envs, ctypes.Array) else env_array(envs)
-    ctx.check(ctx.lib.evis_step_batch(ctx.handle, arr, len(arr), _ptr(out), out.shape[0],
-                                      _ptr(n_total), _ptr(K_used), flags, _stream(stream)))
+    op, npt = _events_ptrs(out, n_total)
+    kp = _ptr(K_used, "K_used", torch.int32, min_numel=len(arr), device=out.device)
+    ctx.check(ctx.lib.evis_step_batch(ctx.handle, arr, len(arr), op, out.shape[0],
+                                      npt, kp, flags, _stream(stream)))
     return n_total
 
 
@@ -400,7 +486,8 @@ def evis_autotune(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, 
     arr = envs if isinstance(envs, ctypes.Array) else env_array(envs)
     best = EvisTuning()
     ms = ctypes.c_float()
-    ctx.check(ctx.lib.evis_autotune(ctx.handle, arr, len(arr), _ptr(out), out.shape[0], _ptr(n_total),
+    op, npt = _events_ptrs(out, n_total)
+    ctx.check(ctx.lib.evis_autotune(ctx.handle, arr, len(arr), op, out.shape[0], npt,
                                     reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
     return best, ms.value
 
@@ -408,8 +495,15 @@ def evis_autotune(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, 
 def soft_env_array(L_A, L_B, m_A, m_B, Z_A, Z_B, L_ref, S=None, gS=None, gL_A=None, gL_B=None,
                    gm_A=None, gm_B=None):
     """evis_soft_env[n] from batched tensors [n, H, W] (m: [n, H, W, 2])."""
-    n = L_A.shape[0]
+    if not isinstance(L_A, torch.Tensor) or L_A.dim() != 3:
+        raise ValueError("L_A: expected float32 planes of shape [n, H, W]")
+    n, H, W = (int(v) for v in L_A.shape)
+    dev = L_A.device
     arr = (EvisSoftEnv * n)()
+    for name, t, per in (("L_ref", L_ref, H * W), ("S", S, H * W), ("gS", gS, H * W),
+                         ("gL_A", gL_A, H * W), ("gL_B", gL_B, H * W), ("gm_A", gm_A, 2 * H * W),
+                         ("gm_B", gm_B, 2 * H * W)):
+        _ptr(t, name, torch.float32, numel=n * per, device=dev)
     for e in range(n):
         pair = make_pair(dict(L_A=L_A[e], L_B=L_B[e], m_A=m_A[e], m_B=m_B[e], Z_A=Z_A[e], Z_B=Z_B[e],
                               t0=0, t1=1))
@@ -421,14 +515,17 @@ def soft_env_array(L_A, L_B, m_A, m_B, Z_A, Z_B, L_ref, S=None, gS=None, gL_A=No
 
 def evis_soft_count_forward(ctx: Context, envs, K: int, tau: float, blend_mode: int,
                             C: torch.Tensor, stream=None):
-    ctx.check(ctx.lib.evis_soft_count_forward(ctx.handle, envs, len(envs), K, tau, blend_mode, _ptr(C),
+    cp = _ptr(C, "C", torch.float32, min_numel=len(envs))
+    ctx.check(ctx.lib.evis_soft_count_forward(ctx.handle, envs, len(envs), K, tau, blend_mode, cp,
                                               _stream(stream)))
 
 
 def evis_soft_count_backward(ctx: Context, envs, K: int, tau: float, blend_mode: int,
                              C: torch.Tensor, gC: torch.Tensor, flags: int = 0, stream=None):
-    ctx.check(ctx.lib.evis_soft_count_backward(ctx.handle, envs, len(envs), K, tau, blend_mode, _ptr(C),
-                                               _ptr(gC), flags, _stream(stream)))
+    cp = _ptr(C, "C", torch.float32, min_numel=len(envs))
+    gp = _ptr(gC, "gC", torch.float32, min_numel=len(envs), device=C.device)
+    ctx.check(ctx.lib.evis_soft_count_backward(ctx.handle, envs, len(envs), K, tau, blend_mode, cp,
+                                               gp, flags, _stream(stream)))
 
 
 EVIS_SOFT_HOLD_REF = 1

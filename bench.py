@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=str, default=None, help="WxH, skips the autotuner")
+    ap.add_argument("--tuning-cache", type=str, default=os.path.join(ROOT, "tuning_cache.jsonl"),
+                    help="the autotuner's cache file (empty string: no cache)")
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
     ap.add_argument("--variants", action="store_true",
                     help="timed loop and the variants only (for profilers)")
@@ -204,25 +206,64 @@ def disc_sustained(ctx, steps):
                 events_per_s=round(events / (ms / 1e3), 1), overflow=overflow, tuning=tuning)
 
 
-def cpu_baseline(batch_specs, sample_envs):
-    """The CPU oracle, as it stands, on a bounded sample of the workload:
-    (pixel-substeps done, seconds in the oracle's step, sample names)."""
+def _oracle_pair_task(task):
+    """The oracle on keyframes 0 -> 1 of one env of the sequence: (pixel-
+    substeps, seconds in the oracle's step, name)."""
+    e, H, W, seed = task
     import numpy as np
     from oracle import evis_oracle as o
     from paper_2607_08098_amd import scenes
-    work, secs, names = 0.0, 0.0, []
-    for e in sample_envs:
-        H, W, seed = batch_specs[e]
-        sc = scenes.mixed_env(H, W, seed)
-        L_A = o.log_luminance(sc["I_A"]).astype(np.float32)
-        L_B = o.log_luminance(sc["I_B"]).astype(np.float32)
-        pair = o.Pair(L_A, L_B, sc["m_A"], sc["m_B"], sc["Z_A"], sc["Z_B"], 0, 16667)
-        t0 = time.perf_counter()
-        _, _, _, K = o.step(pair, o.Sensor(C_on=0.2, C_off=0.2, K=0, K_max=64), L_A.copy())
-        secs += time.perf_counter() - t0
-        work += H * W * K
-        names.append(f"env{e}:{W}x{H},K={K}")
-    return work, secs, names
+    seq = scenes.RotatingSequence(H, W, seed)
+    (I0, m0, Z0), (I1, m1, Z1) = seq.keyframe(0), seq.keyframe(1)
+    L0 = o.log_luminance(I0).astype(np.float32)
+    L1 = o.log_luminance(I1).astype(np.float32)
+    pair = o.Pair(L0, L1, m0, m1, Z0, Z1, scenes.frame_time_us(0), scenes.frame_time_us(1))
+    t0 = time.perf_counter()
+    _, _, _, K = o.step(pair, o.Sensor(C_on=0.2, C_off=0.2, K=0, K_max=64), L0.copy(), None, e)
+    return H * W * K, time.perf_counter() - t0, f"env{e}:{W}x{H},K={K}"
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(specs):
+    """The CPU oracle, as it stands, on a bounded sample of the workload
+    (keyframes 0 -> 1 of some envs): one process per env on every core this
+    process may use (at most 16), and one env after another on one core.
+    Runs before anything touches the GPU (the pool forks)."""
+    import multiprocessing as mp
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    small = [e for e, (H, W, _) in enumerate(specs) if H * W <= 640 * 480]
+    # one env per core, half of each of the two smaller classes
+    par = [e for e in small if specs[e][0] == 260][: (cores + 1) // 2]
+    par += [e for e in small if specs[e][0] == 480][: cores - len(par)]
+    tasks = [(e,) + tuple(specs[e]) for e in par]
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_pair_task, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    work = float(sum(r[0] for r in res))
+    single = [_oracle_pair_task((e,) + tuple(specs[e])) for e in (0, 24)]
+    s_work = float(sum(r[0] for r in single))
+    s_secs = sum(r[1] for r in single)
+    model = cpu_model()
+    return dict(value=round(work / 1e6 / wall, 3), unit="Mpix-substeps/s", cores=cores, kind="oracle",
+                cpu_model=model,
+                sample=f"keyframes 0->1 of {len(tasks)} envs ({', '.join(r[2] for r in res)}), "
+                       f"one process per env on {cores} cores of {model}, {wall:.1f}s wall; "
+                       f"pixel-substeps over wall time",
+                single_core=dict(value=round(s_work / 1e6 / s_secs, 3), cores=1,
+                                 sample=f"keyframes 0->1 of {', '.join(r[2] for r in single)}, "
+                                        f"{s_secs:.1f}s in the oracle's step"))
 
 
 def main():
@@ -236,9 +277,16 @@ def main():
               "(environments are independent and would shard by env across GPUs)", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2607_08098_amd import scenes
+    specs = scenes.mixed_batch_specs(3000)
+    cpu = None
+    if not (args.no_cpu_baseline or args.quick or args.variants or args.copy_calibration):
+        cpu = cpu_baseline(specs)          # before anything touches the GPU
+        log(f"cpu oracle: {cpu}")
+
     import numpy as np
     import torch
-    from paper_2607_08098_amd import evis, scenes, workloads
+    from paper_2607_08098_amd import evis, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -247,82 +295,101 @@ def main():
         return
     ctx = evis.Context(0)
     t = time.time()
-    specs = scenes.mixed_batch_specs(3000)
-    batch = workloads.mixed_batch(ctx, specs=specs)
+    W0, S = max(1, args.warmup), args.steps
+    n_kf = W0 + S + 1
+    seq = workloads.MixedSequence(ctx, n_kf, specs=specs)
     sensor = dict(C_on=0.2, C_off=0.2, K=0, K_max=64, refractory_us=0)
-    envs = batch.env_dicts(sensor)
-    arr = evis.env_array(envs)
-    n_envs = len(envs)
+    arrs = [evis.env_array(seq.env_dicts(i, sensor)) for i in range(n_kf - 1)]
+    n_envs = seq.n_envs
+    shapes = np.array(seq.shapes, np.int64)
+    px = shapes[:, 0] * shapes[:, 1]
     torch.cuda.synchronize()
-    log(f"workload ready in {time.time() - t:.1f}s: {n_envs} envs, {batch.n_px} px")
+    log(f"workload ready in {time.time() - t:.1f}s: {n_envs} envs, {seq.n_px} px, {n_kf} keyframes")
 
-    K_used = torch.zeros(n_envs, dtype=torch.int32, device="cuda")
+    K_all = torch.zeros((n_kf - 1, n_envs), dtype=torch.int32, device="cuda")
     out, n_total = evis.event_buffer(1 << 26)
 
-    def step(flags=0):
-        evis.evis_log_luminance(ctx, batch.I_B, 1e-3, out=batch.L_B)
-        evis.evis_step_batch(ctx, arr, out, n_total, K_used, flags)
+    def step(i, flags=0):
+        """Pair (i, i + 1): log intensity of keyframe i + 1 (one launch over
+        every env), then the fused step."""
+        seq.log_keyframe(i + 1)
+        evis.evis_step_batch(ctx, arrs[i], out, n_total, K_all[i], flags)
 
-    tuning = None
+    seq.reset_state(0)
     if args.tile:
         tw, th = (int(v) for v in args.tile.lower().split("x"))
         evis.evis_set_tuning(ctx, tile_w=tw, tile_h=th)
-    elif not args.no_autotune:
-        best, ms = evis.evis_autotune(ctx, arr, out, n_total, reps=3)
+    autotune = None
+    if not args.tile and not args.no_autotune:
+        best, ms, trials, hit = evis.evis_autotune_ex(ctx, arrs[0], out, n_total, reps=3,
+                                                      cache_path=args.tuning_cache or None)
         evis.evis_set_tuning(ctx, **best.as_dict())
-        log(f"autotuned: tile {best.tile_w}x{best.tile_h} ({ms:.3f} ms)")
+        keys = ("tile_w", "tile_h", "grid_mult", "list_cap")
+        autotune = dict(from_cache=hit, cache=os.path.basename(args.tuning_cache) if args.tuning_cache else None,
+                        winner=dict({k: best.as_dict()[k] for k in keys}, ms=round(ms, 4)),
+                        searched=[dict({k: t[k] for k in keys}, ms=round(m, 4)) for t, m in trials])
+        log(f"autotune: {autotune}")
     tuning = evis.evis_get_tuning(ctx).as_dict()
 
-    # warmup (the first step also captures the graph); size the event buffer
-    for _ in range(max(1, args.warmup)):
+    # warmup: pairs 0 .. W0-1 (the first step also captures the graph); size
+    # the event buffer from the largest warmup step
+    per_step = 0
+    for i in range(W0):
         n_total.zero_()
-        step()
-    torch.cuda.synchronize()
-    per_step_events = int(n_total.item())
-    need = per_step_events * args.steps * 5 // 4 + 1024
+        step(i)
+        torch.cuda.synchronize()
+        per_step = max(per_step, int(n_total.item()))
+    need = per_step * S * 3 // 2 + 1024
     if need > out.shape[0]:
         out, n_total = evis.event_buffer(need)
-        for _ in range(2):
-            n_total.zero_()
-            step()
-    Ks = K_used.cpu().numpy().astype(np.int64)
-    shapes = np.array(batch.shapes, np.int64)
-    px = shapes[:, 0] * shapes[:, 1]
-    mpix_substeps = float((px * Ks).sum()) / 1e6
+    R_start = seq.L_ref.clone()      # the state at the start of the timed pairs
 
-    # timed region
+    # timed region: pairs W0 .. W0+S-1 of the sequence
     n_total.zero_()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(args.steps):
-        step()
+    for i in range(W0, W0 + S):
+        step(i)
     e1.record()
     torch.cuda.synchronize()
     ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
+    ms_step = ms_total / S
     events_total = int(n_total.item())
-    value = mpix_substeps / (ms_step / 1e3)
+    overflow = events_total > out.shape[0]
+    Ks = K_all[W0:W0 + S].cpu().numpy().astype(np.int64)          # [S, n_envs]
+    mpix_total = float((px[None, :] * Ks).sum()) / 1e6
+    mpix_substeps = mpix_total / S
+    value = mpix_total / (ms_total / 1e3)
     events_per_s = events_total / (ms_total / 1e3)
     log(f"batched: {ms_step:.3f} ms/step, {value:.0f} Mpix-substeps/s, {events_per_s:.3e} events/s")
     if args.quick and not args.variants:
         print(json.dumps(dict(ms_per_step=ms_step, value=value)))
         return
 
-    roof = None
-    if not args.variants:
-        # the fused tile kernel alone, timed with HIP events on its own stream
+    def replay_timed(fn_step, pairs, kind=evis.EVIS_KERNEL_STEP):
+        """Run fn_step over `pairs` from the timed region's start state with
+        the library's kernel timing on; (mean kernel ms, launches, events)."""
+        seq.L_ref.copy_(R_start)
+        torch.cuda.synchronize()
         evis.evis_profile_enable(ctx, True)
         n_total.zero_()
-        for _ in range(args.steps):
-            step()
+        for i in pairs:
+            fn_step(i)
         torch.cuda.synchronize()
-        tile_ms, launches = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
+        kms, launches = evis.evis_profile_read(ctx, kind)
         evis.evis_profile_enable(ctx, False)
-        tile_ms_avg = tile_ms / max(launches, 1)
-        ev_per_launch = int(n_total.item()) / max(launches, 1)
-        ops = float((px * (OPS_INTERIOR * (Ks - 1) + OPS_LAST)).sum())
+        return kms / max(launches, 1), launches, int(n_total.item())
+
+    timed_pairs = list(range(W0, W0 + S))
+    roof = None
+    if not args.variants:
+        # the fused tile kernel alone, timed with HIP events on its own stream,
+        # over the same pairs from the same state
+        tile_ms_avg, launches, ev = replay_timed(step, timed_pairs)
+        ev_per_launch = ev / max(launches, 1)
+        ops = float((px[None, :] * (OPS_INTERIOR * (Ks - 1) + OPS_LAST)).sum()) / S
         bytes_ = float(px.sum() * BYTES_PER_PX + BYTES_PER_EVENT * ev_per_launch)
         t_alu = ops / (ALU_PEAK_TOPS * 1e12)
         t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
@@ -330,7 +397,8 @@ def main():
         if os.path.exists(TRAFFIC_FILE):
             with open(TRAFFIC_FILE) as fh:
                 tr = json.load(fh)
-            if tr.get("kernel_hash") == kernel_hash() and tr.get("tuning") == [tuning["tile_w"], tuning["tile_h"]]:
+            if tr.get("kernel_hash") == kernel_hash() and tr.get("tuning") == [tuning["tile_w"], tuning["tile_h"]] \
+                    and tr.get("workload") == "mixed64_sequence":
                 traffic = tr.get("bytes_per_launch")
         if t_alu >= t_hbm:
             achieved = ops / (tile_ms_avg / 1e3) / 1e12
@@ -342,13 +410,19 @@ def main():
                         unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
         roof["kernel"] = "k_tile(step)"
         roof["kernel_ms"] = round(tile_ms_avg, 4)
+        roof["ops_per_launch"] = ops
+        roof["algorithmic_bytes_per_launch"] = bytes_
         roof["hbm_algorithmic_GBps"] = round(bytes_ / (tile_ms_avg / 1e3) / 1e9, 1)
         log(f"tile kernel {tile_ms_avg:.3f} ms; roofline {roof}")
 
-    # the two-splat warps, and the gather warp with sensor noise, on the same
-    # batch and tile shape
+    # the two-splat warps, and the gather warp with sensor noise, over the
+    # first pairs of the same sequence and tile shape
     warps = None
-    if args.warp_steps > 0:
+    n_var = max(0, min(args.warp_steps, S))
+    var_pairs = timed_pairs[:n_var]
+    Kv = Ks[:n_var]
+    mpix_var = float((px[None, :] * Kv).sum()) / 1e6 / max(n_var, 1)
+    if n_var > 0:
         warps = {}
         noise = dict(leak_rate_hz=0.1, shot_rate_hz=1.0, hot_rate_hz=100.0, hot_fraction=1e-3,
                      shot_L0=-7.0, shot_inv_range=0.1)
@@ -356,40 +430,37 @@ def main():
                                 None),
                                ("joint", evis.EVIS_WARP_JOINT, None),
                                ("gather_with_noise", evis.EVIS_WARP_GATHER, noise)):
-            wenvs = batch.env_dicts(dict(sensor, blend_mode=mode))
-            if nz is not None:
-                for e, d in enumerate(wenvs):
-                    d["noise"] = dict(nz, seed=9000 + e)
-            warr = evis.env_array(wenvs)
-            for _ in range(2):
-                n_total.zero_()
-                evis.evis_step_batch(ctx, warr, out, n_total, K_used, 0)
-            torch.cuda.synchronize()
-            evis.evis_profile_enable(ctx, True)
-            n_total.zero_()
-            for _ in range(args.warp_steps):
-                evis.evis_step_batch(ctx, warr, out, n_total, K_used, 0)
-            torch.cuda.synchronize()
-            wms, wl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
-            evis.evis_profile_enable(ctx, False)
-            wms /= max(wl, 1)
+            warrs = {}
+            for i in var_pairs:
+                wenvs = seq.env_dicts(i, dict(sensor, blend_mode=mode))
+                if nz is not None:
+                    for e, d in enumerate(wenvs):
+                        d["noise"] = dict(nz, seed=9000 + e, pair_index=i)
+                warrs[i] = evis.env_array(wenvs)
+            wstep = lambda i: evis.evis_step_batch(ctx, warrs[i], out, n_total, None, 0)
+            wstep(var_pairs[0])            # first launch of this kernel
+            wms, wl, wev = replay_timed(wstep, var_pairs)
             if nz is None:
-                wops = float((px * (OPS_INTERIOR_TWO_SPLAT * (Ks - 1) + OPS_LAST)).sum())
+                wops = float((px[None, :] * (OPS_INTERIOR_TWO_SPLAT * (Kv - 1) + OPS_LAST)).sum())
             else:
-                wops = float((px * ((OPS_INTERIOR + OPS_NOISE) * (Ks - 1) + OPS_LAST + OPS_NOISE)).sum())
+                wops = float((px[None, :] * ((OPS_INTERIOR + OPS_NOISE) * (Kv - 1) + OPS_LAST
+                                             + OPS_NOISE)).sum())
+            wops /= n_var
             wach = wops / (wms / 1e3) / 1e12
-            warps[name] = dict(kernel_ms=round(wms, 4), value=round(mpix_substeps / (wms / 1e3), 1),
-                               events_per_step=round(int(n_total.item()) / max(wl, 1), 1),
+            warps[name] = dict(kernel_ms=round(wms, 4), value=round(mpix_var / (wms / 1e3), 1),
+                               events_per_step=round(wev / max(wl, 1), 1),
                                roofline=dict(bound="alu", achieved=round(wach, 3),
                                              peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
                                              frac=round(wach / ALU_PEAK_TOPS, 4)))
             log(f"warp {name}: tile kernel {wms:.3f} ms")
+            del warrs
 
-    # defocus of every env's new keyframe (one batched launch, sigma 0.5 px):
+    # defocus of every env's keyframe 1 (one batched launch, sigma 0.5 px):
     # HBM-bound, 8 algorithmic bytes per pixel (one read, one write)
-    if args.warp_steps > 0:
-        blurred = torch.empty_like(batch.I_B)
-        views = [(batch.view(batch.I_B, e), batch.view(blurred, e)) for e in range(n_envs)]
+    if n_var > 0:
+        src = seq.I[1]
+        blurred = torch.empty_like(src)
+        views = [(seq.view(src, e), seq.view(blurred, e)) for e in range(n_envs)]
 
         def defocus_all():
             evis.evis_defocus_batch(ctx, views, 0.5)
@@ -402,7 +473,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         eager_ms = e0.elapsed_time(e1) / args.warp_steps
-        # the same 64 launches captured once into a HIP graph and replayed
+        # the same launches captured once into a HIP graph and replayed
         gs = torch.cuda.Stream()
         gs.wait_stream(torch.cuda.current_stream())
         graph = torch.cuda.CUDAGraph()
@@ -429,21 +500,23 @@ def main():
         log(f"defocus: {dms:.3f} ms (graph), {eager_ms:.3f} ms (eager) for {n_envs} images, {gbs:.0f} GB/s")
         del blurred, views, graph
 
-    # voxel grid (128 bins per polarity) of one 1280x720 env from one step's
-    # stream: HBM-bound, 8 algorithmic bytes per event read and per voxel
-    # written
-    if args.warp_steps > 0:
+    # voxel grid (128 bins per polarity) of one 1280x720 env from the stream
+    # of the first timed pair: HBM-bound, 8 algorithmic bytes per event read
+    # and per voxel written
+    if n_var > 0:
+        seq.L_ref.copy_(R_start)
         n_total.zero_()
-        step()
+        step(timed_pairs[0])
         torch.cuda.synchronize()
         ve = n_envs - 1
-        vh, vw = batch.shapes[ve]
+        vh, vw = seq.shapes[ve]
+        vt0, vt1 = seq.times(timed_pairs[0])
         grid = torch.empty((2, 128, vh, vw), dtype=torch.float32, device="cuda")
-        evis.evis_voxel_grid(ctx, out, n_total, ve, vh, vw, 0, 16667, 128, out=grid)
+        evis.evis_voxel_grid(ctx, out, n_total, ve, vh, vw, vt0, vt1, 128, out=grid)
         torch.cuda.synchronize()
         e0.record()
         for _ in range(args.warp_steps):
-            evis.evis_voxel_grid(ctx, out, n_total, ve, vh, vw, 0, 16667, 128, out=grid)
+            evis.evis_voxel_grid(ctx, out, n_total, ve, vh, vw, vt0, vt1, 128, out=grid)
         e1.record()
         torch.cuda.synchronize()
         vms = e0.elapsed_time(e1) / args.warp_steps
@@ -458,143 +531,139 @@ def main():
         del grid
 
     # the HBM-bound forms: the event model over materialised frames (one
-    # 1280x720 env, its K + 1 sub-frames written by evis_interpolate first),
-    # and the fused step with small motion (K <= 2, one warped substep)
-    if args.warp_steps > 0:
+    # 1280x720 env, the K + 1 samples of the first timed pair written by
+    # evis_interpolate first), and the fused step with small motion (K <= 2,
+    # one warped substep) over the timed pairs
+    if n_var > 0:
         ve = n_envs - 1
-        vh, vw = batch.shapes[ve]
-        Kv = int(Ks[ve])
-        frames = torch.empty((Kv + 1, vh, vw), dtype=torch.float32, device="cuda")
-        dv = envs[ve]
+        vh, vw = seq.shapes[ve]
+        i0 = timed_pairs[0]
+        Kg = int(Ks[0, ve])
+        frames = torch.empty((Kg + 1, vh, vw), dtype=torch.float32, device="cuda")
+        dv = seq.env_dicts(i0, sensor)[ve]
+        vt0, vt1 = seq.times(i0)
         pair_v = dict(L_A=dv["L_A"], L_B=dv["L_B"], m_A=dv["m_A"], m_B=dv["m_B"], Z_A=dv["Z_A"],
-                      Z_B=dv["Z_B"], t0=0, t1=16667)
-        evis.evis_interpolate(ctx, pair_v, Kv, 0, Kv + 1, evis.EVIS_BLEND_TIME, L_out=frames,
+                      Z_B=dv["Z_B"], t0=vt0, t1=vt1)
+        evis.evis_interpolate(ctx, pair_v, Kg, 0, Kg + 1, evis.EVIS_BLEND_TIME, L_out=frames,
                               want_holes=False)
-        lref = dv["L_ref"].clone()
+        lref = seq.view(R_start, ve).clone()
         st_v = dict(L_ref=lref)
         evis.evis_profile_enable(ctx, True)
         n_total.zero_()
         for _ in range(args.warp_steps):
-            lref.copy_(dv["L_A"])
-            evis.evis_generate_events(ctx, frames, 0, 16667, sensor, st_v, ve, out, n_total, flags=0)
+            lref.copy_(seq.view(R_start, ve))
+            evis.evis_generate_events(ctx, frames, vt0, vt1, sensor, st_v, ve, out, n_total, flags=0)
         torch.cuda.synchronize()
         gms, gl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_EVENTS)
         evis.evis_profile_enable(ctx, False)
         gms /= max(gl, 1)
         gev = int(n_total.item()) / max(gl, 1)
-        gbytes = 4.0 * (Kv + 1) * vh * vw + 8.0 * vh * vw + 8.0 * gev
+        gbytes = 4.0 * (Kg + 1) * vh * vw + 8.0 * vh * vw + 8.0 * gev
         ggbs = gbytes / (gms / 1e3) / 1e9
         warps["generate_events_1280x720"] = dict(
-            kernel_ms=round(gms, 4), K=Kv, events=round(gev),
+            kernel_ms=round(gms, 4), K=Kg, events=round(gev),
             roofline=dict(bound="hbm", achieved=round(ggbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(ggbs / HBM_PEAK_GBS, 4)))
         log(f"generate_events: {gms:.3f} ms, {ggbs:.0f} GB/s")
         del frames
         # small motion (every |m| scaled to at most 1.9 px): the adaptive K is
         # at most 2, the form whose bytes per pixel-substep are largest
-        mmax = float(torch.sqrt((batch.m_A.double() ** 2).sum(1)).max())
-        mmax = max(mmax, float(torch.sqrt((batch.m_B.double() ** 2).sum(1)).max()))
-        s_small = 1.9 / mmax
-        mA_small = (batch.m_A * s_small).contiguous()
-        mB_small = (batch.m_B * s_small).contiguous()
-        k2_envs = batch.env_dicts(dict(sensor))
-        for e, d in enumerate(k2_envs):
-            d["m_A"] = batch.view(mA_small, e)
-            d["m_B"] = batch.view(mB_small, e)
-        k2 = evis.env_array(k2_envs)
-        for _ in range(2):
-            n_total.zero_()
-            evis.evis_step_batch(ctx, k2, out, n_total, K_used, 0)
-        torch.cuda.synchronize()
-        evis.evis_profile_enable(ctx, True)
-        n_total.zero_()
-        for _ in range(args.warp_steps):
-            evis.evis_step_batch(ctx, k2, out, n_total, K_used, 0)
-        torch.cuda.synchronize()
-        kms, kl = evis.evis_profile_read(ctx, evis.EVIS_KERNEL_STEP)
-        evis.evis_profile_enable(ctx, False)
-        kms /= max(kl, 1)
-        kev = int(n_total.item()) / max(kl, 1)
+        mmax = float(torch.sqrt((seq.m.double() ** 2).sum(-1)).max())
+        m_small = (seq.m * (1.9 / mmax)).contiguous()
+        k2arrs = {}
+        for i in var_pairs:
+            ds = seq.env_dicts(i, dict(sensor))
+            for e, d in enumerate(ds):
+                d["m_A"] = seq.view(m_small[i], e)
+                d["m_B"] = seq.view(m_small[i + 1], e)
+            k2arrs[i] = evis.env_array(ds)
+        K2 = torch.zeros(n_envs, dtype=torch.int32, device="cuda")
+        k2step = lambda i: evis.evis_step_batch(ctx, k2arrs[i], out, n_total, K2, 0)
+        k2step(var_pairs[0])
+        kms, kl, kev = replay_timed(k2step, var_pairs)
+        kev /= max(kl, 1)
         kbytes = float(px.sum()) * BYTES_PER_PX + BYTES_PER_EVENT * kev
         kgbs = kbytes / (kms / 1e3) / 1e9
-        kK = K_used.cpu().numpy().astype(np.int64)
+        kK = K2.cpu().numpy().astype(np.int64)
         warps["fused_K2"] = dict(kernel_ms=round(kms, 4), events=round(kev), max_K=int(kK.max()),
                                  mpix_substeps_per_s=round(float((px * kK).sum()) / 1e6 / (kms / 1e3), 1),
                                  roofline=dict(bound="hbm", achieved=round(kgbs, 1), peak=HBM_PEAK_GBS,
                                                unit="GB/s", frac=round(kgbs / HBM_PEAK_GBS, 4)))
         log(f"fused, small motion (K <= 2): {kms:.3f} ms, {kgbs:.0f} GB/s")
-        del mA_small, mB_small
+        del m_small, k2arrs
 
     if args.variants:
         print(json.dumps(dict(ms_per_step=ms_step, value=value, variants=warps)))
         return
 
-    # per-env-launch plain form: every sub-frame to HBM, then the event model
+    # per-env-launch forms over the first timed pairs from the same state:
+    # plain (every sample to HBM, then the event model, env by env) and the
+    # fused step launched env by env
     plain = None
     fused_per_env = None
-    if args.plain_steps > 0:
-        Kmax = int(Ks.max())
+    n_plain = max(0, min(args.plain_steps, S))
+    if n_plain > 0:
+        Kp = Ks[:n_plain]
+        mpix_plain = float((px[None, :] * Kp).sum()) / 1e6
         Hmax_W = int(px.max())
-        L_seq = torch.empty((Kmax + 1) * Hmax_W, dtype=torch.float32, device="cuda")
-        pairs = [dict(L_A=d["L_A"], L_B=d["L_B"], m_A=d["m_A"], m_B=d["m_B"], Z_A=d["Z_A"],
-                      Z_B=d["Z_B"], t0=0, t1=16667) for d in envs]
-        st = [dict(L_ref=d["L_ref"]) for d in envs]
+        L_seq = torch.empty((int(Kp.max()) + 1) * Hmax_W, dtype=torch.float32, device="cuda")
+        st = [dict(L_ref=seq.view(seq.L_ref, e)) for e in range(n_envs)]
 
-        def plain_step():
-            evis.evis_log_luminance(ctx, batch.I_B, 1e-3, out=batch.L_B)
-            for e in range(n_envs):
-                H, W = batch.shapes[e]
-                K = int(Ks[e])
+        def plain_step(i):
+            seq.log_keyframe(i + 1)
+            t0_, t1_ = seq.times(i)
+            for e, d in enumerate(seq.env_dicts(i, sensor)):
+                H, W = seq.shapes[e]
+                K = int(Ks[i - W0, e])
                 Ls = L_seq[: (K + 1) * H * W].view(K + 1, H, W)
-                evis.evis_interpolate(ctx, pairs[e], K, 0, K + 1, evis.EVIS_BLEND_TIME, L_out=Ls,
+                evis.evis_interpolate(ctx, d, K, 0, K + 1, evis.EVIS_BLEND_TIME, L_out=Ls,
                                       want_holes=False)
-                evis.evis_generate_events(ctx, Ls, 0, 16667, sensor, st[e], e, out, n_total, flags=0)
+                evis.evis_generate_events(ctx, Ls, t0_, t1_, sensor, st[e], e, out, n_total, flags=0)
 
-        singles = [evis.env_array([d]) for d in envs]
+        singles = {i: [evis.env_array([d]) for d in seq.env_dicts(i, sensor)]
+                   for i in timed_pairs[:n_plain]}
 
-        def fused_single_step():
-            evis.evis_log_luminance(ctx, batch.I_B, 1e-3, out=batch.L_B)
-            for e in range(n_envs):
-                evis.evis_step_batch(ctx, singles[e], out, n_total, None, 0)
+        def fused_single_step(i):
+            seq.log_keyframe(i + 1)
+            for a in singles[i]:
+                evis.evis_step_batch(ctx, a, out, n_total, None, 0)
 
         res = {}
         for name, fn in (("plain", plain_step), ("fused_per_env", fused_single_step)):
-            fn()
+            seq.L_ref.copy_(R_start)
+            fn(timed_pairs[0])                      # first launches of these shapes
+            seq.L_ref.copy_(R_start)
             n_total.zero_()
             torch.cuda.synchronize()
             e0.record()
-            for _ in range(args.plain_steps):
-                fn()
+            for i in timed_pairs[:n_plain]:
+                fn(i)
             e1.record()
             torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / args.plain_steps
-            res[name] = dict(ms_per_step=round(ms, 3), value=round(mpix_substeps / (ms / 1e3), 1))
+            ms = e0.elapsed_time(e1) / n_plain
+            res[name] = dict(ms_per_step=round(ms, 3), value=round(mpix_plain / n_plain / (ms / 1e3), 1),
+                             pairs=n_plain)
             log(f"{name}: {ms:.3f} ms/step")
         plain, fused_per_env = res["plain"], res["fused_per_env"]
 
     disc = disc_sustained(ctx, args.disc_steps) if args.disc_steps > 0 else None
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        sample = [0, 24]
-        work, secs, names = cpu_baseline(specs, sample)
-        cpu = dict(value=round(work / 1e6 / secs, 4), unit="Mpix-substeps/s", cores=1, kind="oracle",
-                   sample=f"one pair of envs {names} of the 64, {secs:.1f}s in the oracle's step, "
-                          "single-threaded numpy")
-        log(f"cpu oracle: {cpu}")
-
     rec = dict(
         metric="Mpix-substeps/s (64 mixed-res envs, batched persistent launch)",
-        value=round(value, 1), unit="Mpix-substeps/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
+        value=round(value, 1), unit="Mpix-substeps/s", n_gpus=1, steps=S,
+        warmup=W0, ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f32", data="synthetic",
-        config=dict(workload="mixed64: 24x346x260 + 24x640x480 + 16x1280x720 rotating blob scenes, "
-                             "adaptive K<=64, C=0.2", n_envs=n_envs, px_per_step=int(px.sum()),
+        config=dict(workload="mixed64_sequence: 24x346x260 + 24x640x480 + 16x1280x720 rotating blob "
+                             "keyframe sequences at 60 Hz, one new keyframe per step (pairs "
+                             f"{W0}..{W0 + S - 1}, state carried), adaptive K<=64, C=0.2",
+                    n_envs=n_envs, px_per_step=int(px.sum()),
                     mean_K=round(float(Ks.mean()), 2), mpix_substeps_per_step=round(mpix_substeps, 2),
-                    tuning=tuning),
-        events_per_s=round(events_per_s, 1), events_per_step=round(events_total / args.steps, 1),
+                    tuning=tuning, autotune=autotune),
+        events_per_s=round(events_per_s, 1), events_per_step=round(events_total / S, 1),
+        event_buffer_overflow=overflow,
         per_env_plain=plain, per_env_fused=fused_per_env,
         batched_vs_plain=(round(value / plain["value"], 2) if plain else None),
+        batched_vs_fused_per_env=(round(value / fused_per_env["value"], 2) if fused_per_env else None),
         roofline=roof, cpu_baseline=cpu, variants=warps, disc512_sustained=disc,
     )
     print(json.dumps(rec))

@@ -311,12 +311,46 @@ typedef struct {
 int evis_get_tuning(const evis_ctx *ctx, evis_tuning *out);
 int evis_set_tuning(evis_ctx *ctx, const evis_tuning *tuning);
 
-/* Time every tile shape on this batch (reps launches each, states are
- * restored afterwards from a private copy) and keep the fastest in ctx.
- * best (host, nullable) receives it, best_ms (host, nullable) its time. */
+/* Search the launch schedule on this batch and keep the fastest in ctx
+ * (states and *n_total are restored afterwards from a private copy; each
+ * trial times reps launches after one untimed launch).  The search runs
+ * one axis at a time, each from the best point so far:
+ *   1. tile shape, i.e. pixels per thread: 16x16 (1), 32x16 (2), 32x32 (4),
+ *      64x16 (4); one or two pixels per thread are compiled for 4 waves per
+ *      SIMD, four for 2 (64x32, eight per thread at 1 wave, is settable but
+ *      not searched);
+ *   2. grid_mult: the occupancy limit, then one and two workgroups per CU
+ *      fewer;
+ *   3. list_cap: 1024, 512, 256 candidate source blocks per tile.
+ * best (host, nullable) receives the winner, best_ms (host, nullable) its
+ * mean launch time in ms. */
 int evis_autotune(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_event *out,
                   int64_t capacity, int64_t *n_total, int32_t reps, evis_tuning *best,
                   float *best_ms, void *stream);
+
+/* One trial of the schedule search: the tuning and its mean launch time in
+ * ms (negative if the trial failed). */
+typedef struct {
+  evis_tuning tuning;
+  float ms;
+  int32_t reserved;
+} evis_tune_trial;
+
+/* evis_autotune with a cache and the trials reported.  cache_path (host
+ * string, nullable: no cache) names a text file of one JSON object per line,
+ *   {"key": "...", "tile_w": W, "tile_h": H, "grid_mult": G, "list_cap": L, "ms": T}
+ * keyed by the GPU architecture, this library build, the warp mode, the
+ * noise flag, the sorted multiset of env sizes and the pixel-weighted mean
+ * substep count of the batch rounded up to a power of two (measured by one
+ * launch).  A key found there is applied without a search (*from_cache = 1,
+ * no trials); otherwise the search runs and its winner is appended.
+ * trials (host, nullable, max_trials entries) receive the trials in search
+ * order, *n_trials (nullable) their number; from_cache nullable.  The
+ * library opens the file only inside this call. */
+int evis_autotune_ex(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_event *out,
+                     int64_t capacity, int64_t *n_total, int32_t reps, const char *cache_path,
+                     evis_tuning *best, float *best_ms, evis_tune_trial *trials,
+                     int32_t max_trials, int32_t *n_trials, int32_t *from_cache, void *stream);
 
 /* Smooth event-count surrogate and its gradient (a differentiable stand-in
  * for the crossing count of Eq. 4 that lets a contrast threshold and flow

@@ -171,8 +171,13 @@ def _bilinear64(img, sx, sy):
     return top + wy * (bot - top)
 
 
-def _sigmoid(u):
-    return 1.0 / (1.0 + np.exp(-u))
+def _logistic(u):
+    """sigma(u) and sigma'(u) = sigma (1 - sigma) from e = exp(-|u|): the
+    derivative as e / (1 + e)^2, which keeps its digits where sigma is
+    within rounding of 1 (1 - sigma would cancel to 0 beyond |u| ~ 37)."""
+    e = np.exp(-np.abs(u))
+    inv = 1.0 / (1.0 + e)
+    return np.where(u >= 0, inv, e * inv), e * inv * inv
 
 
 def _subframe(LA, LB, mB, j, K, blend_mode, D: Decisions):
@@ -220,11 +225,31 @@ def subframes64(L_A, L_B, m_B, K, blend_mode, D: Decisions):
 
 
 def soft_count(L_A, L_B, m_A, m_B, C, R_traj, K, tau, blend_mode, D: Decisions, want_grad=False,
-               gS=None):
+               gS=None, magnitudes=False, frames32=None):
     """Float64 S (and, with want_grad, the gradient of sum(gS * S) with
     respect to L_A, L_B, m_A, m_B and C) along the decisions D.  R_traj is
     (R_0..R_K, dR_0/dC..dR_K/dC) of reference_levels / reference_levels64;
-    the sub-frames are those of _subframe."""
+    the sub-frames are those of _subframe.
+
+    frames32 (optional): the float32 oracle's sub-frames L_0..L_K; the
+    logistic is then evaluated at those values (the ones a float32
+    evaluation along the same decisions sees) instead of the float64
+    sub-frames, everything else in float64.
+
+    magnitudes (with want_grad): also return, per gradient element ("L_A",
+    "L_B", "m_B", "C") and for S, a bound on the error of a float32
+    evaluation of the same sums along the same decisions and sub-frame
+    values.  Each term is held to 2^-24 (3 |u| + 64) of its absolute value:
+    u = (|L - R| - C) / tau carries about 2^-24 (3 |u| + 10) of absolute
+    error from its three roundings (|L - R| = tau |u| + C), which is the
+    relative error of exp(-|u|) and so of the logistic and its derivative,
+    and 54 more roundings cover the products and sums around it.  The terms
+    that go through B's bilinear weights add the weights' error from the
+    float32 sample position (s = q - g m_B rounded at |s|:
+    2^-23 (|s_x| + |s_y| + 1) per weight), and every element 1e-30 (float32
+    underflow of terms below the normal range).  "abs_C" is the plain sum
+    of the absolute C terms (for an accumulation whose order is not a short
+    tree).  The returned S and gradient are the same either way."""
     LA = np.asarray(L_A, np.float64)
     LB = np.asarray(L_B, np.float64)
     mB = np.asarray(m_B, np.float64)
@@ -236,22 +261,38 @@ def soft_count(L_A, L_B, m_A, m_B, C, R_traj, K, tau, blend_mode, D: Decisions, 
         gLB = np.zeros(H * W)
         gmB = np.zeros((H, W, 2))
         gC = 0.0
+        if magnitudes:
+            aLA, aLB, amB = np.zeros(H * W), np.zeros(H * W), np.zeros((H, W, 2))
+            pLB, pmB = np.zeros(H * W), np.zeros((H, W, 2))      # position terms
+            aC, rC, aS = 0.0, 0.0, np.zeros((H, W))
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
     R_list, dRdC_list = R_traj
     for j in range(1, K + 1):
         R = np.asarray(R_list[j - 1], np.float64)
         dRdC = np.asarray(dRdC_list[j - 1], np.float64)
         L, p = _subframe(LA, LB, mB, j, K, blend_mode, D)
+        if frames32 is not None:
+            L = np.asarray(frames32[j], np.float64)
         dlt = L - R
         u = (np.abs(dlt) - C) / tau
-        sg = _sigmoid(u)
+        sg, sg1 = _logistic(u)
         S += sg
         if not want_grad:
             continue
-        dS = sg * (1.0 - sg) / tau
+        dS = sg1 / tau
         gL = gS * dS * np.sign(dlt)
         gC += float(np.sum(gS * dS * (-np.sign(dlt) * dRdC - 1.0)))
+        if magnitudes:
+            rf = 2.0 ** -24 * (3.0 * np.abs(u) + 64.0)      # relative error of one term
+            tC = np.abs(gS * dS) * (np.abs(dRdC) + 1.0)
+            aC += float(np.sum(tC))
+            rC += float(np.sum(tC * rf))
+            aS += sg * rf
+            aL = np.abs(gL) * rf                              # |gL| held to its error
         if j == K:
             gLB += gL.ravel()
+            if magnitudes:
+                aLB += aL.ravel()
             continue
         alpha, vA, vB, both, win = p["alpha"], p["vA"], p["vB"], p["both"], p["win"]
         wx, wy = p["wx"], p["wy"]
@@ -261,17 +302,43 @@ def soft_count(L_A, L_B, m_A, m_B, C, R_traj, K, tau, blend_mode, D: Decisions, 
         np.add.at(gLA, win[vA], cA[vA])
         gLA += np.where(hole, (1.0 - alpha) * gL, 0.0).ravel()
         gLB += np.where(hole, alpha * gL, 0.0).ravel()
-        for (ty, tx, wgt) in ((p["y0"], p["x0"], (1 - wx) * (1 - wy)), (p["y0"], p["x1"], wx * (1 - wy)),
-                              (p["y1"], p["x0"], (1 - wx) * wy), (p["y1"], p["x1"], wx * wy)):
+        corners = ((p["y0"], p["x0"], (1 - wx) * (1 - wy)), (p["y0"], p["x1"], wx * (1 - wy)),
+                   (p["y1"], p["x0"], (1 - wx) * wy), (p["y1"], p["x1"], wx * wy))
+        for (ty, tx, wgt) in corners:
             np.add.at(gLB, (ty * W + tx)[vB], (cB * wgt)[vB])
         dBdwx = (1 - wy) * (p["b"] - p["a"]) + wy * (p["d"] - p["c"])
         dBdwy = p["bot"] - p["top"]
         gmB[..., 0] += np.where(vB, cB * dBdwx * -p["g"], 0.0)
         gmB[..., 1] += np.where(vB, cB * dBdwy * -p["g"], 0.0)
+        if magnitudes:
+            kA = np.where(both, 1.0 - alpha, np.where(vA, 1.0, 0.0)) * aL
+            kB = np.where(both, alpha, np.where(vA, 0.0, np.where(vB, 1.0, 0.0))) * aL
+            np.add.at(aLA, win[vA], kA[vA])
+            aLA += np.where(hole, (1.0 - alpha) * aL, 0.0).ravel()
+            aLB += np.where(hole, alpha * aL, 0.0).ravel()
+            for (ty, tx, wgt) in corners:
+                np.add.at(aLB, (ty * W + tx)[vB], (kB * wgt)[vB])
+            # the position derivative sums the taps' differences: bound it
+            # by the taps themselves
+            taps = np.abs(p["a"]) + np.abs(p["b"]) + np.abs(p["c"]) + np.abs(p["d"])
+            tapx = (1 - wy) * (np.abs(p["b"]) + np.abs(p["a"])) + wy * (np.abs(p["d"]) + np.abs(p["c"]))
+            tapy = np.abs(p["bot"]) + np.abs(p["top"])
+            amB[..., 0] += np.where(vB, kB * tapx * p["g"], 0.0)
+            amB[..., 1] += np.where(vB, kB * tapy * p["g"], 0.0)
+            # weights from the float32 sample position
+            dw = 2.0 ** -23 * (np.abs(xx - p["g"] * mB[..., 0]) + np.abs(yy - p["g"] * mB[..., 1]) + 1.0)
+            for (ty, tx, _) in corners:
+                np.add.at(pLB, (ty * W + tx)[vB], (2.0 * np.abs(cB) * dw)[vB])
+            pmB[..., 0] += np.where(vB, np.abs(cB) * dw * taps * p["g"], 0.0)
+            pmB[..., 1] += np.where(vB, np.abs(cB) * dw * taps * p["g"], 0.0)
     if not want_grad:
         return S
-    return S, dict(L_A=gLA.reshape(H, W), L_B=gLB.reshape(H, W), m_A=np.zeros((H, W, 2)),
-                   m_B=gmB, C=gC)
+    grads = dict(L_A=gLA.reshape(H, W), L_B=gLB.reshape(H, W), m_A=np.zeros((H, W, 2)), m_B=gmB, C=gC)
+    if magnitudes:
+        fl = 1e-30
+        return S, grads, dict(L_A=aLA.reshape(H, W) + fl, L_B=aLB.reshape(H, W) + pLB.reshape(H, W) + fl,
+                              m_B=amB + pmB + fl, C=rC + fl, S=aS + 2.0 ** -24 * K, abs_C=aC)
+    return S, grads
 
 
 def same_decisions(a: Decisions, b: Decisions) -> np.ndarray:

@@ -36,9 +36,24 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def build_id() -> str:
+    """Hash of every source, the public header and the flags: names this
+    build in the library's tuning-cache keys."""
+    import hashlib
+    h = hashlib.sha256(" ".join(HIP_FLAGS).encode())
+    for name in sorted(os.listdir(CSRC)) + ["evis.h"]:
+        path = os.path.join(INCLUDE if name == "evis.h" else CSRC, name)
+        if os.path.isfile(path) and name.endswith((".h", ".hip", ".cpp")):
+            h.update(name.encode())
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every source to an object, link libevis.so; returns its path."""
     objdir = os.path.join(PKG, "_build")
+    bid = build_id()
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
@@ -48,7 +63,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             continue
         obj = os.path.join(objdir, src + ".o")
         objs.append(obj)
-        cmd = [hipcc(), "-x", "hip", "-c", path, "-o", obj, "-I", INCLUDE, "-I", CSRC] + HIP_FLAGS
+        cmd = [hipcc(), "-x", "hip", "-c", path, "-o", obj, "-I", INCLUDE, "-I", CSRC,
+               f'-DEVIS_BUILD_ID="{bid}"'] + HIP_FLAGS
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

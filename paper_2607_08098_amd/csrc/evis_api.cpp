@@ -29,6 +29,33 @@ struct GraphEntry {
 
 constexpr int kStageSlots = 4;
 
+// Fixed-capacity vector: a call's descriptor plan lives on the stack, so no
+// call allocates host memory for it (the capacity is the ABI's env limit).
+template <typename T, int N>
+struct FixedVec {
+  T v[N];
+  int n = 0;
+  int size() const { return n; }
+  bool empty() const { return n == 0; }
+  void clear() { n = 0; }
+  void push_back(const T& x) { v[n++] = x; }   // callers keep n <= N
+  void assign(int m, const T& x) {
+    n = m;
+    for (int i = 0; i < m; ++i) v[i] = x;
+  }
+  T& operator[](int i) { return v[i]; }
+  const T& operator[](int i) const { return v[i]; }
+  T& back() { return v[n - 1]; }
+  T* data() { return v; }
+  const T* data() const { return v; }
+  const T* begin() const { return v; }
+  const T* end() const { return v + n; }
+};
+
+// Largest descriptor block of one call: EnvDesc per env plus the prefix table.
+constexpr size_t kMetaMax = EVIS_MAX_ENVS * sizeof(EnvDesc) + (EVIS_MAX_ENVS + 1) * sizeof(int32_t);
+using Blob = FixedVec<unsigned char, (int)kMetaMax>;
+
 }  // namespace
 
 struct evis_ctx {
@@ -164,32 +191,38 @@ int ensure_stage(evis_ctx* ctx, size_t bytes) {
 
 // Copy a block of host data to a device buffer unless it already holds it
 // (pinned staging ring; the copy is ordered on stream s).
+// Copy bytes through the next slot of the pinned staging ring to dst on
+// stream s (the slot's previous copy is waited for first).  The ring is
+// allocated at evis_create for any descriptor block; only larger blocks
+// (the surrogate's) make it grow.
+int stage_copy(evis_ctx* ctx, void* dst, const void* data, size_t bytes, hipStream_t s) {
+  int rc = ensure_stage(ctx, bytes);
+  if (rc) return rc;
+  const int slot = ctx->stage_next;
+  ctx->stage_next = (slot + 1) % kStageSlots;
+  EVIS_HIP(hipEventSynchronize(ctx->stage_ev[slot]), "hipEventSynchronize");
+  std::memcpy(ctx->stage[slot], data, bytes);
+  EVIS_HIP(hipMemcpyAsync(dst, ctx->stage[slot], bytes, hipMemcpyHostToDevice, s),
+           "hipMemcpyAsync(descriptors)");
+  EVIS_HIP(hipEventRecord(ctx->stage_ev[slot], s), "hipEventRecord");
+  return EVIS_OK;
+}
+
+// Copy a block of host data to a device buffer unless it already holds it.
 int upload_to(evis_ctx* ctx, DevBuf& dst, std::vector<unsigned char>& shadow,
-              const std::vector<unsigned char>& blob, hipStream_t s, bool* grew_out = nullptr) {
+              const unsigned char* data, size_t bytes, hipStream_t s) {
   bool grew = false;
-  int rc = ensure(ctx, dst, blob.size(), &grew);
+  int rc = ensure(ctx, dst, bytes, &grew);
   if (rc) return rc;
   if (grew) {
     drop_graphs(ctx);
     shadow.clear();
   }
-  if (grew_out) *grew_out = grew;
-  if (shadow == blob) return EVIS_OK;
-  rc = ensure_stage(ctx, blob.size());
+  if (shadow.size() == bytes && std::memcmp(shadow.data(), data, bytes) == 0) return EVIS_OK;
+  rc = stage_copy(ctx, dst.p, data, bytes, s);
   if (rc) return rc;
-  const int slot = ctx->stage_next;
-  ctx->stage_next = (slot + 1) % kStageSlots;
-  EVIS_HIP(hipEventSynchronize(ctx->stage_ev[slot]), "hipEventSynchronize");
-  std::memcpy(ctx->stage[slot], blob.data(), blob.size());
-  EVIS_HIP(hipMemcpyAsync(dst.p, ctx->stage[slot], blob.size(), hipMemcpyHostToDevice, s),
-           "hipMemcpyAsync(descriptors)");
-  EVIS_HIP(hipEventRecord(ctx->stage_ev[slot], s), "hipEventRecord");
-  shadow = blob;
+  shadow.assign(data, data + bytes);
   return EVIS_OK;
-}
-
-int upload_meta(evis_ctx* ctx, const std::vector<unsigned char>& blob, hipStream_t s) {
-  return upload_to(ctx, ctx->meta, ctx->shadow, blob, s);
 }
 
 int check_pair(evis_ctx* ctx, const evis_pair& p, const char* who) {
@@ -306,16 +339,42 @@ size_t sched_head_ints(int n) { return ((size_t)kXcd * (n + 1) + n + kXcd + kQue
 size_t sched_ints(int n) { return sched_head_ints(n) + (size_t)kXcd * kQueueStride; }
 
 struct Plan {
-  std::vector<EnvDesc> desc;
-  std::vector<int32_t> src_prefix;   // n + 1: groups of four source blocks before each env
+  FixedVec<EnvDesc, EVIS_MAX_ENVS> desc;
+  FixedVec<int32_t, EVIS_MAX_ENVS + 1> src_prefix;   // n + 1: groups of four source blocks before each env
   long long px_total = 0;
   int src_total = 0;                 // groups of four source blocks (prep work units)
   int items = 0;
 };
 
-// Lay out per-env scratch (splat records, tile bounds) and the descriptor block.
-int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
-  const int n = (int)pl.desc.size();
+// Where a launch's scratch lives (the context's buffers, or any device
+// memory laid out the same way).
+struct ScratchView {
+  void* meta;        // descriptor block: EnvDesc[n], then int32 src_prefix[n + 1]
+  EnvDyn* dyn;       // [n]
+  int32_t* sched;    // sched_ints(n)
+};
+
+ScratchView ctx_view(evis_ctx* ctx) {
+  return ScratchView{ctx->meta.p, static_cast<EnvDyn*>(ctx->dyn.p), static_cast<int32_t*>(ctx->sched.p)};
+}
+
+// Point every env's splat records and block bounds into src / tb (and B's
+// into srcB / tbB for the two-splat warps), four blocks per group.
+void plan_bind(Plan& pl, float4* src, float4* tb, float4* srcB, float4* tbB) {
+  const bool two = pl.desc.size() > 0 && pl.desc[0].warp != EVIS_WARP_GATHER;   // one warp per plan
+  for (int e = 0; e < pl.desc.size(); ++e) {
+    const long long blk0 = 4LL * pl.src_prefix[e];
+    pl.desc[e].src = src + blk0 * kBlkPx;
+    pl.desc[e].tb = tb + blk0;
+    pl.desc[e].srcB = two ? srcB + blk0 * kBlkPx : nullptr;
+    pl.desc[e].tbB = two ? tbB + blk0 : nullptr;
+    pl.desc[e].src_tile_base = pl.src_prefix[e];
+  }
+}
+
+// Prefix of source-block groups, pixel and work-item totals.
+void plan_layout(Plan& pl, int tw, int th) {
+  const int n = pl.desc.size();
   long long px = 0;
   int src = 0, items = 0;
   pl.src_prefix.assign(n + 1, 0);
@@ -329,6 +388,14 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   pl.px_total = px;
   pl.src_total = src;
   pl.items = items;
+}
+
+// Lay out per-env scratch (splat records, tile bounds) in the context's
+// buffers (grown as needed) and the descriptor block.
+int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
+  const int n = pl.desc.size();
+  plan_layout(pl, tw, th);
+  const int src = pl.src_total;
   bool grew = false;
   // per block: one bounds record and 16 splat records (four blocks per group)
   int rc = ensure(ctx, ctx->src, (size_t)src * 4 * kBlkPx * sizeof(float4), &grew);
@@ -350,23 +417,24 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
     drop_graphs(ctx);
     ctx->shadow.clear();
   }
-  for (int e = 0; e < n; ++e) {
-    const long long blk0 = 4LL * pl.src_prefix[e];
-    pl.desc[e].src = static_cast<float4*>(ctx->src.p) + blk0 * kBlkPx;
-    pl.desc[e].tb = static_cast<float4*>(ctx->tb.p) + blk0;
-    pl.desc[e].srcB = two ? static_cast<float4*>(ctx->srcB.p) + blk0 * kBlkPx : nullptr;
-    pl.desc[e].tbB = two ? static_cast<float4*>(ctx->tbB.p) + blk0 : nullptr;
-    pl.desc[e].src_tile_base = pl.src_prefix[e];
-  }
+  plan_bind(pl, static_cast<float4*>(ctx->src.p), static_cast<float4*>(ctx->tb.p),
+            two ? static_cast<float4*>(ctx->srcB.p) : nullptr,
+            two ? static_cast<float4*>(ctx->tbB.p) : nullptr);
   return EVIS_OK;
 }
 
-std::vector<unsigned char> meta_blob(const Plan& pl) {
+// The descriptor block of a plan.
+void meta_blob(const Plan& pl, Blob& blob) {
   const size_t n = pl.desc.size();
-  std::vector<unsigned char> blob(n * sizeof(EnvDesc) + (n + 1) * sizeof(int32_t));
+  blob.n = (int)(n * sizeof(EnvDesc) + (n + 1) * sizeof(int32_t));
   std::memcpy(blob.data(), pl.desc.data(), n * sizeof(EnvDesc));
   std::memcpy(blob.data() + n * sizeof(EnvDesc), pl.src_prefix.data(), (n + 1) * sizeof(int32_t));
-  return blob;
+}
+
+int upload_meta(evis_ctx* ctx, const Plan& pl, hipStream_t s) {
+  Blob blob;
+  meta_blob(pl, blob);
+  return upload_to(ctx, ctx->meta, ctx->shadow, blob.data(), (size_t)blob.size(), s);
 }
 
 struct Sched {
@@ -376,8 +444,7 @@ struct Sched {
   unsigned int* queue;
 };
 
-Sched sched_ptrs(evis_ctx* ctx, int n) {
-  int32_t* base = static_cast<int32_t*>(ctx->sched.p);
+Sched sched_ptrs(int32_t* base, int n) {
   Sched s;
   s.xbegin = base;                               // kXcd * (n + 1)
   s.env_order = base + kXcd * (n + 1);           // n
@@ -393,14 +460,14 @@ bool plan_has_noise(const Plan& pl) {
 }
 
 // Enqueue reset, prep, queue and the tile kernel for the uploaded plan.
-int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileArgs ta,
-                  int32_t* K_used, unsigned long long* reset_cursor, hipStream_t s) {
-  const int n = (int)pl.desc.size();
-  const EnvDesc* d_desc = static_cast<const EnvDesc*>(ctx->meta.p);
+int enqueue_batch(evis_ctx* ctx, const ScratchView& sv, const Plan& pl, int mode, int tw, int th,
+                  TileArgs ta, int32_t* K_used, unsigned long long* reset_cursor, hipStream_t s) {
+  const int n = pl.desc.size();
+  const EnvDesc* d_desc = static_cast<const EnvDesc*>(sv.meta);
   const int32_t* d_prefix = reinterpret_cast<const int32_t*>(
-      static_cast<const unsigned char*>(ctx->meta.p) + n * sizeof(EnvDesc));
-  EnvDyn* d_dyn = static_cast<EnvDyn*>(ctx->dyn.p);
-  Sched sc = sched_ptrs(ctx, n);
+      static_cast<const unsigned char*>(sv.meta) + n * sizeof(EnvDesc));
+  EnvDyn* d_dyn = sv.dyn;
+  Sched sc = sched_ptrs(sv.sched, n);
   EVIS_HIP(launch_reset(d_dyn, n, sc.queue, reset_cursor, s), "k_reset");
   EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n, pl.src_total, s), "k_prep");
   if (!pl.desc.empty() && pl.desc[0].warp != EVIS_WARP_GATHER)   // one warp per plan
@@ -424,6 +491,74 @@ int enqueue_batch(evis_ctx* ctx, const Plan& pl, int mode, int tw, int th, TileA
     EVIS_HIP(launch_tile(tw, th, mode, warp, noise, ta, grid, s), "k_tile");
   }
   return EVIS_OK;
+}
+
+// Tuning cache: one JSON object per line, {"key": ..., "tile_w": ..., ...};
+// the last line with a key wins.
+#ifndef EVIS_BUILD_ID
+#define EVIS_BUILD_ID "unversioned"
+#endif
+
+std::string tuning_key(evis_ctx* ctx, const Plan& pl, const evis_env* envs, int n_envs,
+                       double mean_k) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == '"' || c == '\\') c = '_';
+  std::map<std::pair<int, int>, int> sizes;
+  for (int e = 0; e < n_envs; ++e) ++sizes[{envs[e].pair.H, envs[e].pair.W}];
+  std::string shapes;
+  for (const auto& kv : sizes) {
+    char b[48];
+    std::snprintf(b, sizeof(b), "%s%dx%d*%d", shapes.empty() ? "" : ",", kv.first.second,
+                  kv.first.first, kv.second);
+    shapes += b;
+  }
+  int kb = 1;
+  while (kb < mean_k && kb < EVIS_MAX_K) kb *= 2;
+  char b[160];
+  std::snprintf(b, sizeof(b), "%s|%s|warp%d|noise%d|K<=%d|", arch.c_str(), EVIS_BUILD_ID,
+                pl.desc.empty() ? 0 : pl.desc[0].warp, plan_has_noise(pl) ? 1 : 0, kb);
+  return std::string(b) + shapes;
+}
+
+bool json_int(const char* line, const char* name, int* v) {
+  const char* p = std::strstr(line, name);
+  return p && std::sscanf(p + std::strlen(name), " : %d", v) == 1;
+}
+
+bool cache_lookup(const char* path, const std::string& key, evis_tuning& t, float& ms) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const std::string want = "\"key\": \"" + key + "\"";
+  char line[1024];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    if (!std::strstr(line, want.c_str())) continue;
+    evis_tuning c = t;
+    double m = 0.0;
+    const char* pm = std::strstr(line, "\"ms\"");
+    if (json_int(line, "\"tile_w\"", &c.tile_w) && json_int(line, "\"tile_h\"", &c.tile_h) &&
+        json_int(line, "\"grid_mult\"", &c.grid_mult) && json_int(line, "\"list_cap\"", &c.list_cap) &&
+        pm && std::sscanf(pm + 4, " : %lf", &m) == 1 && tile_shape_supported(c.tile_w, c.tile_h) &&
+        c.grid_mult >= 0 && c.list_cap >= 1 && c.list_cap <= kListCapMax) {
+      t = c;
+      ms = (float)m;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_store(const char* path, const std::string& key, const evis_tuning& t, float ms) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"tile_w\": %d, \"tile_h\": %d, \"grid_mult\": %d, "
+                  "\"list_cap\": %d, \"ms\": %.4f}\n",
+               key.c_str(), t.tile_w, t.tile_h, t.grid_mult, t.list_cap, (double)ms);
+  std::fclose(f);
 }
 
 }  // namespace
@@ -659,7 +794,7 @@ int evis_interpolate(evis_ctx* ctx, const evis_pair* pair, int32_t K, int32_t j_
   const int tw = 32, th = 32;
   rc = plan_envs(ctx, pl, tw, th);
   if (rc) return rc;
-  rc = upload_meta(ctx, meta_blob(pl), (hipStream_t)stream);
+  rc = upload_meta(ctx, pl, (hipStream_t)stream);
   if (rc) return rc;
   TileArgs ta{};
   ta.list_cap = std::min(std::max(ctx->tuning.list_cap, 1), kListCapMax);
@@ -668,7 +803,8 @@ int evis_interpolate(evis_ctx* ctx, const evis_pair* pair, int32_t K, int32_t j_
   ta.hole = hole_mask;
   ta.j_begin = j_begin;
   ta.j_end = j_end;
-  return enqueue_batch(ctx, pl, MODE_INTERP, tw, th, ta, nullptr, nullptr, (hipStream_t)stream);
+  return enqueue_batch(ctx, ctx_view(ctx), pl, MODE_INTERP, tw, th, ta, nullptr, nullptr,
+                       (hipStream_t)stream);
 }
 
 int evis_generate_events(evis_ctx* ctx, const float* L_seq, int32_t H, int32_t W, int32_t K,
@@ -740,7 +876,6 @@ static int validate_envs(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, Pl
   if (n_envs < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": n_envs must be >= 1");
   if (n_envs > EVIS_MAX_ENVS) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": n_envs > 512");
   pl.desc.clear();
-  pl.desc.reserve(n_envs);
   for (int e = 0; e < n_envs; ++e) {
     const evis_env& v = envs[e];
     int rc = check_pair(ctx, v.pair, who);
@@ -774,7 +909,7 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
   const evis_tuning tu = ctx->tuning;
   int rc = plan_envs(ctx, pl, tu.tile_w, tu.tile_h);
   if (rc) return rc;
-  rc = upload_meta(ctx, meta_blob(pl), s);
+  rc = upload_meta(ctx, pl, s);
   if (rc) return rc;
   TileArgs ta{};
   ta.list_cap = std::min(std::max(tu.list_cap, 1), kListCapMax);
@@ -783,7 +918,8 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
   ta.capacity = capacity;
   ta.cursor = reinterpret_cast<unsigned long long*>(n_total);
   unsigned long long* reset = (flags & EVIS_FLAG_RESET_CURSOR) ? ta.cursor : nullptr;
-  if (!tu.use_graph || ctx->prof) return enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
+  if (!tu.use_graph || ctx->prof)
+    return enqueue_batch(ctx, ctx_view(ctx), pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
 
   char key[256];
   std::snprintf(key, sizeof(key), "%d|%d|%d|%p|%lld|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d", (int)pl.desc.size(),
@@ -797,7 +933,7 @@ static int run_step(evis_ctx* ctx, Plan& pl, evis_event* out, int64_t capacity, 
     GraphEntry g;
     hipStream_t cs = ctx->capture_stream;
     EVIS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    rc = enqueue_batch(ctx, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, cs);
+    rc = enqueue_batch(ctx, ctx_view(ctx), pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, cs);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &graph);
     if (rc) {
@@ -914,7 +1050,7 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   int rc = plan_envs(ctx, pl, kSoftTW, kSoftTH);
   if (rc) return rc;
-  rc = upload_meta(ctx, meta_blob(pl), s);
+  rc = upload_meta(ctx, pl, s);
   if (rc) return rc;
   std::vector<int32_t> item_prefix(n_envs + 1, 0);
   for (int e = 0; e < n_envs; ++e)
@@ -924,13 +1060,13 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
   std::vector<unsigned char> blob(off_ptrs + n_envs * sizeof(SoftPtrs));
   std::memcpy(blob.data(), item_prefix.data(), (n_envs + 1) * sizeof(int32_t));
   std::memcpy(blob.data() + off_ptrs, ptrs.data(), n_envs * sizeof(SoftPtrs));
-  rc = upload_to(ctx, ctx->soft, ctx->soft_shadow, blob, s);
+  rc = upload_to(ctx, ctx->soft, ctx->soft_shadow, blob.data(), blob.size(), s);
   if (rc) return rc;
   const EnvDesc* d_desc = static_cast<const EnvDesc*>(ctx->meta.p);
   const int32_t* d_prefix = reinterpret_cast<const int32_t*>(
       static_cast<const unsigned char*>(ctx->meta.p) + n_envs * sizeof(EnvDesc));
   EnvDyn* d_dyn = static_cast<EnvDyn*>(ctx->dyn.p);
-  Sched sc = sched_ptrs(ctx, n_envs);
+  Sched sc = sched_ptrs(static_cast<int32_t*>(ctx->sched.p), n_envs);
   const SoftPtrs* d_ptrs = reinterpret_cast<const SoftPtrs*>(static_cast<unsigned char*>(ctx->soft.p) + off_ptrs);
   EVIS_HIP(launch_reset(d_dyn, n_envs, sc.queue, nullptr, s), "k_reset");
   EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n_envs, pl.src_total, s), "k_prep");
@@ -985,23 +1121,37 @@ int evis_set_tuning(evis_ctx* ctx, const evis_tuning* t) {
 int evis_autotune(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_event* out,
                   int64_t capacity, int64_t* n_total, int32_t reps, evis_tuning* best,
                   float* best_ms, void* stream) {
+  return evis_autotune_ex(ctx, envs, n_envs, out, capacity, n_total, reps, nullptr, best, best_ms,
+                          nullptr, 0, nullptr, nullptr, stream);
+}
+
+int evis_autotune_ex(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_event* out,
+                     int64_t capacity, int64_t* n_total, int32_t reps, const char* cache_path,
+                     evis_tuning* best, float* best_ms, evis_tune_trial* trials,
+                     int32_t max_trials, int32_t* n_trials, int32_t* from_cache, void* stream) {
   if (!ctx) return EVIS_ERR_INVALID;
+  if (n_trials) *n_trials = 0;
+  if (from_cache) *from_cache = 0;
   Plan pl;
   int rc = validate_envs(ctx, envs, n_envs, pl, "evis_autotune");
   if (rc) return rc;
   rc = check_events_out(ctx, out, capacity, n_total, "evis_autotune");
   if (rc) return rc;
   if (reps < 1) return fail(ctx, EVIS_ERR_INVALID, "evis_autotune: reps must be >= 1");
+  if (max_trials < 0 || (max_trials > 0 && !trials))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_autotune: trials / max_trials");
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  // Private copy of every state so that trial launches leave it untouched.
-  size_t bytes = 8;
+  // Private copy of every state (and of the cursor) so that trial launches
+  // leave them untouched, and room for the substep counts of one launch.
+  size_t bytes = 8 + 4 * (size_t)n_envs;
   for (int e = 0; e < n_envs; ++e) {
     const size_t px = (size_t)envs[e].pair.H * envs[e].pair.W;
     bytes += px * 4 * (envs[e].state.t_last ? 2 : 1);
   }
   void* saved = nullptr;
   EVIS_HIP(hipMalloc(&saved, bytes), "hipMalloc(autotune state copy)");
+  int32_t* d_K = reinterpret_cast<int32_t*>(static_cast<unsigned char*>(saved) + bytes - 4 * (size_t)n_envs);
   auto copy_states = [&](bool save) -> hipError_t {
     unsigned char* p = static_cast<unsigned char*>(saved);
     hipError_t e = save ? hipMemcpyAsync(p, n_total, 8, hipMemcpyDeviceToDevice, s)
@@ -1023,23 +1173,26 @@ int evis_autotune(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_even
     }
     return hipSuccess;
   };
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
   const evis_tuning orig = ctx->tuning;
   evis_tuning winner = orig;
   float winner_ms = 1e30f;
-  const int shapes[5][2] = {{16, 16}, {32, 16}, {32, 32}, {64, 16}, {64, 32}};
-  hipError_t he = copy_states(true);
-  for (int i = 0; i < 5 && he == hipSuccess && rc == EVIS_OK; ++i) {
-    evis_tuning t = orig;
-    t.tile_w = shapes[i][0];
-    t.tile_h = shapes[i][1];
+  int n_done = 0;
+  bool cached = false;
+  std::string key;
+  // Mean launch time of one tuning (the first launch of a shape also
+  // captures its graph and is not timed); negative on failure.
+  auto trial = [&](const evis_tuning& t) -> float {
     ctx->tuning = t;
     float total = 0.0f;
     for (int r = 0; r <= reps && rc == EVIS_OK; ++r) {
-      he = copy_states(false);
-      if (he != hipSuccess) break;
+      hipError_t he = copy_states(false);
+      if (he != hipSuccess) {
+        rc = hip_fail(ctx, he, "evis_autotune state copy");
+        break;
+      }
       hipEventRecord(e0, s);
       Plan p2 = pl;
       rc = run_step(ctx, p2, out, capacity, n_total, nullptr, 0, s);
@@ -1047,24 +1200,94 @@ int evis_autotune(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_even
       hipEventSynchronize(e1);
       float ms = 0.0f;
       hipEventElapsedTime(&ms, e0, e1);
-      if (r > 0) total += ms;   // the first launch of a shape also captures its graph
+      if (r > 0) total += ms;
     }
-    const float avg = total / (float)reps;
+    const float avg = rc == EVIS_OK ? total / (float)reps : -1.0f;
+    if (trials && n_done < max_trials) trials[n_done] = evis_tune_trial{t, avg, 0};
+    ++n_done;
     if (rc == EVIS_OK && avg < winner_ms) {
       winner_ms = avg;
       winner = t;
     }
+    return avg;
+  };
+  hipError_t he = copy_states(true);
+  if (he != hipSuccess) rc = hip_fail(ctx, he, "evis_autotune state copy");
+  // the batch's substep counts, from one launch with the current tuning
+  double mean_k = 1.0;
+  if (rc == EVIS_OK) {
+    Plan p2 = pl;
+    rc = run_step(ctx, p2, out, capacity, n_total, d_K, 0, s);
+    std::vector<int32_t> K(n_envs, 1);
+    if (rc == EVIS_OK) {
+      he = hipMemcpyAsync(K.data(), d_K, 4 * (size_t)n_envs, hipMemcpyDeviceToHost, s);
+      if (he == hipSuccess) he = hipStreamSynchronize(s);
+      if (he != hipSuccess) rc = hip_fail(ctx, he, "evis_autotune K readback");
+    }
+    double wk = 0.0, w = 0.0;
+    for (int e = 0; e < n_envs; ++e) {
+      const double px = (double)envs[e].pair.H * envs[e].pair.W;
+      wk += px * K[e];
+      w += px;
+    }
+    mean_k = w > 0.0 ? wk / w : 1.0;
   }
-  if (he == hipSuccess) he = copy_states(false);
+  if (rc == EVIS_OK && cache_path) {
+    key = tuning_key(ctx, pl, envs, n_envs, mean_k);
+    evis_tuning t = orig;
+    float ms = 0.0f;
+    if (cache_lookup(cache_path, key, t, ms)) {
+      cached = true;
+      winner = t;
+      winner_ms = ms;
+    }
+  }
+  if (rc == EVIS_OK && !cached) {
+    // 1. tile shape (pixels per thread) at the occupancy limit and the full list
+    const int shapes[4][2] = {{16, 16}, {32, 16}, {32, 32}, {64, 16}};
+    for (int i = 0; i < 4 && rc == EVIS_OK; ++i) {
+      evis_tuning t = orig;
+      t.tile_w = shapes[i][0];
+      t.tile_h = shapes[i][1];
+      t.grid_mult = 0;
+      t.list_cap = kListCapMax;
+      trial(t);
+    }
+    // 2. workgroups per CU below the occupancy limit
+    if (rc == EVIS_OK) {
+      const int occ = tile_occupancy(winner.tile_w, winner.tile_h, MODE_STEP, pl.desc[0].warp,
+                                     plan_has_noise(pl));
+      const evis_tuning base = winner;
+      for (int g = occ - 1; g >= std::max(1, occ - 2) && rc == EVIS_OK; --g) {
+        evis_tuning t = base;
+        t.grid_mult = g;
+        trial(t);
+      }
+    }
+    // 3. candidate-list capacity
+    if (rc == EVIS_OK) {
+      const evis_tuning base = winner;
+      for (int cap : {kListCapMax / 2, kListCapMax / 4}) {
+        if (rc != EVIS_OK) break;
+        evis_tuning t = base;
+        t.list_cap = cap;
+        trial(t);
+      }
+    }
+    if (rc == EVIS_OK && cache_path) cache_store(cache_path, key, winner, winner_ms);
+  }
+  he = copy_states(false);
   hipStreamSynchronize(s);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipFree(saved);
   ctx->tuning = (rc == EVIS_OK && he == hipSuccess) ? winner : orig;
-  if (he != hipSuccess) return hip_fail(ctx, he, "evis_autotune state copy");
   if (rc) return rc;
+  if (he != hipSuccess) return hip_fail(ctx, he, "evis_autotune state copy");
   if (best) *best = winner;
   if (best_ms) *best_ms = winner_ms;
+  if (n_trials) *n_trials = n_done;
+  if (from_cache) *from_cache = cached ? 1 : 0;
   return EVIS_OK;
 }
 

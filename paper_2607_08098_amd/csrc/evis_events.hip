@@ -96,6 +96,7 @@ struct EventArgs {
 template <int PPT, int NOISE>
 __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   __shared__ uint2 evbuf[kEventBuf];
+  __shared__ float4 s_cq[kWavesPerBlock * kCrossQ];   // crossing queues (no refractory period)
   __shared__ int s_evn, s_req[4];
   __shared__ unsigned long long s_gbase;
   __shared__ float s_con[kBlock * PPT], s_coff[kBlock * PPT];
@@ -118,7 +119,9 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
     const bool ok = q < plane;
     okbits |= (ok ? 1u : 0u) << k;
     R[k] = ok ? a.Lref[q] : 0.0f;
-    s_tl[i] = (ok && a.tlast) ? a.tlast[q] : EVIS_T_LAST_INIT;
+    // without a refractory period t_last is only written: keep the largest
+    // event time of each pixel (INT_MIN: none)
+    s_tl[i] = (a.refr == 0) ? INT_MIN : ((ok && a.tlast) ? a.tlast[q] : EVIS_T_LAST_INIT);
     if (a.th_on) s_con[i] = ok ? a.th_on[q] : 1.0f;
     if (a.th_off) s_coff[i] = ok ? a.th_off[q] : 1.0f;
     Lp[k] = ok ? a.L_seq[q] : 0.0f;
@@ -131,6 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   uint32_t hotb = 0;
   if constexpr (NOISE != 0) hotb = hot_bits<PPT>(a.noise, aux, okbits);
   SinkRound sr;
+  CrossQueue cq{s_cq};
   sink_init(sh);
   __syncthreads();
   for (int j = 1; j <= a.K; ++j) {
@@ -143,8 +147,12 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
                               ? a.L_seq[(long long)(j + kAhead) * plane + base + tid + k * kBlock]
                               : 0.0f;
     }
-    emit_substep<PPT>(j, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.refr, a.env_bits, sh, so,
-                      sr);
+    if (a.refr == 0)   // uniform
+      emit_queued<PPT>(j, j == a.K, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.env_bits, sh, so,
+                       sr, cq);
+    else
+      emit_substep<PPT>(j, Lj, Lp, R, aux, okbits, a.t0, a.span, a.Dt, a.refr, a.env_bits, sh, so,
+                        sr);
     if constexpr (NOISE != 0)
       emit_noise<PPT>(j, Lj, aux, okbits, hotb, a.noise, a.t0, a.span, a.Dt, a.env_bits, sh, so, sr);
 #pragma unroll
@@ -155,7 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
     if ((okbits >> k) & 1u) {
       const long long q = base + tid + k * kBlock;
       a.Lref[q] = R[k];
-      if (a.tlast) a.tlast[q] = s_tl[tid + k * kBlock];
+      const int tl = s_tl[tid + k * kBlock];
+      if (a.tlast && (a.refr != 0 || tl != INT_MIN)) a.tlast[q] = tl;
     }
   }
   sink_flush(sh, so);

@@ -296,6 +296,166 @@ __device__ __forceinline__ void emit_substep(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Deferred emission (no refractory period): the crossing pixels of each
+// substep are appended to a queue of the wave in LDS, and their events are
+// timed and written when the queue is full and after the last substep, one
+// queue entry per lane.  A substep then costs every pixel only its count
+// and the reference update; the timestamp (a correctly rounded division
+// among other things) runs with nearly every lane busy, instead of once per
+// pixel slot whenever any lane of the wave crosses.  Without a refractory
+// period the crossings of a pixel are independent of each other, so their
+// order does not matter; the pixel's last event time, kept for the next
+// pair, is the largest (times grow with the substep and the crossing), so
+// it is taken with an atomic maximum over an array that starts at INT_MIN
+// for every item (unchanged pixels keep the caller's value).
+// ---------------------------------------------------------------------------
+
+constexpr int kCrossQ = 64;   // queue entries per wave
+
+// Entry: (reference before the substep, previous sample, current sample,
+// pixel index | substep << 11 | polarity << 19).
+struct CrossQueue {
+  float4* q;   // LDS [kWavesPerBlock * kCrossQ]
+  int n = 0;   // entries this wave holds (wave-uniform)
+};
+
+__device__ __forceinline__ void lds_atomic_max(int* p, int idx, int v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __hip_atomic_fetch_max(((__attribute__((address_space(3))) int*)p) + idx, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+#else
+  p[idx] = v > p[idx] ? v : p[idx];
+#endif
+}
+
+// Time and write the events of every queued entry (the wave's lanes take
+// one entry each) and empty the queue.  Wave-level: no barrier.
+__device__ __forceinline__ void cq_drain(CrossQueue& cq, const PixAux& aux, long long t0, int span,
+                                         float Dt, uint32_t env_bits, const SinkShared& sh,
+                                         const SinkOut& so, int slot_req) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool v = lane < cq.n;
+  const float4 e = v ? lds_ld(cq.q, wave * kCrossQ + lane) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  cq.n = 0;
+  const uint32_t meta = __float_as_uint(e.w);
+  const int io = (int)(meta & 0x7FFu), j = (int)((meta >> 11) & 0xFFu);
+  const bool pos = ((meta >> 19) & 1u) != 0u;
+  const float R = e.x, Lp = e.y, Lj = e.z;
+  const float c = aux.c_at(io, pos);
+  int n = 0;
+  if (v) {   // the same count the substep took (same values, same operations)
+    const float a = fabsf(Lj - R);
+    n = (a < c + c) ? 1 : crossing_count(a, c);
+  }
+  const int incl = wave_inclusive_scan(n);
+  const int excl = incl - n;
+  const int wtot = __builtin_amdgcn_readlane(incl, kWave - 1);
+  int lb = 0;
+  if (lane == kWave - 1) lb = atomicAdd(sh.cnt, wtot);
+  lb = __builtin_amdgcn_readlane(lb, kWave - 1);
+  // slots [0, n_lds) of the wave go to the buffer, the rest to the stream
+  const int n_lds = max(0, min(wtot, sh.cap - lb));
+  unsigned long long gbase_w = 0;
+  if (n_lds < wtot) {   // wave-uniform
+    unsigned long long g = 0;
+    if (lane == kWave - 1) g = atomicAdd(so.cursor, (unsigned long long)(wtot - n_lds));
+    gbase_w = __shfl(g, kWave - 1, kWave);
+  }
+  if (lane == kWave - 1 && lb + wtot > sh.cap - sh.cap / 4) lds_st(sh.req, slot_req, 1);
+  auto put = [&](int slot, uint32_t word, int t) {
+    if (slot < n_lds) {
+      lds_st(sh.buf, lb + slot, make_uint2(word, (uint32_t)t));
+    } else {
+      const unsigned long long idx = gbase_w + (unsigned long long)(slot - n_lds);
+      if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
+    }
+  };
+  if (__ballot(n > 4) == 0ull) {   // wave-uniform: few events per entry
+    const uint32_t word = aux.xy_at(io) | ((pos ? 1u : 0u) << 22) | env_bits;
+    int t = 0;
+    for (int kk = 1; kk <= n; ++kk) {
+      t = (int)(t0 + crossing_offset(j, kk, R, c, pos, Lp, Lj, Dt, span));
+      put(excl + kk - 1, word, t);
+    }
+    if (n > 0) lds_atomic_max(aux.tl, io, t);
+  } else {
+    // Expansion: lane l writes events l, l + 64, ... of the wave.  Event s
+    // belongs to the lane whose exclusive prefix is the largest <= s.
+    for (int s = lane; s - lane < wtot; s += kWave) {
+      int o = 0;
+#pragma unroll
+      for (int step = kWave / 2; step >= 1; step >>= 1) {
+        const int ex = __shfl(excl, o + step, kWave);
+        if (ex <= s) o += step;
+      }
+      const int kk = s - __shfl(excl, o, kWave) + 1;
+      const float Ro = __shfl(R, o, kWave), Lpo = __shfl(Lp, o, kWave), Ljo = __shfl(Lj, o, kWave);
+      const float co = __shfl(c, o, kWave);
+      const uint32_t mo = (uint32_t)__shfl((int)meta, o, kWave);
+      const int no = __shfl(n, o, kWave);
+      if (s < wtot) {
+        const int ioo = (int)(mo & 0x7FFu), jo = (int)((mo >> 11) & 0xFFu);
+        const bool po = ((mo >> 19) & 1u) != 0u;
+        const int t = (int)(t0 + crossing_offset(jo, kk, Ro, co, po, Lpo, Ljo, Dt, span));
+        put(s, aux.xy_at(ioo) | ((po ? 1u : 0u) << 22) | env_bits, t);
+        if (kk == no) lds_atomic_max(aux.tl, ioo, t);
+      }
+    }
+  }
+}
+
+// One substep of the event model without a refractory period: counts and
+// reference updates now, the crossing pixels queued (see above); `last`
+// (the pair's final substep) drains the queue.  Every thread of the
+// workgroup must call it, like emit_substep.
+template <int PPT>
+__device__ __forceinline__ void emit_queued(
+    int j, bool last, const float (&Lj)[PPT], const float (&Lp)[PPT], float (&R)[PPT],
+    const PixAux& aux, uint32_t okbits, long long t0, int span, float Dt, uint32_t env_bits,
+    const SinkShared& sh, const SinkOut& so, SinkRound& sr, CrossQueue& cq) {
+  const int tid = threadIdx.x, wave = tid / kWave;
+  if (sr.unchecked >= 2) {
+    __syncthreads();
+    sink_check(sh, so, sr);
+  }
+  const int slot_req = sr.round & 3;
+  ++sr.round;
+  ++sr.unchecked;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    int n = 0;
+    bool pos = false;
+    float c = 0.0f;
+    if ((okbits >> k) & 1u) {
+      const float d = Lj[k] - R[k];
+      pos = d > 0.0f;
+      c = aux.c(k, pos);
+      const float a = fabsf(d);
+      // c <= a < 2c (2c is exact) is one crossing: the common case skips
+      // the general count
+      if (a >= c && c > 0.0f) n = (a < c + c) ? 1 : crossing_count(a, c);
+    }
+    const unsigned long long bal = __ballot(n > 0);
+    if (bal != 0ull) {   // wave-uniform
+      const int cnt = (int)__popcll(bal);
+      if (cq.n + cnt > kCrossQ) cq_drain(cq, aux, t0, span, Dt, env_bits, sh, so, slot_req);
+      if (n > 0) {
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        const uint32_t meta = (uint32_t)(tid + k * kBlock) | ((uint32_t)j << 11) |
+                              ((pos ? 1u : 0u) << 19);
+        lds_st(cq.q, wave * kCrossQ + cq.n + rank, make_float4(R[k], Lp[k], Lj[k], __uint_as_float(meta)));
+        // the reference moves by n*c for every crossing
+        const float nc = (float)n * c;
+        R[k] = pos ? (R[k] + nc) : (R[k] - nc);
+      }
+      cq.n += cnt;
+    }
+  }
+  if (last && cq.n > 0) cq_drain(cq, aux, t0, span, Dt, env_bits, sh, so, slot_req);
+}
+
 __device__ __forceinline__ NoiseCfg noise_cfg(const EnvDesc& d, float Dt) {
   const float dts = Dt * 1e-6f;
   return NoiseCfg{d.leak_hz * dts, d.shot_hz * dts, d.hot_hz * dts, d.shot_L0, d.shot_inv,

@@ -123,11 +123,17 @@ __global__ __launch_bounds__(kBlock) void k_soft(const SoftArgs a) {
       }
       const float dl = L - R[k];
       const float u = (fabsf(dl) - C) * a.inv_tau;
-      const float sg = 1.0f / (1.0f + expf(-u));
+      // sigma(u) and sigma(u) (1 - sigma(u)) from e = exp(-|u|) <= 1, so
+      // that neither loses digits to 1 - sigma when sigma is close to 1:
+      // sigma = 1 / (1 + e) for u >= 0, e / (1 + e) below, and
+      // sigma (1 - sigma) = e / (1 + e)^2 either way
+      const float e = expf(-fabsf(u));
+      const float inv = 1.0f / (1.0f + e);
+      const float sg = (u >= 0.0f) ? inv : e * inv;
       if (!BWD) {
         acc[k] += sg;
       } else {
-        const float dS = sg * (1.0f - sg) * a.inv_tau;
+        const float dS = e * inv * inv * a.inv_tau;
         const float sgn = (dl > 0.0f) ? 1.0f : ((dl < 0.0f) ? -1.0f : 0.0f);
         const float gL = gSq[k] * dS * sgn;
         gCacc -= gSq[k] * dS * (a.hold_ref ? 1.0f : (1.0f + sgn * dRdC[k]));

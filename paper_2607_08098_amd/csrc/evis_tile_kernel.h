@@ -33,8 +33,16 @@ namespace evis {
 //
 // NOISE = 1 (fused step only) adds the sensor-noise events of every env that
 // has noise after each substep's crossings.
+// Waves per SIMD each tile shape is compiled for: with one or two pixels
+// per thread the kernel fits 128 VGPRs (4 waves per SIMD, four workgroups
+// per CU); four pixels per thread need up to 256 (2 waves), eight 1.
+template <int TW, int TH>
+constexpr int tile_waves() {
+  return (TW * TH / kBlock) <= 2 ? 4 : ((TW * TH / kBlock) == 4 ? 2 : 1);
+}
+
 template <int TW, int TH, int MODE, int WARP = EVIS_WARP_GATHER, int NOISE = 0>
-__global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
+__global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const TileArgs a) {
   constexpr int NPX = TW * TH;
   constexpr int PPT = NPX / kBlock;
   static_assert(PPT * kBlock == NPX, "tile must be a multiple of the workgroup");
@@ -43,7 +51,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   // long, paid for by half the event buffer (LDS stays within 4 workgroups
   // per CU for the 32 x 16 tile).
   constexpr int LCAP = kGather ? kListCapMax : 2 * kListCapMax;
-  constexpr int EVB = (MODE == MODE_STEP) ? (kGather ? kEventBuf : kEventBuf / 2) : 1;
+  // The gather warp's crossing queues (4 KB) are paid for by half the
+  // event buffer; the two-splat warps, whose LDS is full, and the noise
+  // path, whose registers are, emit at once.
+  constexpr bool kQueue = MODE == MODE_STEP && kGather && NOISE == 0;
+  constexpr int EVB = (MODE != MODE_STEP) ? 1 : ((kGather && !kQueue) ? kEventBuf : kEventBuf / 2);
+  constexpr int CQN = kQueue ? kWavesPerBlock * kCrossQ : 1;
   constexpr int ZN = zcells<TW, TH>();
   constexpr bool kOwnB = WARP == EVIS_WARP_SPLAT;   // B has z-buffers of its own
   constexpr int NZB = 4;
@@ -51,6 +64,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
   __shared__ uint32_t list[LCAP];
   __shared__ uint32_t s_wl[kWavesPerBlock][kWave];   // per-wave packed active candidates
   __shared__ uint2 evbuf[EVB];
+  __shared__ float4 s_cq[CQN];   // crossing queues of the waves (no refractory period)
   __shared__ int s_evn, s_req[4];
   __shared__ unsigned long long s_gbase;
   __shared__ int s_item, s_rank, s_q, s_lcnt;
@@ -140,7 +154,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
       if (MODE == MODE_STEP) {
         const int i = tid + k * kBlock;
         R[k] = ok ? ldg(d.Lref, qq) : 0.0f;
-        s_tl[i] = (ok && d.tlast) ? ldg(d.tlast, qq) : EVIS_T_LAST_INIT;
+        // without a refractory period t_last is only written: the item
+        // keeps the largest event time of each pixel (INT_MIN: none)
+        s_tl[i] = (kQueue && d.refr == 0)
+                      ? INT_MIN : ((ok && d.tlast) ? ldg(d.tlast, qq) : EVIS_T_LAST_INIT);
         if (d.th_on) s_con[i] = ok ? ldg(d.th_on, qq) : 1.0f;
         if (d.th_off) s_coff[i] = ok ? ldg(d.th_off, qq) : 1.0f;
       }
@@ -215,10 +232,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
     }
 
     // Consumers of a finished sub-frame (substep jj, values Lj, holes hb).
+    CrossQueue cq{s_cq};
     auto consume = [&](int jj, const float (&Lj)[PPT], const uint32_t (&hb)[PPT]) {
       if (MODE == MODE_STEP) {
-        emit_substep<PPT>(jj, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.refr, d.env_bits,
-                          sh, so, sr);
+        if (kQueue && d.refr == 0)   // uniform
+          emit_queued<PPT>(jj, jj == K, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.env_bits,
+                           sh, so, sr, cq);
+        else
+          emit_substep<PPT>(jj, Lj, Lp, R, aux, okbits, d.t0, d.span, dy.Dt, d.refr, d.env_bits,
+                            sh, so, sr);
         if constexpr (NOISE != 0) {
           if (d.noise_on)
             emit_noise<PPT>(jj, Lj, aux, okbits, hotb, ncfg, d.t0, d.span, dy.Dt, d.env_bits, sh,
@@ -407,7 +429,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_tile(const TileArgs a) {
         if ((okbits >> k) & 1u) {
           const int qq = pix_y(k) * W + pix_x(k);
           stg(d.Lref, qq, R[k]);
-          if (d.tlast) stg(d.tlast, qq, s_tl[tid + k * kBlock]);
+          const int tl = s_tl[tid + k * kBlock];
+          if (d.tlast && (!kQueue || d.refr != 0 || tl != INT_MIN)) stg(d.tlast, qq, tl);
         }
       }
     }

@@ -9,17 +9,17 @@
 // the same arithmetic as A's q_A = p - f m_A (the negation is exact, so
 // the position is bit for bit p + g m_B), while the depth is still
 // interpolated at f from A's side (Z_A at p + m_B) to B's (Z_B at p).
+#pragma once
+
+#include "evis_internal.h"
+
+namespace evis {
 
 // Splat direction: A forward, B backward, or A forward with its keys
 // tagged (one z-buffer shared by both splats; a tagged key loses a depth
 // tie to B's).
 enum SplatDir { DIR_A = 0, DIR_B = 1, DIR_A_TAGGED = 2 };
 constexpr uint32_t kATag = 0x80000000u;   // tag bit in the low word of a key
-#pragma once
-
-#include "evis_internal.h"
-
-namespace evis {
 
 // ---------------------------------------------------------------------------
 // candidate source blocks

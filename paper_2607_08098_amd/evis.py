@@ -82,6 +82,10 @@ class EvisTuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class EvisTuneTrial(ctypes.Structure):
+    _fields_ = [("tuning", EvisTuning), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
 # Every symbol include/evis.h declares, with its ctypes signature.
 _VP = ctypes.c_void_p
 SIGNATURES = {
@@ -127,6 +131,12 @@ SIGNATURES = {
     "evis_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
                                      _VP, ctypes.c_int32, ctypes.POINTER(EvisTuning),
                                      ctypes.POINTER(ctypes.c_float), _VP]),
+    "evis_autotune_ex": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP,
+                                        ctypes.c_int64, _VP, ctypes.c_int32, ctypes.c_char_p,
+                                        ctypes.POINTER(EvisTuning), ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(EvisTuneTrial), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                        _VP]),
 }
 
 _lib = None
@@ -490,6 +500,25 @@ def evis_autotune(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, 
     ctx.check(ctx.lib.evis_autotune(ctx.handle, arr, len(arr), op, out.shape[0], npt,
                                     reps, ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
     return best, ms.value
+
+
+def evis_autotune_ex(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor, reps: int = 3,
+                     cache_path: Optional[str] = None, max_trials: int = 32, stream=None):
+    """(best EvisTuning, its ms, [(tuning dict, ms) per trial in search order],
+    from_cache) of the library's schedule search (see include/evis.h)."""
+    arr = envs if isinstance(envs, ctypes.Array) else env_array(envs)
+    best = EvisTuning()
+    ms = ctypes.c_float()
+    trials = (EvisTuneTrial * max_trials)()
+    n_tr = ctypes.c_int32()
+    hit = ctypes.c_int32()
+    op, npt = _events_ptrs(out, n_total)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    ctx.check(ctx.lib.evis_autotune_ex(ctx.handle, arr, len(arr), op, out.shape[0], npt, reps, path,
+                                       ctypes.byref(best), ctypes.byref(ms), trials, max_trials,
+                                       ctypes.byref(n_tr), ctypes.byref(hit), _stream(stream)))
+    got = [(trials[i].tuning.as_dict(), trials[i].ms) for i in range(min(n_tr.value, max_trials))]
+    return best, ms.value, got, bool(hit.value)
 
 
 def soft_env_array(L_A, L_B, m_A, m_B, Z_A, Z_B, L_ref, S=None, gS=None, gL_A=None, gL_B=None,

@@ -140,6 +140,57 @@ def blob_pair(H: int, W: int, seed: int, *, flow: str = "translate",
                 Z_A=Z_A.astype(F32), Z_B=Z_B.astype(F32), omega=omega)
 
 
+class RotatingSequence:
+    """A sequence of keyframes of the rotating blob scene (the benchmark's
+    mixed batch advanced frame by frame).
+
+    Keyframe 0 draws its radiance and depth exactly as ``blob_pair(flow=
+    'rotate')`` draws keyframe A (same seed, same draws in the same order,
+    then omega); keyframe i is that content turned by i * omega / frame_rate
+    rad about the image centre, resampled from keyframe 0 once (bilinear,
+    edge-clamped, float64), so no resampling error accumulates along the
+    sequence.  Each keyframe carries its own backward motion field towards
+    keyframe i - 1: the exact rotation back by one frame plus fresh
+    N(0, noise^2) px noise per keyframe (the renderer's motion-vector error),
+    drawn from PCG64 seeded with (seed, i).  A pair (i, i + 1) uses
+    m_A = keyframe i's field and m_B = keyframe i + 1's.
+    """
+
+    def __init__(self, H: int, W: int, seed: int, frame_rate: float = 60.0, noise: float = 0.3):
+        rng = rng_for(seed)
+        self.H, self.W, self.seed, self.noise = H, W, seed, noise
+        self.base = blob_radiance(H, W, rng)
+        self.Z0 = rng.uniform(0.5, 5.0, size=(H, W))
+        self.omega = float(rng.uniform(0.5, 20.0))
+        self.theta = self.omega / frame_rate
+
+    def _turned(self, img: np.ndarray, angle: float) -> np.ndarray:
+        """img turned by `angle` rad about the centre: out(p) = img(R(-angle)(p - c) + c)."""
+        xx, yy = _grid(self.H, self.W)
+        cx, cy = (self.W - 1) / 2.0, (self.H - 1) / 2.0
+        c, s = math.cos(angle), math.sin(angle)
+        rx, ry = xx - cx, yy - cy
+        return _resample(img, c * rx + s * ry + cx, -s * rx + c * ry + cy)
+
+    def keyframe(self, i: int):
+        """(radiance float32 [H][W], backward motion float32 [H][W][2] towards
+        keyframe i - 1, depth float32 [H][W]) of keyframe i."""
+        a = i * self.theta
+        I = self._turned(self.base, a)
+        Z = self._turned(self.Z0, a)
+        xx, yy = _grid(self.H, self.W)
+        cx, cy = (self.W - 1) / 2.0, (self.H - 1) / 2.0
+        c, s = math.cos(self.theta), math.sin(self.theta)
+        rx, ry = xx - cx, yy - cy
+        m = np.empty((self.H, self.W, 2), np.float64)
+        m[..., 0] = c * rx + s * ry - rx
+        m[..., 1] = -s * rx + c * ry - ry
+        if self.noise > 0:
+            m += np.random.Generator(np.random.PCG64([self.seed, i])).normal(
+                0.0, self.noise, size=(self.H, self.W, 2))
+        return I.astype(F32), m.astype(F32), Z.astype(F32)
+
+
 def mixed_batch_specs(seed_base: int = 3000):
     """The 64-environment mixed-resolution batch: list of (H, W, seed)."""
     out = []
@@ -186,6 +237,35 @@ def disc_scene_params(H: int, W: int, seed: int):
     return dict(albedo=albedo, omega=omega, phase=phase, bg=bg)
 
 
+class DiscScene:
+    """The disc scene of one env with its time-independent parts computed
+    once (pixel angles, disc mask, motion, depth); ``frame(t)`` gives the
+    radiance at time t.  ``disc_frame`` is the one-call form."""
+
+    def __init__(self, H: int, W: int, params: dict, frame_rate: float = 60.0,
+                 irradiance: float = 100.0):
+        self.H, self.W, self.params, self.irradiance = H, W, params, irradiance
+        xx, yy = _grid(H, W)
+        cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+        rad = 0.6 * min(H, W) / 2.0
+        rx, ry = xx - cx, yy - cy
+        self.inside = rx * rx + ry * ry <= rad * rad
+        self.ang0 = np.arctan2(ry, rx)
+        th = -params["omega"] / frame_rate
+        c, s = math.cos(th), math.sin(th)
+        mx = np.where(self.inside, c * rx - s * ry - rx, 0.0)
+        my = np.where(self.inside, s * rx + c * ry - ry, 0.0)
+        self.m = np.stack([mx, my], axis=-1).astype(F32)
+        self.Z = np.where(self.inside, 1.0, 3.0).astype(F32)
+
+    def frame(self, t: float) -> np.ndarray:
+        p = self.params
+        ang = self.ang0 - (p["phase"] + p["omega"] * t)
+        sector = np.floor(np.mod(ang, 2.0 * math.pi) / (2.0 * math.pi / 8.0)).astype(np.int64) % 8
+        img = np.where(self.inside, p["albedo"][sector], p["bg"]) * self.irradiance
+        return img.astype(F32)
+
+
 def disc_frame(H: int, W: int, params: dict, t: float, frame_rate: float = 60.0,
                irradiance: float = 100.0):
     """Radiance, backward MV and depth of the disc scene at time t (seconds).
@@ -194,21 +274,8 @@ def disc_frame(H: int, W: int, params: dict, t: float, frame_rate: float = 60.0,
     rotating at omega rad/s.  Background: static value-noise plane at 3 m.
     The backward MV of a disc pixel rotates it back by omega/frame_rate.
     """
-    xx, yy = _grid(H, W)
-    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
-    rad = 0.6 * min(H, W) / 2.0
-    rx, ry = xx - cx, yy - cy
-    inside = rx * rx + ry * ry <= rad * rad
-    ang = np.arctan2(ry, rx) - (params["phase"] + params["omega"] * t)
-    sector = np.floor(np.mod(ang, 2.0 * math.pi) / (2.0 * math.pi / 8.0)).astype(np.int64) % 8
-    img = np.where(inside, params["albedo"][sector], params["bg"]) * irradiance
-    Z = np.where(inside, 1.0, 3.0)
-    th = -params["omega"] / frame_rate
-    c, s = math.cos(th), math.sin(th)
-    mx = np.where(inside, c * rx - s * ry - rx, 0.0)
-    my = np.where(inside, s * rx + c * ry - ry, 0.0)
-    m = np.stack([mx, my], axis=-1).astype(F32)
-    return img.astype(F32), m, Z.astype(F32)
+    sc = DiscScene(H, W, params, frame_rate, irradiance)
+    return sc.frame(t), sc.m, sc.Z
 
 
 def disc_pair(H: int, W: int, seed: int, step: int = 0, frame_rate: float = 60.0) -> dict:
@@ -397,3 +464,30 @@ class PlaneScene:
         I_A, m_A, Z_A = self.frame(k, k + 1)
         I_B, m_B, Z_B = self.frame(k + 1, k)
         return dict(H=self.H, W=self.W, I_A=I_A, I_B=I_B, m_A=m_A, m_B=m_B, Z_A=Z_A, Z_B=Z_B)
+
+    def keyframe(self, k: int):
+        """Keyframe k with both of its fields, one ray cast: (radiance, the
+        field towards k + 1 (its m_A as keyframe A; None at the last
+        keyframe), the field towards k - 1 (its m_B as keyframe B; None at
+        k = 0), depth), each equal to what frame(k, k + 1) and
+        frame(k, k - 1) return."""
+        idx, uu, vv, Z = self._hit(k)
+        img = np.zeros((self.H, self.W))
+        nxt = [np.zeros((self.H, self.W)), np.zeros((self.H, self.W))]
+        prv = [np.zeros((self.H, self.W)), np.zeros((self.H, self.W))]
+        for i, p in enumerate(self.planes):
+            sel = idx == i
+            if not sel.any():
+                continue
+            n = _perlin2(uu[sel] * p["freq"], vv[sel] * p["freq"], p["perm"])
+            img[sel] = np.clip(0.525 + 0.475 * n, 0.05, 1.0) * p["irr"]
+            if k + 1 < len(self.cam):
+                qx, qy = self._project(i, uu[sel], vv[sel], k + 1)
+                nxt[0][sel], nxt[1][sel] = qx, qy
+            if k > 0:
+                qx, qy = self._project(i, uu[sel], vv[sel], k - 1)
+                prv[0][sel], prv[1][sel] = qx, qy
+        yy, xx = np.mgrid[0:self.H, 0:self.W].astype(np.float64)
+        m_next = np.stack([xx - nxt[0], yy - nxt[1]], -1).astype(F32) if k + 1 < len(self.cam) else None
+        m_prev = np.stack([prv[0] - xx, prv[1] - yy], -1).astype(F32) if k > 0 else None
+        return img.astype(F32), m_next, m_prev, np.where(np.isfinite(Z), Z, 8.0).astype(F32)

@@ -172,3 +172,99 @@ class DiscBatch(Batch):
     def times(self) -> Tuple[int, int]:
         return scenes.frame_time_us(self.frame, self.frame_rate), \
             scenes.frame_time_us(self.frame + 1, self.frame_rate)
+
+
+class MixedSequence:
+    """The 64-environment mixed batch as a sequence of keyframes resident in
+    device memory: keyframe i of env e is ``scenes.RotatingSequence``'s
+    keyframe i (radiance, its own backward motion field, depth), so a step
+    takes the pair (i, i + 1) of every env, at times i / 60 s and
+    (i + 1) / 60 s, and the reference level carries over from one pair to
+    the next as in a rendered sequence.
+
+    Layout: one packed allocation per field and keyframe ([n_kf][n_px] for
+    radiance, log intensity and depth, [n_kf][n_px][2] for motion), so the
+    log front end of one keyframe is one launch over all envs and every
+    env's planes are contiguous views.  Keyframes are generated on the host
+    by a thread pool and copied once; log intensity comes either from
+    ``log_fn`` (a host function: tests feed both sides the same numbers) or
+    from the library's own front end (``log_keyframe``).
+    """
+
+    def __init__(self, ctx: evis.Context, n_keyframes: int, specs=None, device="cuda",
+                 log_fn: Optional[Callable[[np.ndarray], np.ndarray]] = None, threads: int = 16):
+        from concurrent.futures import ThreadPoolExecutor
+        self.ctx = ctx
+        self.specs = specs if specs is not None else scenes.mixed_batch_specs(3000)
+        self.shapes = [(H, W) for H, W, _ in self.specs]
+        self.n_envs = len(self.specs)
+        self.n_kf = int(n_keyframes)
+        self.offsets = [0]
+        for H, W in self.shapes:
+            self.offsets.append(self.offsets[-1] + H * W)
+        n = self.offsets[-1]
+        f32 = dict(dtype=torch.float32, device=device)
+        self.I = torch.empty((self.n_kf, n), **f32)
+        self.L = torch.empty((self.n_kf, n), **f32)
+        self.m = torch.empty((self.n_kf, n, 2), **f32)
+        self.Z = torch.empty((self.n_kf, n), **f32)
+        self.L_ref = torch.empty(n, **f32)
+        self.t_last: Optional[torch.Tensor] = None
+        seqs = [scenes.RotatingSequence(H, W, seed) for H, W, seed in self.specs]
+        self.omega = [s.omega for s in seqs]
+
+        def make(task):
+            e, i = task
+            I, m, Z = seqs[e].keyframe(i)
+            L = log_fn(I).astype(np.float32) if log_fn is not None else None
+            return e, i, I, m, Z, L
+
+        tasks = [(e, i) for i in range(self.n_kf) for e in range(self.n_envs)]
+        with ThreadPoolExecutor(max(1, threads)) as ex:
+            for e, i, I, m, Z, L in ex.map(make, tasks):
+                a, b = self.offsets[e], self.offsets[e + 1]
+                self.I[i, a:b].copy_(torch.from_numpy(I.reshape(-1)))
+                self.m[i, a:b].copy_(torch.from_numpy(m.reshape(-1, 2)))
+                self.Z[i, a:b].copy_(torch.from_numpy(Z.reshape(-1)))
+                if L is not None:
+                    self.L[i, a:b].copy_(torch.from_numpy(L.reshape(-1)))
+        if log_fn is None:
+            for i in range(self.n_kf):
+                self.log_keyframe(i)
+
+    @property
+    def n_px(self) -> int:
+        return self.offsets[-1]
+
+    def view(self, buf: torch.Tensor, e: int) -> torch.Tensor:
+        H, W = self.shapes[e]
+        a, b = self.offsets[e], self.offsets[e + 1]
+        return buf[..., a:b, :].view(H, W, 2) if buf.dim() == 2 and buf.shape[-1] == 2 \
+            else buf[a:b].view(H, W)
+
+    def log_keyframe(self, i: int) -> None:
+        """Log intensity of keyframe i of every env: one launch of the library's a1."""
+        evis.evis_log_luminance(self.ctx, self.I[i], 1e-3, out=self.L[i])
+
+    def reset_state(self, i: int = 0) -> None:
+        """L_ref = keyframe i's log intensity (every env)."""
+        for e in range(self.n_envs):
+            evis.evis_state_init(self.ctx, self.view(self.L[i], e), self.view(self.L_ref, e))
+
+    def times(self, i: int) -> Tuple[int, int]:
+        return scenes.frame_time_us(i), scenes.frame_time_us(i + 1)
+
+    def env_dicts(self, i: int, sensor: dict) -> List[dict]:
+        """Env dicts of the pair (i, i + 1)."""
+        t0, t1 = self.times(i)
+        out = []
+        for e in range(self.n_envs):
+            d = dict(L_A=self.view(self.L[i], e), L_B=self.view(self.L[i + 1], e),
+                     m_A=self.view(self.m[i], e), m_B=self.view(self.m[i + 1], e),
+                     Z_A=self.view(self.Z[i], e), Z_B=self.view(self.Z[i + 1], e),
+                     L_ref=self.view(self.L_ref, e), t0=t0, t1=t1, env_id=e)
+            if self.t_last is not None:
+                d["t_last"] = self.view(self.t_last, e)
+            d.update(sensor)
+            out.append(d)
+        return out

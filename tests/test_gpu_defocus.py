@@ -1,11 +1,18 @@
 """Defocus (separable Gaussian on linear intensity) through the C ABI
-against the float64 oracle.  Bar: the float32 kernel sums 2r + 1 taps per
-pass in order, so each output is within (4 (2r + 1) + 4) 2^-24 max|x| of
-the exact blur (each pass: one rounding per product and per partial sum,
-all partial sums bounded by max|x| since the weights are positive and sum
-to 1; the weights themselves rounded to float32)."""
+against the float64 oracle.  Bar, per output pixel: the float32 kernel sums
+2r + 1 taps per pass in order, so each output is within
+(4 (2r + 1) + 4) 2^-24 M of the exact blur, M the largest |x| in that
+pixel's own (2r + 1) x (2r + 1) window (edge pixels repeated, as the blur
+does): each pass rounds once per product and per partial sum, every
+partial sum of the horizontal pass at a row of the window is bounded by
+the largest |x| of that row's segment and every partial sum of the
+vertical pass by the largest horizontal result in the window, since the
+weights are positive and sum to 1; the weights themselves are rounded to
+float32.  A dark pixel next to bright ones is held to its own window, not
+to the image's maximum."""
 import numpy as np
 import pytest
+from scipy import ndimage
 
 from oracle import evis_oracle as o
 
@@ -32,16 +39,28 @@ def say(*a):
     print("[case]", *a, flush=True)
 
 
+def pixel_bound(x, r):
+    """(4 (2r + 1) + 4) 2^-24 times the largest |x| in each pixel's
+    (2r + 1) x (2r + 1) window, per channel."""
+    a = np.abs(x.astype(np.float64))
+    size = (2 * r + 1, 2 * r + 1) + ((1,) if x.ndim == 3 else ())
+    return (4 * (2 * r + 1) + 4) * 2.0 ** -24 * ndimage.maximum_filter(a, size=size, mode="nearest")
+
+
+def within_bound(got, want, x, r):
+    err = np.abs(got - want)
+    bound = pixel_bound(x, r)
+    worst = np.unravel_index(np.argmax(err - bound), err.shape)
+    return bool(np.all(err <= bound)), (worst, float(err[worst]), float(bound[worst]))
+
+
 def check(torch, ctx, x, sigma):
     from paper_2607_08098_amd import evis
     xd = torch.from_numpy(x).cuda()
     got = evis.evis_defocus(ctx, xd, sigma).cpu().numpy().astype(np.float64)
     want = o.defocus(x.astype(np.float64), sigma)
-    r = o.defocus_radius(sigma)
-    tol = (4 * (2 * r + 1) + 4) * 2.0 ** -24 * float(np.abs(x).max())
-    err = float(np.abs(got - want).max())
-    assert err <= tol, (sigma, x.shape, err, tol)
-    return err
+    ok, info = within_bound(got, want, x, o.defocus_radius(sigma))
+    assert ok, (sigma, x.shape, info)
 
 
 @pytest.mark.parametrize("shape", [(100, 130), (1, 1), (17, 300), (70, 90, 3), (300, 5)])
@@ -82,8 +101,8 @@ def test_defocus_batch(torch, ctx):
         for x, (_, od) in zip(xs, pairs):
             got = od.cpu().numpy().astype(np.float64)
             want = o.defocus(x.astype(np.float64), 1.3)
-            tol = (4 * (2 * r + 1) + 4) * 2.0 ** -24 * float(np.abs(x).max())
-            assert float(np.abs(got - want).max()) <= tol, x.shape
+            ok, info = within_bound(got, want, x, r)
+            assert ok, (x.shape, info)
 
 
 def test_defocus_argument_errors(torch, ctx):

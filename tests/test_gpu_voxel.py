@@ -167,5 +167,6 @@ def test_voxel_grid_errors(torch, ctx):
         with pytest.raises(evis.EvisError) as ei:
             evis.evis_voxel_grid(ctx, out, n, args["env_id"], args["H"], args["W"], args["t0_us"],
                                  args["t1_us"], args["bins"],
-                                 out=torch.empty(2 * 4 * 8 * 8, device="cuda"))
+                                 out=torch.empty(2 * args["bins"] * args["H"] * args["W"],
+                                                 device="cuda"))
         assert ei.value.code in (evis.EVIS_ERR_INVALID, evis.EVIS_ERR_UNSUPPORTED), kw

@@ -294,6 +294,27 @@ int evis_step_batch(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_ev
                     int64_t capacity, int64_t *n_total, int32_t *K_used, int32_t flags,
                     void *stream);
 
+/* evis_step_batch for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, but every scratch buffer of the call (descriptor
+ * block, per-env substep counts, work queues, splat records, block bounds)
+ * sits in one static device array of EVIS_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipFree or pinned host memory (the
+ * descriptor block goes up through the context's staging ring, allocated by
+ * evis_create), and it launches directly (no graph) with the context's
+ * tuning.  Limit: the scratch a batch needs is about 17 bytes per pixel
+ * (34 for the two-splat warps) plus 1 KB per env; a batch that needs more
+ * than the array returns EVIS_ERR_UNSUPPORTED and enqueues nothing (64 MiB
+ * hold about 3.8 M pixels, e.g. four 1280x720 envs).  Every call on one GPU
+ * shares that GPU's array, from any context: calls that overlap on one GPU
+ * (two streams, two threads, two contexts) race and must be serialised by
+ * the caller.  Arguments, errors and results as evis_step_batch. */
+#define EVIS_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int evis_step_batch_noalloc(evis_ctx *ctx, const evis_env *envs, int32_t n_envs, evis_event *out,
+                            int64_t capacity, int64_t *n_total, int32_t *K_used, int32_t flags,
+                            void *stream);
+
 /* Tuning of the fused launch: target tile shape and persistent grid size.
  * tile_w x tile_h in {16x16, 32x16, 32x32, 64x16, 64x32}; grid_mult >= 1
  * workgroups per compute unit (0 = occupancy limit); list_cap in 1..1024

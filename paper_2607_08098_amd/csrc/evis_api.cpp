@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -14,6 +15,13 @@
 #include "evis_internal.h"
 
 using namespace evis;
+
+// Scratch of evis_step_batch_noalloc: device memory the library holds from
+// load to process end (each GPU its own copy), so that entry point allocates
+// nothing.  In host code this name is a host-side stand-in, never a device
+// address: the address comes from hipGetSymbolAddress, once per device, at
+// evis_create (noalloc_scratch_ptr below).
+static __device__ __align__(256) unsigned char scratch[EVIS_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -81,6 +89,8 @@ struct evis_ctx {
   hipEvent_t stage_ev[kStageSlots] = {};
   int stage_next = 0;
   std::vector<unsigned char> shadow;   // what d_meta currently holds
+  // the static scratch of evis_step_batch_noalloc on this context's device
+  unsigned char* noalloc_scratch = nullptr;
   // graphs
   std::map<std::string, GraphEntry> graphs;
   evis_tuning tuning{32, 32, 0, kListCapMax, 1, 1};
@@ -346,8 +356,8 @@ struct Plan {
   int items = 0;
 };
 
-// Where a launch's scratch lives (the context's buffers, or any device
-// memory laid out the same way).
+// Where a launch's scratch lives: the context's buffers, or the static
+// array of evis_step_batch_noalloc.
 struct ScratchView {
   void* meta;        // descriptor block: EnvDesc[n], then int32 src_prefix[n + 1]
   EnvDyn* dyn;       // [n]
@@ -493,6 +503,60 @@ int enqueue_batch(evis_ctx* ctx, const ScratchView& sv, const Plan& pl, int mode
   return EVIS_OK;
 }
 
+// Device address of `scratch` on `device`, taken once per device with that
+// device current (the caller sets it); null if the runtime refuses.
+unsigned char* noalloc_scratch_ptr(int device) {
+  static std::mutex mu;
+  static unsigned char* ptr[64] = {};
+  static bool tried[64] = {};
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!tried[device]) {
+    tried[device] = true;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) ptr[device] = static_cast<unsigned char*>(p);
+  }
+  return ptr[device];
+}
+
+// Carve a launch's scratch out of the static array: descriptor block,
+// EnvDyn, schedule tables, splat records and block bounds (and B's for the
+// two-splat warps), each from a 256-byte boundary.  Fails (nothing
+// enqueued) when the batch needs more than the array holds.
+int plan_static(evis_ctx* ctx, Plan& pl, int tw, int th, ScratchView& sv) {
+  plan_layout(pl, tw, th);
+  const int n = pl.desc.size();
+  const bool two = n > 0 && pl.desc[0].warp != EVIS_WARP_GATHER;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return o;
+  };
+  const size_t o_meta = take(n * sizeof(EnvDesc) + (n + 1) * sizeof(int32_t));
+  const size_t o_dyn = take(n * sizeof(EnvDyn));
+  const size_t o_sched = take(sched_ints(n) * sizeof(int32_t));
+  const size_t rec = (size_t)pl.src_total * 4 * kBlkPx * sizeof(float4);
+  const size_t bnd = (size_t)pl.src_total * 4 * sizeof(float4);
+  const size_t o_src = take(rec), o_tb = take(bnd);
+  const size_t o_srcB = two ? take(rec) : 0, o_tbB = two ? take(bnd) : 0;
+  if (off > (size_t)EVIS_NOALLOC_SCRATCH_BYTES) {
+    char b[200];
+    std::snprintf(b, sizeof(b),
+                  "evis_step_batch_noalloc: this batch needs %zu bytes of scratch, more than the "
+                  "%zu the entry point holds",
+                  off, (size_t)EVIS_NOALLOC_SCRATCH_BYTES);
+    return fail(ctx, EVIS_ERR_UNSUPPORTED, b);
+  }
+  unsigned char* base = ctx->noalloc_scratch;
+  sv = ScratchView{base + o_meta, reinterpret_cast<EnvDyn*>(base + o_dyn),
+                   reinterpret_cast<int32_t*>(base + o_sched)};
+  plan_bind(pl, reinterpret_cast<float4*>(base + o_src), reinterpret_cast<float4*>(base + o_tb),
+            two ? reinterpret_cast<float4*>(base + o_srcB) : nullptr,
+            two ? reinterpret_cast<float4*>(base + o_tbB) : nullptr);
+  return EVIS_OK;
+}
+
 // Tuning cache: one JSON object per line, {"key": ..., "tile_w": ..., ...};
 // the last line with a key wins.
 #ifndef EVIS_BUILD_ID
@@ -582,6 +646,13 @@ int evis_create(evis_ctx** out, int device) {
   if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     delete ctx;
     return EVIS_ERR_HIP;
+  }
+  // set-up for evis_step_batch_noalloc: the static scratch's address on this
+  // device and a staging ring large enough for any descriptor block
+  ctx->noalloc_scratch = noalloc_scratch_ptr(device);
+  if (ensure_stage(ctx, kMetaMax) != EVIS_OK) {
+    evis_destroy(ctx);
+    return EVIS_ERR_NOMEM;
   }
   *out = ctx;
   return EVIS_OK;
@@ -965,6 +1036,41 @@ int evis_step_batch(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_ev
   if (K_used && !aligned(K_used, 4)) return fail(ctx, EVIS_ERR_INVALID, "evis_step_batch: K_used");
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   return run_step(ctx, pl, out, capacity, n_total, K_used, flags, (hipStream_t)stream);
+}
+
+int evis_step_batch_noalloc(evis_ctx* ctx, const evis_env* envs, int32_t n_envs, evis_event* out,
+                            int64_t capacity, int64_t* n_total, int32_t* K_used, int32_t flags,
+                            void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  if (!ctx->noalloc_scratch)
+    return fail(ctx, EVIS_ERR_HIP, "evis_step_batch_noalloc: the static scratch has no device address");
+  Plan pl;
+  int rc = validate_envs(ctx, envs, n_envs, pl, "evis_step_batch_noalloc");
+  if (rc) return rc;
+  rc = check_events_out(ctx, out, capacity, n_total, "evis_step_batch_noalloc");
+  if (rc) return rc;
+  if (K_used && !aligned(K_used, 4))
+    return fail(ctx, EVIS_ERR_INVALID, "evis_step_batch_noalloc: K_used");
+  const evis_tuning tu = ctx->tuning;
+  ScratchView sv{};
+  rc = plan_static(ctx, pl, tu.tile_w, tu.tile_h, sv);
+  if (rc) return rc;
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  // the descriptor block always goes up: other contexts on this device
+  // share the array
+  Blob blob;
+  meta_blob(pl, blob);
+  rc = stage_copy(ctx, sv.meta, blob.data(), (size_t)blob.size(), s);
+  if (rc) return rc;
+  TileArgs ta{};
+  ta.list_cap = std::min(std::max(tu.list_cap, 1), kListCapMax);
+  ta.static_tiles = tu.static_tiles ? 1 : 0;
+  ta.out = out;
+  ta.capacity = capacity;
+  ta.cursor = reinterpret_cast<unsigned long long*>(n_total);
+  unsigned long long* reset = (flags & EVIS_FLAG_RESET_CURSOR) ? ta.cursor : nullptr;
+  return enqueue_batch(ctx, sv, pl, MODE_STEP, tu.tile_w, tu.tile_h, ta, K_used, reset, s);
 }
 
 int evis_profile_enable(evis_ctx* ctx, int32_t enable) {

@@ -118,6 +118,8 @@ SIGNATURES = {
                                                   ctypes.c_int64, _VP, ctypes.c_int32, _VP]),
     "evis_step_batch": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
                                        _VP, _VP, ctypes.c_int32, _VP]),
+    "evis_step_batch_noalloc": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP,
+                                               ctypes.c_int64, _VP, _VP, ctypes.c_int32, _VP]),
     "evis_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
     "evis_set_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(EvisTuning)]),
     "evis_soft_count_forward": (ctypes.c_int, [_VP, ctypes.POINTER(EvisSoftEnv), ctypes.c_int32,
@@ -474,6 +476,18 @@ def evis_step_batch(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor
     kp = _ptr(K_used, "K_used", torch.int32, min_numel=len(arr), device=out.device)
     ctx.check(ctx.lib.evis_step_batch(ctx.handle, arr, len(arr), op, out.shape[0],
                                       npt, kp, flags, _stream(stream)))
+    return n_total
+
+
+def evis_step_batch_noalloc(ctx: Context, envs, out: torch.Tensor, n_total: torch.Tensor,
+                            K_used: Optional[torch.Tensor] = None, flags: int = EVIS_FLAG_RESET_CURSOR,
+                            stream=None):
+    """evis_step_batch with the library's static scratch (allocates nothing)."""
+    arr = envs if isinstance(envs, ctypes.Array) else env_array(envs)
+    op, npt = _events_ptrs(out, n_total)
+    kp = _ptr(K_used, "K_used", torch.int32, min_numel=len(arr), device=out.device)
+    ctx.check(ctx.lib.evis_step_batch_noalloc(ctx.handle, arr, len(arr), op, out.shape[0],
+                                              npt, kp, flags, _stream(stream)))
     return n_total
 
 

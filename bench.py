@@ -134,9 +134,12 @@ def _counter_means(run_dir, counter):
 
 
 def traffic_from(d, tile_label):
-    """HBM traffic of the fused tile kernel per launch: FETCH_SIZE and
-    WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads
-    for a copy of exactly 1 GiB."""
+    """HBM traffic of the fused tile kernel per launch, from rocprofv3 runs in
+    DIR/{rd,write,cal_rd,cal_write}: reads as 32, 64 and 128 bytes times the
+    L2-to-memory read requests of each size (TCC_EA0_RDREQ_{32B,64B,128B}),
+    writes from WRITE_SIZE; the copy of exactly 1 GiB checks both (FETCH_SIZE
+    is not used: its gfx950 formula takes 128-byte reads from TCC_BUBBLE, and
+    counts this part's 128-byte reads as 64 bytes, half of a copy's)."""
     def pick(means, key):
         ks = [k for k in means if key(k)]
         assert ks, f"no dispatch matched in {sorted(means)[:8]}"
@@ -144,19 +147,24 @@ def traffic_from(d, tile_label):
         return ks[0], means[ks[0]]
     is_tile = lambda k: "k_tile<" in k
     is_copy = lambda k: "copy" in k.lower() or "elementwise" in k
-    kf, fetch = pick(_counter_means(os.path.join(d, "fetch"), "FETCH_SIZE"), is_tile)
+
+    def read_bytes(sub, key):
+        n = {c: pick(_counter_means(os.path.join(d, sub), c), key) for c in
+             ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")}
+        kern = n["TCC_EA0_RDREQ_128B_sum"][0]
+        return kern, (32 * n["TCC_EA0_RDREQ_32B_sum"][1] + 64 * n["TCC_EA0_RDREQ_64B_sum"][1]
+                      + 128 * n["TCC_EA0_RDREQ_128B_sum"][1])
+
+    kf, rb = read_bytes("rd", is_tile)
+    _, crb = read_bytes("cal_rd", is_copy)
     kw, write = pick(_counter_means(os.path.join(d, "write"), "WRITE_SIZE"), is_tile)
-    _, cf = pick(_counter_means(os.path.join(d, "cal_fetch"), "FETCH_SIZE"), is_copy)
     _, cw = pick(_counter_means(os.path.join(d, "cal_write"), "WRITE_SIZE"), is_copy)
-    f_fetch = COPY_BYTES / (cf * 1024.0)
-    f_write = COPY_BYTES / (cw * 1024.0)
-    rb, wb = fetch * 1024.0 * f_fetch, write * 1024.0 * f_write
+    wb = write * 1024.0
     tw, th = (int(v) for v in tile_label.lower().split("x"))
-    rec = dict(kernel=kf, kernel_hash=kernel_hash(), tuning=[tw, th],
-               fetch_kib_per_dispatch=round(fetch, 1), write_kib_per_dispatch=round(write, 1),
-               copy_fetch_kib=round(cf, 1), copy_write_kib=round(cw, 1),
-               fetch_factor=round(f_fetch, 4), write_factor=round(f_write, 4),
-               read_bytes=round(rb), write_bytes=round(wb), bytes_per_launch=round(rb + wb))
+    rec = dict(kernel=kf, kernel_hash=kernel_hash(), tuning=[tw, th], workload="mixed64_sequence",
+               read_bytes=round(rb), write_bytes=round(wb), bytes_per_launch=round(rb + wb),
+               copy_read_bytes=round(crb), copy_write_bytes=round(cw * 1024.0),
+               copy_bytes=COPY_BYTES)
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
         fh.write("\n")
@@ -368,10 +376,12 @@ def main():
         print(json.dumps(dict(ms_per_step=ms_step, value=value)))
         return
 
-    def replay_timed(fn_step, pairs, kind=evis.EVIS_KERNEL_STEP):
-        """Run fn_step over `pairs` from the timed region's start state with
-        the library's kernel timing on; (mean kernel ms, launches, events)."""
-        seq.L_ref.copy_(R_start)
+    def replay_timed(fn_step, pairs, kind=evis.EVIS_KERNEL_STEP, state=None):
+        """Run fn_step over `pairs` from the timed region's start state (or
+        state = (L_ref, start)) with the library's kernel timing on; (mean
+        kernel ms, launches, events)."""
+        lref, start = state if state is not None else (seq.L_ref, R_start)
+        lref.copy_(start)
         torch.cuda.synchronize()
         evis.evis_profile_enable(ctx, True)
         n_total.zero_()
@@ -566,21 +576,50 @@ def main():
                           frac=round(ggbs / HBM_PEAK_GBS, 4)))
         log(f"generate_events: {gms:.3f} ms, {ggbs:.0f} GB/s")
         del frames
-        # small motion (every |m| scaled to at most 1.9 px): the adaptive K is
-        # at most 2, the form whose bytes per pixel-substep are largest
-        mmax = float(torch.sqrt((seq.m.double() ** 2).sum(-1)).max())
-        m_small = (seq.m * (1.9 / mmax)).contiguous()
-        k2arrs = {}
-        for i in var_pairs:
-            ds = seq.env_dicts(i, dict(sensor))
-            for e, d in enumerate(ds):
-                d["m_A"] = seq.view(m_small[i], e)
-                d["m_B"] = seq.view(m_small[i + 1], e)
-            k2arrs[i] = evis.env_array(ds)
+        # the same form over every env's samples of that pair in one launch
+        # (evis_generate_events_batch): Σ 4 (K + 1) px bytes of samples, the
+        # reference read and written, 8 B per event
+        Kp = Ks[0]
+        offs = np.concatenate([[0], np.cumsum((Kp + 1) * px)])
+        allf = torch.empty(int(offs[-1]), dtype=torch.float32, device="cuda")
+        dicts = seq.env_dicts(i0, sensor)
+        items = []
+        for e, d in enumerate(dicts):
+            H, W = seq.shapes[e]
+            fr = allf[int(offs[e]):int(offs[e + 1])].view(int(Kp[e]) + 1, H, W)
+            evis.evis_interpolate(ctx, d, int(Kp[e]), 0, int(Kp[e]) + 1, evis.EVIS_BLEND_TIME,
+                                  L_out=fr, want_holes=False)
+            items.append(dict(L_seq=fr, t0=vt0, t1=vt1, env_id=e, C_on=0.2, C_off=0.2,
+                              L_ref=seq.view(seq.L_ref, e)))
+        def bstep(i):   # every repetition from the same state (outside the kernel's timing)
+            seq.L_ref.copy_(R_start)
+            evis.evis_generate_events_batch(ctx, items, out, n_total, flags=0)
+        bstep(i0)
+        bms, bl, bev = replay_timed(bstep, [i0] * args.warp_steps, kind=evis.EVIS_KERNEL_EVENTS)
+        bev /= max(bl, 1)
+        bbytes = 4.0 * float(offs[-1]) + 8.0 * float(px.sum()) + 8.0 * bev
+        bgbs = bbytes / (bms / 1e3) / 1e9
+        warps["generate_events_batch64"] = dict(
+            kernel_ms=round(bms, 4), samples_GB=round(4.0 * float(offs[-1]) / 1e9, 3),
+            events=round(bev),
+            roofline=dict(bound="hbm", achieved=round(bgbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(bgbs / HBM_PEAK_GBS, 4)))
+        log(f"generate_events batch of 64: {bms:.3f} ms, {bgbs:.0f} GB/s")
+        del allf, items
+        # small motion: the same scenes turned by at most 1 px per keyframe
+        # at the image corners, motion noise N(0, 0.15^2) px, so the
+        # adaptive K is at most 2 (the form whose bytes per pixel-substep
+        # are largest), content and motion vectors agreeing
+        small = workloads.MixedSequence(
+            ctx, n_var + 1, specs=specs,
+            seq_kw=lambda e, H, W: dict(noise=0.15, theta=1.0 / np.hypot((W - 1) / 2, (H - 1) / 2)))
+        small.reset_state(0)
+        k2arrs = {W0 + i: evis.env_array(small.env_dicts(i, dict(sensor))) for i in range(n_var)}
         K2 = torch.zeros(n_envs, dtype=torch.int32, device="cuda")
         k2step = lambda i: evis.evis_step_batch(ctx, k2arrs[i], out, n_total, K2, 0)
         k2step(var_pairs[0])
-        kms, kl, kev = replay_timed(k2step, var_pairs)
+        small.reset_state(0)
+        kms, kl, kev = replay_timed(k2step, var_pairs, state=(small.L_ref, small.L_ref.clone()))
         kev /= max(kl, 1)
         kbytes = float(px.sum()) * BYTES_PER_PX + BYTES_PER_EVENT * kev
         kgbs = kbytes / (kms / 1e3) / 1e9
@@ -590,7 +629,7 @@ def main():
                                  roofline=dict(bound="hbm", achieved=round(kgbs, 1), peak=HBM_PEAK_GBS,
                                                unit="GB/s", frac=round(kgbs / HBM_PEAK_GBS, 4)))
         log(f"fused, small motion (K <= 2): {kms:.3f} ms, {kgbs:.0f} GB/s")
-        del m_small, k2arrs
+        del small, k2arrs
 
     if args.variants:
         print(json.dumps(dict(ms_per_step=ms_step, value=value, variants=warps)))

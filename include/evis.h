@@ -276,6 +276,27 @@ int evis_generate_events_noise(evis_ctx *ctx, const float *L_seq, int32_t H, int
                                evis_event *out, int64_t capacity, int64_t *n_total,
                                int32_t flags, void *stream);
 
+/* One env of a batch of the event model on caller frames: its samples
+ * L_seq[0..K] ([K+1][H*W], device), times, sensor (C_on, C_off, theta_*,
+ * refractory_us; K, K_max and blend_mode ignored), state and env id. */
+typedef struct {
+  const float *L_seq;
+  int32_t H, W, K;
+  int32_t env_id;
+  int64_t t0_us, t1_us;
+  evis_sensor sensor;
+  evis_state state;
+} evis_frames;
+
+/* evis_generate_events for n_envs envs (1..EVIS_MAX_ENVS; envs is a HOST
+ * array) in one launch: the same events, states and limits as one call per
+ * env, all appended to one stream (Eq. 4, Eq. 8 and the refractory period
+ * as above; no sensor noise).  Host-detected errors in any env enqueue
+ * nothing. */
+int evis_generate_events_batch(evis_ctx *ctx, const evis_frames *envs, int32_t n_envs,
+                               evis_event *out, int64_t capacity, int64_t *n_total, int32_t flags,
+                               void *stream);
+
 /* Fused step -- one keyframe pair for each of n_envs environments
  * (1..EVIS_MAX_ENVS; envs is a HOST array of descriptors) in one
  * persistent launch: substep count, sub-frames and events of every env,

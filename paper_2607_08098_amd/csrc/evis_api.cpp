@@ -82,6 +82,7 @@ struct evis_ctx {
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
   DevBuf voxmax;      // per-plane maxima of evis_voxel_grid
+  DevBuf evb;         // evis_generate_events_batch: EventArgs[n], then int32 prefix[n + 1]
   std::vector<unsigned char> soft_shadow;
   // host staging of the descriptor block (pinned ring)
   void* stage[kStageSlots] = {};
@@ -668,8 +669,8 @@ void evis_destroy(evis_ctx* ctx) {
     hipEventDestroy(r.e1);
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
-  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn,  &ctx->sched, &ctx->src, &ctx->tb,
-                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft, &ctx->voxmax};
+  DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->src,    &ctx->tb,
+                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft,   &ctx->voxmax, &ctx->evb};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {
@@ -938,6 +939,72 @@ int evis_generate_events_noise(evis_ctx* ctx, const float* L_seq, int32_t H, int
                          (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0, noisy ? &nc : nullptr,
                          (hipStream_t)stream),
            "k_events");
+  return EVIS_OK;
+}
+
+int evis_generate_events_batch(evis_ctx* ctx, const evis_frames* envs, int32_t n_envs,
+                               evis_event* out, int64_t capacity, int64_t* n_total, int32_t flags,
+                               void* stream) {
+  if (!ctx) return EVIS_ERR_INVALID;
+  const char* who = "evis_generate_events_batch";
+  if (!envs) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": null envs");
+  if (n_envs < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": n_envs must be >= 1");
+  if (n_envs > EVIS_MAX_ENVS) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": n_envs > 512");
+  int rc = check_events_out(ctx, out, capacity, n_total, who);
+  if (rc) return rc;
+  std::vector<EventArgs> descs(n_envs);
+  std::vector<int32_t> prefix(n_envs + 1, 0);
+  long long blocks = 0;
+  for (int e = 0; e < n_envs; ++e) {
+    const evis_frames& v = envs[e];
+    if (!v.L_seq || !aligned(v.L_seq, 4)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": L_seq");
+    if (v.H < 1 || v.W < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": H, W");
+    if (v.H > EVIS_MAX_DIM || v.W > EVIS_MAX_DIM)
+      return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": H, W > 2047");
+    if (v.K < 1) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": K must be >= 1");
+    if (v.K > EVIS_MAX_K) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": K > 128");
+    rc = check_times(ctx, v.t0_us, v.t1_us, who);
+    if (rc) return rc;
+    rc = check_sensor(ctx, v.sensor, who, false);
+    if (rc) return rc;
+    if (!v.state.L_ref || !aligned(v.state.L_ref, 4))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": state.L_ref");
+    if (v.sensor.refractory_us > 0 && !v.state.t_last)
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": refractory period needs state.t_last");
+    if (v.state.t_last && !aligned(v.state.t_last, 4))
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": state.t_last");
+    if (v.env_id < 0 || v.env_id >= EVIS_MAX_ENVS)
+      return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": env_id");
+    const int span = (int)(v.t1_us - v.t0_us);
+    descs[e] = EventArgs{v.L_seq, v.H, v.W, v.K, v.t0_us, span, (float)span / (float)v.K,
+                         v.sensor.C_on, v.sensor.C_off, v.sensor.theta_on, v.sensor.theta_off,
+                         v.sensor.refractory_us, (uint32_t)v.env_id << 23, v.state.L_ref,
+                         v.state.t_last, out, capacity, reinterpret_cast<unsigned long long*>(n_total),
+                         NoiseCfg{}};
+    prefix[e] = (int32_t)blocks;
+    blocks += events_batch_blocks((long long)v.H * v.W);
+  }
+  if (blocks > 0x7FFFFFFFLL) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": batch too large");
+  prefix[n_envs] = (int32_t)blocks;
+  EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t off_prefix = ((size_t)n_envs * sizeof(EventArgs) + 255) & ~(size_t)255;
+  std::vector<unsigned char> blob(off_prefix + (n_envs + 1) * sizeof(int32_t));
+  std::memcpy(blob.data(), descs.data(), (size_t)n_envs * sizeof(EventArgs));
+  std::memcpy(blob.data() + off_prefix, prefix.data(), (n_envs + 1) * sizeof(int32_t));
+  rc = ensure(ctx, ctx->evb, blob.size());
+  if (rc) return rc;
+  rc = stage_copy(ctx, ctx->evb.p, blob.data(), blob.size(), s);
+  if (rc) return rc;
+  const EventArgs* d_descs = static_cast<const EventArgs*>(ctx->evb.p);
+  const int32_t* d_prefix =
+      reinterpret_cast<const int32_t*>(static_cast<unsigned char*>(ctx->evb.p) + off_prefix);
+  ProfScope ps(ctx, EVIS_KERNEL_EVENTS, s);
+  EVIS_HIP(launch_events_batch(d_descs, d_prefix, n_envs, (int)blocks,
+                               (flags & EVIS_FLAG_RESET_CURSOR)
+                                   ? reinterpret_cast<unsigned long long*>(n_total) : nullptr,
+                               s),
+           "k_events_batch");
   return EVIS_OK;
 }
 

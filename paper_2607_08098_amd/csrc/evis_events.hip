@@ -74,27 +74,11 @@ __global__ void k_zero_u64(unsigned long long* p) {
 // Events over materialised frames: PPT pixels per thread, consecutive pixels
 // across the workgroup, one pass over the K+1 frames with the state in
 // registers and the next frame's values loaded ahead.
-struct EventArgs {
-  const float* L_seq;
-  int H, W, K;
-  long long t0;
-  int span;
-  float Dt;
-  float C_on, C_off;
-  const float* th_on;
-  const float* th_off;
-  int refr;
-  uint32_t env_bits;
-  float* Lref;
-  int32_t* tlast;
-  evis_event* out;
-  long long capacity;
-  unsigned long long* cursor;
-  NoiseCfg noise;   // used by the NOISE instantiation only
-};
 
-template <int PPT, int NOISE>
-__global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
+// The event model over the kBlock * PPT consecutive pixels from `base` of
+// one env's frames (every thread of the workgroup calls it).
+template <int PPT, int NOISE, int AHEAD = 4>
+__device__ __forceinline__ void events_block(const EventArgs& a, long long base) {
   __shared__ uint2 evbuf[kEventBuf];
   __shared__ float4 s_cq[kWavesPerBlock * kCrossQ];   // crossing queues (no refractory period)
   __shared__ int s_evn, s_req[4];
@@ -105,11 +89,10 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
   const SinkOut so{a.out, a.capacity, a.cursor};
   const int tid = threadIdx.x;
   const long long plane = (long long)a.H * a.W;
-  const long long base = (long long)blockIdx.x * (kBlock * PPT);
   // Frames are read kAhead substeps ahead of their use (a ring of registers
   // shifted by one each substep), so that enough loads are in flight to keep
   // HBM busy: the substep loop is otherwise one dependent load per step.
-  constexpr int kAhead = 4;
+  constexpr int kAhead = AHEAD;
   float R[PPT], Lp[PPT], Lj[PPT], Ln[kAhead][PPT];
   uint32_t okbits = 0;
 #pragma unroll
@@ -168,6 +151,28 @@ __global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
     }
   }
   sink_flush(sh, so);
+}
+
+template <int PPT, int NOISE>
+__global__ __launch_bounds__(kBlock) void k_events(const EventArgs a) {
+  events_block<PPT, NOISE>(a, (long long)blockIdx.x * (kBlock * PPT));
+}
+
+// Many envs' frames in one launch: workgroup b works on env e, the last
+// whose first workgroup prefix[e] is <= b (descriptors and prefix in device
+// memory, read through the scalar cache).
+template <int PPT, int AHEAD>
+__global__ __launch_bounds__(kBlock) void k_events_batch(const EventArgs* __restrict__ descs,
+                                                         const int32_t* __restrict__ prefix,
+                                                         int n_envs) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n_envs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const EventArgs a = descs[lo];
+  events_block<PPT, 0, AHEAD>(a, (long long)(b - prefix[lo]) * (kBlock * PPT));
 }
 
 // Defocus: one workgroup per 64 x 32 output tile of one channel of one
@@ -317,6 +322,19 @@ hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, 
   } else {
     hipLaunchKernelGGL((k_events<1, 0>), dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+constexpr int kEventsBatchPPT = 2;
+constexpr int kEventsBatchAhead = 4;
+
+int events_batch_blocks(long long px) { return grid_for(px, kBlock * kEventsBatchPPT); }
+
+hipError_t launch_events_batch(const EventArgs* descs, const int32_t* prefix, int n_envs,
+                               int total_blocks, unsigned long long* reset_cursor, hipStream_t s) {
+  if (reset_cursor) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, reset_cursor);
+  hipLaunchKernelGGL((k_events_batch<kEventsBatchPPT, kEventsBatchAhead>), dim3(total_blocks), dim3(kBlock), 0, s, descs,
+                     prefix, n_envs);
   return hipGetLastError();
 }
 

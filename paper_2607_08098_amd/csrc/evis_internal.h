@@ -148,6 +148,33 @@ hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, 
                          int32_t* t_last, evis_event* out, long long capacity,
                          unsigned long long* cursor, int reset_cursor,
                          const NoiseCfg* noise /* host copy, or null: no noise */, hipStream_t s);
+// The event model over caller frames (k_events): one env's arguments; the
+// batched form (k_events_batch) reads an array of them from device memory.
+struct EventArgs {
+  const float* L_seq;
+  int H, W, K;
+  long long t0;
+  int span;
+  float Dt;
+  float C_on, C_off;
+  const float* th_on;
+  const float* th_off;
+  int refr;
+  uint32_t env_bits;
+  float* Lref;
+  int32_t* tlast;
+  evis_event* out;
+  long long capacity;
+  unsigned long long* cursor;
+  NoiseCfg noise;   // used by the NOISE instantiation only
+};
+
+// Workgroups of one env in a batched event-model launch, and the launch
+// (descs / prefix: device arrays of n_envs descriptors and n_envs + 1
+// workgroup offsets).
+int events_batch_blocks(long long px);
+hipError_t launch_events_batch(const EventArgs* descs, const int32_t* prefix, int n_envs,
+                               int total_blocks, unsigned long long* reset_cursor, hipStream_t s);
 hipError_t launch_substep_count(const float2* mA, const float2* mB, long long n, int K_max,
                                 unsigned long long* msq_scratch, int32_t* K_out, hipStream_t s);
 

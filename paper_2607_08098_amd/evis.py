@@ -61,6 +61,12 @@ class EvisNoise(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class EvisFrames(ctypes.Structure):
+    _fields_ = [("L_seq", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("env_id", ctypes.c_int32), ("t0_us", ctypes.c_int64),
+                ("t1_us", ctypes.c_int64), ("sensor", EvisSensor), ("state", EvisState)]
+
+
 class EvisEnv(ctypes.Structure):
     _fields_ = [("pair", EvisPair), ("sensor", EvisSensor), ("state", EvisState),
                 ("env_id", ctypes.c_int32), ("crop_margin", ctypes.c_int32),
@@ -115,6 +121,8 @@ SIGNATURES = {
                                                   ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                                   ctypes.POINTER(EvisSensor), ctypes.POINTER(EvisState),
                                                   ctypes.c_int32, ctypes.POINTER(EvisNoise), _VP,
+                                                  ctypes.c_int64, _VP, ctypes.c_int32, _VP]),
+    "evis_generate_events_batch": (ctypes.c_int, [_VP, ctypes.POINTER(EvisFrames), ctypes.c_int32, _VP,
                                                   ctypes.c_int64, _VP, ctypes.c_int32, _VP]),
     "evis_step_batch": (ctypes.c_int, [_VP, ctypes.POINTER(EvisEnv), ctypes.c_int32, _VP, ctypes.c_int64,
                                        _VP, _VP, ctypes.c_int32, _VP]),
@@ -455,6 +463,26 @@ def evis_generate_events(ctx: Context, L_seq: torch.Tensor, t0: int, t1: int, se
                                                      env_id, ctypes.byref(nz), op,
                                                      out.shape[0], npt, flags,
                                                      _stream(stream)))
+    return n_total
+
+
+def evis_generate_events_batch(ctx: Context, items: Sequence[dict], out: torch.Tensor,
+                               n_total: torch.Tensor, flags: int = EVIS_FLAG_RESET_CURSOR, stream=None):
+    """items: dicts with L_seq ([K + 1, H, W] float32), t0, t1, env_id, the
+    sensor keys of make_sensor and the state keys of make_state."""
+    arr = (EvisFrames * len(items))()
+    for i, d in enumerate(items):
+        L_seq = d["L_seq"]
+        if not isinstance(L_seq, torch.Tensor) or L_seq.dim() != 3:
+            raise ValueError(f"items[{i}].L_seq: expected float32 samples of shape [K + 1, H, W]")
+        H, W = _hw(L_seq, "L_seq")
+        dev = L_seq.device
+        arr[i] = EvisFrames(_ptr(L_seq, "L_seq", torch.float32), H, W, L_seq.shape[0] - 1,
+                            int(d.get("env_id", i)), int(d.get("t0", 0)), int(d.get("t1", 16667)),
+                            make_sensor(d, H, W, dev), make_state(d, H, W, dev))
+    op, npt = _events_ptrs(out, n_total)
+    ctx.check(ctx.lib.evis_generate_events_batch(ctx.handle, arr, len(arr), op, out.shape[0], npt,
+                                                 flags, _stream(stream)))
     return n_total
 
 

@@ -156,13 +156,15 @@ class RotatingSequence:
     m_A = keyframe i's field and m_B = keyframe i + 1's.
     """
 
-    def __init__(self, H: int, W: int, seed: int, frame_rate: float = 60.0, noise: float = 0.3):
+    def __init__(self, H: int, W: int, seed: int, frame_rate: float = 60.0, noise: float = 0.3,
+                 theta: float | None = None):
         rng = rng_for(seed)
         self.H, self.W, self.seed, self.noise = H, W, seed, noise
         self.base = blob_radiance(H, W, rng)
         self.Z0 = rng.uniform(0.5, 5.0, size=(H, W))
         self.omega = float(rng.uniform(0.5, 20.0))
-        self.theta = self.omega / frame_rate
+        # theta: the turn per keyframe (rad); by default omega / frame_rate
+        self.theta = self.omega / frame_rate if theta is None else float(theta)
 
     def _turned(self, img: np.ndarray, angle: float) -> np.ndarray:
         """img turned by `angle` rad about the centre: out(p) = img(R(-angle)(p - c) + c)."""

@@ -192,7 +192,9 @@ class MixedSequence:
     """
 
     def __init__(self, ctx: evis.Context, n_keyframes: int, specs=None, device="cuda",
-                 log_fn: Optional[Callable[[np.ndarray], np.ndarray]] = None, threads: int = 16):
+                 log_fn: Optional[Callable[[np.ndarray], np.ndarray]] = None, threads: int = 16,
+                 seq_kw: Optional[Callable[[int, int, int], dict]] = None):
+        """seq_kw(e, H, W) (optional): extra RotatingSequence arguments of env e."""
         from concurrent.futures import ThreadPoolExecutor
         self.ctx = ctx
         self.specs = specs if specs is not None else scenes.mixed_batch_specs(3000)
@@ -210,7 +212,8 @@ class MixedSequence:
         self.Z = torch.empty((self.n_kf, n), **f32)
         self.L_ref = torch.empty(n, **f32)
         self.t_last: Optional[torch.Tensor] = None
-        seqs = [scenes.RotatingSequence(H, W, seed) for H, W, seed in self.specs]
+        seqs = [scenes.RotatingSequence(H, W, seed, **(seq_kw(e, H, W) if seq_kw else {}))
+                for e, (H, W, seed) in enumerate(self.specs)]
         self.omega = [s.omega for s in seqs]
 
         def make(task):

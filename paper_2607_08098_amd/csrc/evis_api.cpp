@@ -82,7 +82,8 @@ struct evis_ctx {
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
   DevBuf voxmax;      // per-plane maxima of evis_voxel_grid
-  DevBuf evb;         // evis_generate_events_batch: EventArgs[n], then int32 prefix[n + 1]
+  DevBuf evb;         // evis_generate_events_batch: EventArgs[n], then two int32 prefixes
+  DevBuf evs;         // the sharded event stream of the wave-form event model
   std::vector<unsigned char> soft_shadow;
   // host staging of the descriptor block (pinned ring)
   void* stage[kStageSlots] = {};
@@ -178,6 +179,16 @@ void drop_graphs(evis_ctx* ctx) {
     if (kv.second.graph) hipGraphDestroy(kv.second.graph);
   }
   ctx->graphs.clear();
+}
+
+// The sharded stream state of a wave-form event-model call writing to an
+// output of `capacity` events (grown as needed, never shrunk).
+int stream_state(evis_ctx* ctx, long long capacity, StreamState* st) {
+  const size_t bytes = stream_state_layout(capacity, nullptr, nullptr);
+  const int rc = ensure(ctx, ctx->evs, bytes);
+  if (rc) return rc;
+  stream_state_layout(capacity, ctx->evs.p, st);
+  return EVIS_OK;
 }
 
 int ensure_stage(evis_ctx* ctx, size_t bytes) {
@@ -670,7 +681,7 @@ void evis_destroy(evis_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->src,    &ctx->tb,
-                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft,   &ctx->voxmax, &ctx->evb};
+                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft,   &ctx->voxmax, &ctx->evb, &ctx->evs};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {
@@ -931,14 +942,23 @@ int evis_generate_events_noise(evis_ctx* ctx, const float* L_seq, int32_t H, int
                   (uint32_t)(noise->seed & 0xFFFFFFFFull), (uint32_t)(noise->seed >> 32),
                   noise->pair_index};
   }
-  ProfScope ps(ctx, EVIS_KERNEL_EVENTS, (hipStream_t)stream);
+  const bool wave = events_wave_form(sensor->refractory_us, noisy);
+  StreamState st{};
+  if (wave) {
+    rc = stream_state(ctx, capacity, &st);
+    if (rc) return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* cursor = reinterpret_cast<unsigned long long*>(n_total);
+  const int reset = (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0;
+  ProfScope ps(ctx, EVIS_KERNEL_EVENTS, s);
+  if (wave) EVIS_HIP(launch_stream_init(st, cursor, reset, capacity, s), "k_stream_init");
   EVIS_HIP(launch_events(L_seq, H, W, K, t0_us, span, Dt, sensor->C_on, sensor->C_off,
                          sensor->theta_on, sensor->theta_off, sensor->refractory_us,
                          (uint32_t)env_id << 23, state->L_ref, state->t_last, out, capacity,
-                         reinterpret_cast<unsigned long long*>(n_total),
-                         (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0, noisy ? &nc : nullptr,
-                         (hipStream_t)stream),
+                         cursor, reset, noisy ? &nc : nullptr, st, s),
            "k_events");
+  if (wave) EVIS_HIP(launch_stream_fixup(st, out, capacity, cursor, s), "k_stream_fixup");
   return EVIS_OK;
 }
 
@@ -952,9 +972,11 @@ int evis_generate_events_batch(evis_ctx* ctx, const evis_frames* envs, int32_t n
   if (n_envs > EVIS_MAX_ENVS) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": n_envs > 512");
   int rc = check_events_out(ctx, out, capacity, n_total, who);
   if (rc) return rc;
-  std::vector<EventArgs> descs(n_envs);
-  std::vector<int32_t> prefix(n_envs + 1, 0);
-  long long blocks = 0;
+  // Envs without a refractory period go to the wave form, the others to
+  // the workgroup form: two launches, each over its own descriptors.
+  std::vector<EventArgs> descs;
+  std::vector<EventArgs> descs_refr;
+  descs.reserve(n_envs);
   for (int e = 0; e < n_envs; ++e) {
     const evis_frames& v = envs[e];
     if (!v.L_seq || !aligned(v.L_seq, 4)) return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": L_seq");
@@ -976,22 +998,36 @@ int evis_generate_events_batch(evis_ctx* ctx, const evis_frames* envs, int32_t n
     if (v.env_id < 0 || v.env_id >= EVIS_MAX_ENVS)
       return fail(ctx, EVIS_ERR_INVALID, std::string(who) + ": env_id");
     const int span = (int)(v.t1_us - v.t0_us);
-    descs[e] = EventArgs{v.L_seq, v.H, v.W, v.K, v.t0_us, span, (float)span / (float)v.K,
-                         v.sensor.C_on, v.sensor.C_off, v.sensor.theta_on, v.sensor.theta_off,
-                         v.sensor.refractory_us, (uint32_t)v.env_id << 23, v.state.L_ref,
-                         v.state.t_last, out, capacity, reinterpret_cast<unsigned long long*>(n_total),
-                         NoiseCfg{}};
-    prefix[e] = (int32_t)blocks;
-    blocks += events_batch_blocks((long long)v.H * v.W);
+    const EventArgs a{v.L_seq, v.H, v.W, v.K, v.t0_us, span, (float)span / (float)v.K,
+                      v.sensor.C_on, v.sensor.C_off, v.sensor.theta_on, v.sensor.theta_off,
+                      v.sensor.refractory_us, (uint32_t)v.env_id << 23, v.state.L_ref,
+                      v.state.t_last, out, capacity, reinterpret_cast<unsigned long long*>(n_total),
+                      NoiseCfg{}};
+    (v.sensor.refractory_us > 0 ? descs_refr : descs).push_back(a);
   }
-  if (blocks > 0x7FFFFFFFLL) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": batch too large");
-  prefix[n_envs] = (int32_t)blocks;
+  const int n_wave = (int)descs.size(), n_refr = (int)descs_refr.size();
+  descs.insert(descs.end(), descs_refr.begin(), descs_refr.end());
+  // prefix of each group: [n_wave + 1] then [n_refr + 1]
+  std::vector<int32_t> prefix;
+  prefix.reserve(n_envs + 2);
+  long long blocks_wave = 0, blocks_refr = 0;
+  for (int g = 0; g < 2; ++g) {
+    long long blocks = 0;
+    const int b0 = g == 0 ? 0 : n_wave, b1 = g == 0 ? n_wave : n_envs;
+    for (int e = b0; e < b1; ++e) {
+      prefix.push_back((int32_t)blocks);
+      blocks += events_batch_blocks((long long)descs[e].H * descs[e].W);
+      if (blocks > 0x7FFFFFFFLL) return fail(ctx, EVIS_ERR_UNSUPPORTED, std::string(who) + ": batch too large");
+    }
+    prefix.push_back((int32_t)blocks);
+    (g == 0 ? blocks_wave : blocks_refr) = blocks;
+  }
   EVIS_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const size_t off_prefix = ((size_t)n_envs * sizeof(EventArgs) + 255) & ~(size_t)255;
-  std::vector<unsigned char> blob(off_prefix + (n_envs + 1) * sizeof(int32_t));
+  std::vector<unsigned char> blob(off_prefix + prefix.size() * sizeof(int32_t));
   std::memcpy(blob.data(), descs.data(), (size_t)n_envs * sizeof(EventArgs));
-  std::memcpy(blob.data() + off_prefix, prefix.data(), (n_envs + 1) * sizeof(int32_t));
+  std::memcpy(blob.data() + off_prefix, prefix.data(), prefix.size() * sizeof(int32_t));
   rc = ensure(ctx, ctx->evb, blob.size());
   if (rc) return rc;
   rc = stage_copy(ctx, ctx->evb.p, blob.data(), blob.size(), s);
@@ -999,11 +1035,26 @@ int evis_generate_events_batch(evis_ctx* ctx, const evis_frames* envs, int32_t n
   const EventArgs* d_descs = static_cast<const EventArgs*>(ctx->evb.p);
   const int32_t* d_prefix =
       reinterpret_cast<const int32_t*>(static_cast<unsigned char*>(ctx->evb.p) + off_prefix);
+  StreamState st{};
+  if (n_wave > 0) {
+    rc = stream_state(ctx, capacity, &st);
+    if (rc) return rc;
+  }
+  unsigned long long* cursor = reinterpret_cast<unsigned long long*>(n_total);
+  const int reset = (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0;
   ProfScope ps(ctx, EVIS_KERNEL_EVENTS, s);
-  EVIS_HIP(launch_events_batch(d_descs, d_prefix, n_envs, (int)blocks,
-                               (flags & EVIS_FLAG_RESET_CURSOR)
-                                   ? reinterpret_cast<unsigned long long*>(n_total) : nullptr,
-                               s),
+  // the wave form through the sharded stream (which leaves the cursor at
+  // its end), then the workgroup form at the cursor
+  if (n_wave > 0) {
+    EVIS_HIP(launch_stream_init(st, cursor, reset, capacity, s), "k_stream_init");
+    EVIS_HIP(launch_events_batch(d_descs, d_prefix, n_wave, (int)blocks_wave, true, st, s),
+             "k_events_batch_wave");
+    EVIS_HIP(launch_stream_fixup(st, out, capacity, cursor, s), "k_stream_fixup");
+  } else if (reset) {
+    EVIS_HIP(launch_zero_u64(cursor, s), "k_zero_u64");
+  }
+  EVIS_HIP(launch_events_batch(d_descs + n_wave, d_prefix + n_wave + 1, n_refr, (int)blocks_refr,
+                               false, st, s),
            "k_events_batch");
   return EVIS_OK;
 }

@@ -103,6 +103,31 @@ __device__ __forceinline__ void stg(T* p, int idx, T v) {
 #endif
 }
 
+// A store through a global-address-space pointer with a 64-bit element
+// index (the event stream): a pointer read from device memory would
+// otherwise be generic, and generic stores also count against the LDS wait
+// counter.
+template <typename T>
+__device__ __forceinline__ void stg64(T* p, unsigned long long idx, T v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  ((__attribute__((address_space(1))) T*)p)[idx] = v;
+#else
+  p[idx] = v;
+#endif
+}
+
+// Atomic add on a global counter reached through a pointer read from device
+// memory (a generic atomic would also wait on outstanding LDS operations).
+__device__ __forceinline__ unsigned long long atomic_add_global(unsigned long long* p,
+                                                                unsigned long long v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)p, v,
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+  return atomicAdd(p, v);
+#endif
+}
+
 // Loads and stores of workgroup-shared (LDS) arrays reached through a plain
 // pointer: the cast lets the compiler emit LDS instructions instead of
 // generic (flat) ones, which would also wait on outstanding global loads.

@@ -7,6 +7,7 @@
 
 #include "evis.h"
 #include "evis_common.h"
+#include "evis_stream.h"
 
 namespace evis {
 
@@ -142,12 +143,24 @@ hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s);
 int defocus_tiles(int H, int W, int* tiles_x);
 hipError_t launch_state_init(const float* L_first, long long n, float* L_ref, int32_t* t_last,
                              hipStream_t s);
+// The event model over one env's frames.  Without a refractory period and
+// noise it runs in the wave form, which writes through the call's sharded
+// stream `st` (set up by launch_stream_init before, finished by
+// launch_stream_fixup after); otherwise in the workgroup form, which
+// appends at the cursor (reset first if asked).
+inline bool events_wave_form(int refr, bool noise) { return refr == 0 && !noise; }
 hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, int span,
                          float Dt, float C_on, float C_off, const float* th_on,
                          const float* th_off, int refr, uint32_t env_bits, float* L_ref,
                          int32_t* t_last, evis_event* out, long long capacity,
                          unsigned long long* cursor, int reset_cursor,
-                         const NoiseCfg* noise /* host copy, or null: no noise */, hipStream_t s);
+                         const NoiseCfg* noise /* host copy, or null: no noise */,
+                         const StreamState& st, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);   // a kernel, not a memset
+hipError_t launch_stream_init(const StreamState& st, unsigned long long* cursor, int reset,
+                              long long capacity, hipStream_t s);
+hipError_t launch_stream_fixup(const StreamState& st, evis_event* out, long long capacity,
+                               unsigned long long* cursor, hipStream_t s);
 // The event model over caller frames (k_events): one env's arguments; the
 // batched form (k_events_batch) reads an array of them from device memory.
 struct EventArgs {
@@ -171,10 +184,13 @@ struct EventArgs {
 
 // Workgroups of one env in a batched event-model launch, and the launch
 // (descs / prefix: device arrays of n_envs descriptors and n_envs + 1
-// workgroup offsets).
+// workgroup offsets).  wave_form: every env of the launch has no
+// refractory period (k_events_batch_wave, through the sharded stream st);
+// otherwise the workgroup form (at the cursor).
 int events_batch_blocks(long long px);
 hipError_t launch_events_batch(const EventArgs* descs, const int32_t* prefix, int n_envs,
-                               int total_blocks, unsigned long long* reset_cursor, hipStream_t s);
+                               int total_blocks, bool wave_form, const StreamState& st,
+                               hipStream_t s);
 hipError_t launch_substep_count(const float2* mA, const float2* mB, long long n, int K_max,
                                 unsigned long long* msq_scratch, int32_t* K_out, hipStream_t s);
 

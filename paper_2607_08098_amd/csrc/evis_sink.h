@@ -68,7 +68,7 @@ __device__ __forceinline__ void sink_drain(const SinkShared& sh, const SinkOut& 
   for (int i = tid; i < n; i += kBlock) {
     if ((long long)(gb + i) < so.capacity) {
       const uint2 r = lds_ld(sh.buf, i);
-      so.out[gb + i] = evis_event{r.x, (int32_t)r.y};
+      stg64(so.out, gb + (unsigned long long)i, evis_event{r.x, (int32_t)r.y});
     }
   }
   __syncthreads();         // copies done (and gbase read) before the buffer is reused
@@ -194,7 +194,7 @@ __device__ __forceinline__ void emit_substep(
         lds_st(sh.buf, lb + slot, make_uint2(word, (uint32_t)t));
       } else {
         const unsigned long long idx = gbase_w + (unsigned long long)(slot - n_lds);
-        if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
+        if ((long long)idx < so.capacity) stg64(so.out, idx, evis_event{word, (int32_t)t});
       }
     };
     if (refr == 0 && __ballot(m > 4) == 0ull) {   // no lane has more than four
@@ -368,7 +368,7 @@ __device__ __forceinline__ void cq_drain(CrossQueue& cq, const PixAux& aux, long
       lds_st(sh.buf, lb + slot, make_uint2(word, (uint32_t)t));
     } else {
       const unsigned long long idx = gbase_w + (unsigned long long)(slot - n_lds);
-      if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
+      if ((long long)idx < so.capacity) stg64(so.out, idx, evis_event{word, (int32_t)t});
     }
   };
   if (__ballot(n > 4) == 0ull) {   // wave-uniform: few events per entry
@@ -537,7 +537,7 @@ __device__ __forceinline__ void emit_noise(int j, const float (&Lj)[PPT], const 
           lds_st(sh.buf, lb + widx, make_uint2(word, (uint32_t)t));
         } else {
           const unsigned long long idx = gbase_w + (unsigned long long)(widx - n_lds);
-          if ((long long)idx < so.capacity) so.out[idx] = evis_event{word, (int32_t)t};
+          if ((long long)idx < so.capacity) stg64(so.out, idx, evis_event{word, (int32_t)t});
         }
         ++widx;
       }

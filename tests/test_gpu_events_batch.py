@@ -1,9 +1,11 @@
 """evis_generate_events_batch: the event model over caller frames of many
-envs in one launch, against the oracle env by env (bit-exact event
+envs in one call, against the oracle env by env (bit-exact event
 multisets, reference levels and last-event times), with uneven sizes and
-substep counts, per-pixel thresholds with a refractory period in one env,
-dozens of crossings per pixel-substep in another; and its host-detected
-errors enqueue nothing."""
+substep counts (below, at and above a block of eight), per-pixel
+thresholds with and without a refractory period (the two envs with one
+go to the workgroup form, the others to the wave form), dozens of
+crossings per pixel-substep in another; and its host-detected errors
+enqueue nothing."""
 import numpy as np
 import pytest
 
@@ -39,9 +41,10 @@ def make_case(H, W, K, seed, kind):
     frames, _ = o.interpolate(pair, K, 0, K + 1)
     sensor = o.Sensor(C_on=0.2, C_off=0.2, K=K)
     t_last = None
-    if kind == "refractory":
+    if kind in ("refractory", "mismatch"):
         on, off = scenes.mismatch_thresholds(H, W, 0.25, 0.03, 0.01, scenes.rng_for(seed))
-        sensor = o.Sensor(theta_on=on, theta_off=off, refractory_us=100, K=K)
+        refr = 100 if kind == "refractory" else 0
+        sensor = o.Sensor(theta_on=on, theta_off=off, refractory_us=refr, K=K)
         t_last = np.full((H, W), o.T_LAST_INIT, np.int32)
     if kind == "hdr":
         frames = frames.copy()
@@ -53,7 +56,8 @@ def make_case(H, W, K, seed, kind):
 def test_generate_events_batch_matches_oracle(torch, ctx):
     from paper_2607_08098_amd import evis
     specs = [(37, 53, 3, 801, None), (96, 120, 8, 802, "refractory"), (260, 346, 11, 803, None),
-             (64, 64, 5, 804, "hdr"), (1, 1, 1, 805, None), (200, 17, 16, 806, None)]
+             (64, 64, 5, 804, "hdr"), (1, 1, 1, 805, None), (200, 17, 16, 806, None),
+             (90, 70, 9, 807, "mismatch"), (50, 61, 4, 808, "refractory")]
     dev = "cuda"
     items, want = [], []
     for e, (H, W, K, seed, kind) in enumerate(specs):

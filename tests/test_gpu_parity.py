@@ -137,7 +137,7 @@ def gen_events(torch, ctx, L_seq, t0, t1, sensor, L_ref, t_last, env_id=0, capac
     return ev, int(n.item()), st["L_ref"].cpu().numpy(), (None if t_last is None else st["t_last"].cpu().numpy())
 
 
-@pytest.mark.parametrize("variant", ["plain", "mismatch_refractory", "hdr_many"])
+@pytest.mark.parametrize("variant", ["plain", "mismatch", "mismatch_refractory", "hdr_many"])
 def test_generate_events_bit_exact(torch, ctx, variant):
     pair = U.oracle_pair(U.blob_scene(96, 120, 21))
     K = 8
@@ -146,10 +146,11 @@ def test_generate_events_bit_exact(torch, ctx, variant):
     sensor = o.Sensor(C_on=0.2, C_off=0.2, K=K)
     t_last = None
     L_ref = pair.L_A.copy()
-    if variant == "mismatch_refractory":
+    if variant in ("mismatch", "mismatch_refractory"):
         from paper_2607_08098_amd import scenes
         on, off = scenes.mismatch_thresholds(H, W, 0.25, 0.03, 0.01, scenes.rng_for(5))
-        sensor = o.Sensor(theta_on=on, theta_off=off, refractory_us=100, K=K)
+        refr = 100 if variant == "mismatch_refractory" else 0
+        sensor = o.Sensor(theta_on=on, theta_off=off, refractory_us=refr, K=K)
         t_last = np.full((H, W), o.T_LAST_INIT, np.int32)
     if variant == "hdr_many":
         # large per-substep contrast: dozens of crossings per pixel-substep
@@ -194,6 +195,50 @@ def test_generate_events_capacity_overflow(torch, ctx):
     wanted = set(map(tuple, want.tolist()))
     assert all(tuple(e) in wanted for e in got.tolist())
     assert np.array_equal(gR.view(np.uint32), R.view(np.uint32))   # state still advances
+
+
+def test_generate_events_appends_and_fills_exact_capacity(torch, ctx):
+    """Calls append at the cursor: a first call with reset, a second one
+    without (a refractory-free env: the sharded stream whose base is the
+    cursor), a third in the workgroup form (refractory period); the union is
+    the three oracle multisets.  Then one call into a buffer of exactly its
+    event count (every slot of the prefix filled) and one into a buffer one
+    event short (the prefix still full, the count still whole)."""
+    from paper_2607_08098_amd import evis
+    dev = "cuda"
+    cases = []
+    for e, (seed, refr) in enumerate(((31, 0), (32, 0), (33, 100))):
+        pair = U.oracle_pair(U.blob_scene(70, 90, seed))
+        frames, _ = o.interpolate(pair, 7, 0, 8)
+        sensor = o.Sensor(C_on=0.15, C_off=0.15, K=7, refractory_us=refr)
+        t_last = np.full(pair.shape, o.T_LAST_INIT, np.int32) if refr else None
+        want, _, _ = o.emit_events(list(frames), 500, 500 + 16667, sensor, pair.L_A.copy(), t_last,
+                                   env_id=e)
+        cases.append((frames, sensor, pair.L_A.copy(), t_last, want))
+    out, n = evis.event_buffer(1 << 20)
+    n.fill_(12345)
+    for e, (frames, sensor, L_ref, t_last, _) in enumerate(cases):
+        st = dict(L_ref=torch.from_numpy(L_ref.copy()).to(dev),
+                  t_last=None if t_last is None else torch.from_numpy(t_last.copy()).to(dev))
+        sd = dict(C_on=sensor.C_on, C_off=sensor.C_off, refractory_us=sensor.refractory_us)
+        say("generate_events append", e)
+        evis.evis_generate_events(ctx, torch.from_numpy(np.ascontiguousarray(frames)).to(dev), 500,
+                                  500 + 16667, sd, st, e, out, n,
+                                  flags=evis.EVIS_FLAG_RESET_CURSOR if e == 0 else 0)
+    torch.cuda.synchronize()
+    want_all = np.concatenate([c[4] for c in cases])
+    assert int(n.item()) == len(want_all)
+    assert U.same_multiset(evis.decode_events(out, n), want_all)
+    frames, sensor, L_ref, _, want = cases[0]
+    for cap in (len(want), len(want) - 1):
+        say("generate_events capacity", cap, "of", len(want))
+        got, cnt, _, _ = gen_events(torch, ctx, frames, 500, 500 + 16667, sensor, L_ref, None, 0,
+                                    capacity=cap)
+        assert cnt == len(want) and len(got) == cap
+        if cap == len(want):
+            assert U.same_multiset(got, want)
+        wanted = set(map(tuple, want.tolist()))
+        assert all(tuple(e) in wanted for e in got.tolist())
 
 
 # ---------------------------------------------------------------------------

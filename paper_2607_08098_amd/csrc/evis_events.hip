@@ -204,6 +204,7 @@ struct WaveCtx {
   const float* coff;
   int* tl;             // LDS
   int wbase, W;
+  int x0, y0;          // column and row of pixel wbase
   long long t0;
   int span;
   float Dt;
@@ -245,9 +246,13 @@ __device__ __forceinline__ void wave_drain(int head, int ntake, const float4* cq
       wave_put_direct(wo, g + (unsigned long long)slot, evis_event{word, (int32_t)t});
   };
   // event word of wave pixel i: x | y << 11 | polarity << 22 | env << 23
+  // (the wave's first pixel is (x0, y0); pixel i is i columns on, wrapped)
   auto word_of = [&](int i, bool p) {
-    const uint32_t q = (uint32_t)(w.wbase + i);
-    const uint32_t y = q / (uint32_t)w.W, x = q - y * (uint32_t)w.W;
+    uint32_t x = (uint32_t)(w.x0 + i), y = (uint32_t)w.y0;
+    while (x >= (uint32_t)w.W) {
+      x -= (uint32_t)w.W;
+      ++y;
+    }
     return x | (y << 11) | ((p ? 1u : 0u) << 22) | w.env_bits;
   };
   if (__ballot(n > 4) == 0ull) {   // wave-uniform: few events per entry
@@ -314,8 +319,12 @@ __device__ __forceinline__ void events_wave(const EventArgs& a, const StreamStat
     okbits |= (ok ? 1u : 0u) << k;
     off[k] = ok ? q : 0;   // a slot past the end reads pixel 0 and never crosses
     R[k] = ok ? ldg(a.Lref, q) : 0.0f;
+    // a per-pixel threshold that is not > 0 never crosses: NaN fails every
+    // comparison, so the substep needs no test of its own for it
     con[k] = a.th_on ? ldg(a.th_on, off[k]) : a.C_on;
     coff[k] = a.th_off ? ldg(a.th_off, off[k]) : a.C_off;
+    con[k] = con[k] > 0.0f ? con[k] : __builtin_nanf("");
+    coff[k] = coff[k] > 0.0f ? coff[k] : __builtin_nanf("");
     if (a.th_on) lds_st(L.con, i, con[k]);
     if (a.th_off) lds_st(L.coff, i, coff[k]);
     lds_st(L.tl, i, INT_MIN);
@@ -328,7 +337,7 @@ __device__ __forceinline__ void events_wave(const EventArgs& a, const StreamStat
     for (int k = 0; k < PPT; ++k) cur[v][k] = ldg(fr, off[k]);
   }
   const WaveCtx w{a.C_on, a.C_off, a.th_on ? L.con : nullptr, a.th_off ? L.coff : nullptr, L.tl,
-                  wbase, a.W, a.t0, a.span, a.Dt, a.env_bits};
+                  wbase, a.W, wbase % a.W, wbase / a.W, a.t0, a.span, a.Dt, a.env_bits};
   WaveSink ws{L.ev, 0};
   int head = 0, qn = 0;   // ring: entries [head, head + qn) (mod QR)
   for (int j0 = 1; j0 <= K; j0 += U) {
@@ -352,7 +361,7 @@ __device__ __forceinline__ void events_wave(const EventArgs& a, const StreamStat
         const bool pos = d > 0.0f;
         const float c = pos ? con[k] : coff[k];
         const float ad = fabsf(d);
-        const bool hit = ((okbits >> k) & 1u) && ad >= c && c > 0.0f;
+        const bool hit = ((okbits >> k) & 1u) && ad >= c;
         const unsigned long long bal = __ballot(hit);
         if (hit) {
           // c <= |d| < 2c (2c is exact) is one crossing: the common case

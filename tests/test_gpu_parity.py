@@ -137,7 +137,8 @@ def gen_events(torch, ctx, L_seq, t0, t1, sensor, L_ref, t_last, env_id=0, capac
     return ev, int(n.item()), st["L_ref"].cpu().numpy(), (None if t_last is None else st["t_last"].cpu().numpy())
 
 
-@pytest.mark.parametrize("variant", ["plain", "mismatch", "mismatch_refractory", "hdr_many"])
+@pytest.mark.parametrize("variant", ["plain", "mismatch", "mismatch_nonpositive",
+                                     "mismatch_refractory", "hdr_many"])
 def test_generate_events_bit_exact(torch, ctx, variant):
     pair = U.oracle_pair(U.blob_scene(96, 120, 21))
     K = 8
@@ -146,9 +147,16 @@ def test_generate_events_bit_exact(torch, ctx, variant):
     sensor = o.Sensor(C_on=0.2, C_off=0.2, K=K)
     t_last = None
     L_ref = pair.L_A.copy()
-    if variant in ("mismatch", "mismatch_refractory"):
+    if variant in ("mismatch", "mismatch_nonpositive", "mismatch_refractory"):
         from paper_2607_08098_amd import scenes
         on, off = scenes.mismatch_thresholds(H, W, 0.25, 0.03, 0.01, scenes.rng_for(5))
+        if variant == "mismatch_nonpositive":
+            # thresholds that are not > 0 (zero, negative, NaN) never cross
+            rng = np.random.default_rng(6)
+            for th in (on, off):
+                th[rng.random((H, W)) < 0.05] = F32(0.0)
+                th[rng.random((H, W)) < 0.05] = F32(-0.1)
+                th[rng.random((H, W)) < 0.05] = F32(np.nan)
         refr = 100 if variant == "mismatch_refractory" else 0
         sensor = o.Sensor(theta_on=on, theta_off=off, refractory_us=refr, K=K)
         t_last = np.full((H, W), o.T_LAST_INIT, np.int32)

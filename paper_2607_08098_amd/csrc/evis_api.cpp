@@ -79,6 +79,7 @@ struct evis_ctx {
   DevBuf tb;          // float4[per 4x4 source block]: motion bounds
   DevBuf srcB;        // two-splat warps: B's splat records, same layout as src
   DevBuf tbB;         // two-splat warps: bounds of -m_B per block
+  DevBuf sbb;         // motion bounds per superblock of source blocks
   DevBuf msq;         // one u64 for evis_substep_count
   DevBuf soft;        // item prefix + SoftPtrs of the surrogate calls
   DevBuf voxmax;      // per-plane maxima of evis_voxel_grid
@@ -329,6 +330,8 @@ EnvDesc make_desc(const evis_pair& p, const evis_sensor& s, const evis_state& st
   d.W = p.W;
   d.ntx_src = (p.W + kSrcBlk - 1) / kSrcBlk;
   d.nty_src = (p.H + kSrcBlk - 1) / kSrcBlk;
+  d.ntx_sb = (d.ntx_src + kSbBlk - 1) / kSbBlk;
+  d.nty_sb = (d.nty_src + kSbBlk - 1) / kSbBlk;
   d.K_fixed = s.K > 0 ? s.K : 0;
   d.K_max = s.K_max;
   d.blend = s.blend_mode & kBlendMask;
@@ -365,6 +368,8 @@ struct Plan {
   FixedVec<int32_t, EVIS_MAX_ENVS + 1> src_prefix;   // n + 1: groups of four source blocks before each env
   long long px_total = 0;
   int src_total = 0;                 // groups of four source blocks (prep work units)
+  int sb_total = 0;                  // superblocks of every env
+  int sb_max = 0;                    // superblocks of the largest env
   int items = 0;
 };
 
@@ -382,15 +387,18 @@ ScratchView ctx_view(evis_ctx* ctx) {
 
 // Point every env's splat records and block bounds into src / tb (and B's
 // into srcB / tbB for the two-splat warps), four blocks per group.
-void plan_bind(Plan& pl, float4* src, float4* tb, float4* srcB, float4* tbB) {
+void plan_bind(Plan& pl, float4* src, float4* tb, float4* srcB, float4* tbB, float4* sbb) {
   const bool two = pl.desc.size() > 0 && pl.desc[0].warp != EVIS_WARP_GATHER;   // one warp per plan
+  long long sb0 = 0;
   for (int e = 0; e < pl.desc.size(); ++e) {
     const long long blk0 = 4LL * pl.src_prefix[e];
     pl.desc[e].src = src + blk0 * kBlkPx;
     pl.desc[e].tb = tb + blk0;
+    pl.desc[e].sbb = sbb + sb0;
     pl.desc[e].srcB = two ? srcB + blk0 * kBlkPx : nullptr;
     pl.desc[e].tbB = two ? tbB + blk0 : nullptr;
     pl.desc[e].src_tile_base = pl.src_prefix[e];
+    sb0 += (long long)pl.desc[e].ntx_sb * pl.desc[e].nty_sb;
   }
 }
 
@@ -398,17 +406,22 @@ void plan_bind(Plan& pl, float4* src, float4* tb, float4* srcB, float4* tbB) {
 void plan_layout(Plan& pl, int tw, int th) {
   const int n = pl.desc.size();
   long long px = 0;
-  int src = 0, items = 0;
+  int src = 0, items = 0, sb = 0, sb_max = 0;
   pl.src_prefix.assign(n + 1, 0);
   for (int e = 0; e < n; ++e) {
     pl.src_prefix[e] = src;
     px += (long long)pl.desc[e].H * pl.desc[e].W;
     src += (pl.desc[e].ntx_src * pl.desc[e].nty_src + 3) / 4;
     items += ((pl.desc[e].W + tw - 1) / tw) * ((pl.desc[e].H + th - 1) / th);
+    const int nsb = pl.desc[e].ntx_sb * pl.desc[e].nty_sb;
+    sb += nsb;
+    sb_max = std::max(sb_max, nsb);
   }
   pl.src_prefix[n] = src;
   pl.px_total = px;
   pl.src_total = src;
+  pl.sb_total = sb;
+  pl.sb_max = sb_max;
   pl.items = items;
 }
 
@@ -423,6 +436,8 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   int rc = ensure(ctx, ctx->src, (size_t)src * 4 * kBlkPx * sizeof(float4), &grew);
   if (rc) return rc;
   rc = ensure(ctx, ctx->tb, (size_t)src * 4 * sizeof(float4), &grew);
+  if (rc) return rc;
+  rc = ensure(ctx, ctx->sbb, (size_t)pl.sb_total * sizeof(float4), &grew);
   if (rc) return rc;
   const bool two = n > 0 && pl.desc[0].warp != EVIS_WARP_GATHER;   // one warp per plan
   if (two) {
@@ -441,7 +456,7 @@ int plan_envs(evis_ctx* ctx, Plan& pl, int tw, int th) {
   }
   plan_bind(pl, static_cast<float4*>(ctx->src.p), static_cast<float4*>(ctx->tb.p),
             two ? static_cast<float4*>(ctx->srcB.p) : nullptr,
-            two ? static_cast<float4*>(ctx->tbB.p) : nullptr);
+            two ? static_cast<float4*>(ctx->tbB.p) : nullptr, static_cast<float4*>(ctx->sbb.p));
   return EVIS_OK;
 }
 
@@ -492,6 +507,7 @@ int enqueue_batch(evis_ctx* ctx, const ScratchView& sv, const Plan& pl, int mode
   Sched sc = sched_ptrs(sv.sched, n);
   EVIS_HIP(launch_reset(d_dyn, n, sc.queue, reset_cursor, s), "k_reset");
   EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n, pl.src_total, s), "k_prep");
+  EVIS_HIP(launch_superbounds(d_desc, n, pl.sb_max, s), "k_superbounds");
   if (!pl.desc.empty() && pl.desc[0].warp != EVIS_WARP_GATHER)   // one warp per plan
     EVIS_HIP(launch_prep_b(d_desc, d_prefix, n, pl.src_total, s), "k_prep_b");
   EVIS_HIP(launch_queue(d_desc, d_dyn, n, tw, th, sc.xbegin, sc.env_order, sc.n_items, K_used, s),
@@ -552,6 +568,7 @@ int plan_static(evis_ctx* ctx, Plan& pl, int tw, int th, ScratchView& sv) {
   const size_t bnd = (size_t)pl.src_total * 4 * sizeof(float4);
   const size_t o_src = take(rec), o_tb = take(bnd);
   const size_t o_srcB = two ? take(rec) : 0, o_tbB = two ? take(bnd) : 0;
+  const size_t o_sbb = take((size_t)pl.sb_total * sizeof(float4));
   if (off > (size_t)EVIS_NOALLOC_SCRATCH_BYTES) {
     char b[200];
     std::snprintf(b, sizeof(b),
@@ -565,7 +582,8 @@ int plan_static(evis_ctx* ctx, Plan& pl, int tw, int th, ScratchView& sv) {
                    reinterpret_cast<int32_t*>(base + o_sched)};
   plan_bind(pl, reinterpret_cast<float4*>(base + o_src), reinterpret_cast<float4*>(base + o_tb),
             two ? reinterpret_cast<float4*>(base + o_srcB) : nullptr,
-            two ? reinterpret_cast<float4*>(base + o_tbB) : nullptr);
+            two ? reinterpret_cast<float4*>(base + o_tbB) : nullptr,
+            reinterpret_cast<float4*>(base + o_sbb));
   return EVIS_OK;
 }
 
@@ -681,7 +699,7 @@ void evis_destroy(evis_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
   DevBuf* bufs[] = {&ctx->meta, &ctx->dyn, &ctx->sched, &ctx->src,    &ctx->tb,
-                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft,   &ctx->voxmax, &ctx->evb, &ctx->evs};
+                    &ctx->srcB, &ctx->tbB, &ctx->msq,   &ctx->soft,   &ctx->voxmax, &ctx->evb, &ctx->evs, &ctx->sbb};
   for (DevBuf* b : bufs)
     if (b->p) hipFree(b->p);
   for (int i = 0; i < kStageSlots; ++i) {
@@ -1294,6 +1312,7 @@ static int soft_call(evis_ctx* ctx, const evis_soft_env* envs, int32_t n_envs, i
   const SoftPtrs* d_ptrs = reinterpret_cast<const SoftPtrs*>(static_cast<unsigned char*>(ctx->soft.p) + off_ptrs);
   EVIS_HIP(launch_reset(d_dyn, n_envs, sc.queue, nullptr, s), "k_reset");
   EVIS_HIP(launch_prep(d_desc, d_dyn, d_prefix, n_envs, pl.src_total, s), "k_prep");
+  EVIS_HIP(launch_superbounds(d_desc, n_envs, pl.sb_max, s), "k_superbounds");
   if (backward) EVIS_HIP(launch_soft_zero(d_ptrs, d_desc, n_envs, gC, s), "k_soft_zero");
   SoftArgs a{};
   a.envs = d_desc;

@@ -19,6 +19,7 @@ constexpr int kBlock = 256;                 // 4 waves per workgroup
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kSrcBlk = 4;                  // source blocks are 4x4 pixels
 constexpr int kBlkPx = kSrcBlk * kSrcBlk;   // 16 lanes, one row of a wave
+constexpr int kSbBlk = 8;                   // superblocks are 8x8 source blocks (32x32 pixels)
 constexpr uint64_t kEmptyKey = 0xFFFFFFFFFFFFFFFFull;
 constexpr int kMaxCross = EVIS_MAX_CROSSINGS;
 
@@ -38,8 +39,10 @@ struct EnvDesc {
   float4* src;             // scratch [blocks * 16]: (m_A.x, m_A.y, Z_A, Zend - Z_A) per
                            // source, block-major (block by * ntx_src + bx, then row-major)
   float4* tb;              // scratch [blocks]: (mx_min, mx_max, my_min, my_max) per block
+  float4* sbb;             // scratch [superblocks]: the same bounds over kSbBlk x kSbBlk blocks
   int32_t H, W;
   int32_t ntx_src, nty_src;    // 4x4 source blocks per row / column
+  int32_t ntx_sb, nty_sb;      // superblocks per row / column
   int32_t src_tile_base;       // prefix over envs of groups of four blocks (prep work units)
   int32_t K_fixed;             // > 0: fixed K
   int32_t K_max;

@@ -85,6 +85,8 @@ hipError_t launch_reset(EnvDyn* dyn, int n_envs, unsigned int* queue,
                         unsigned long long* cursor, hipStream_t s);   // queue: kXcd counters
 hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_prefix, int n_envs,
                        int total_groups, hipStream_t s);
+// Per-superblock motion bounds from the per-block ones (after launch_prep).
+hipError_t launch_superbounds(const EnvDesc* envs, int n_envs, int sb_max, hipStream_t s);
 hipError_t launch_prep_b(const EnvDesc* envs, const int32_t* src_prefix, int n_envs,
                          int total_groups, hipStream_t s);   // two-splat warps' B records
 hipError_t launch_queue(const EnvDesc* envs, EnvDyn* dyn, int n_envs, int tile_w, int tile_h,

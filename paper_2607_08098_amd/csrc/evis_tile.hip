@@ -268,6 +268,37 @@ hipError_t launch_prep(const EnvDesc* envs, EnvDyn* dyn, const int32_t* src_pref
   return hipGetLastError();
 }
 
+// Motion bounds of each superblock (kSbBlk x kSbBlk source blocks): the
+// minima and maxima of its blocks' bounds (a block with no finite source
+// holds +inf minima and -inf maxima, which change nothing).  One thread per
+// superblock; workgroup row y is env y.
+__global__ __launch_bounds__(kBlock) void k_superbounds(const EnvDesc* __restrict__ envs) {
+  const EnvDesc& d = envs[blockIdx.y];
+  const int sb = blockIdx.x * kBlock + threadIdx.x;
+  if (sb >= d.ntx_sb * d.nty_sb) return;
+  const int sx = sb % d.ntx_sb, sy = sb / d.ntx_sb;
+  const float inf = __int_as_float(0x7f800000);
+  float4 m = make_float4(inf, -inf, inf, -inf);
+  const int bx1 = min((sx + 1) * kSbBlk, d.ntx_src), by1 = min((sy + 1) * kSbBlk, d.nty_src);
+  for (int by = sy * kSbBlk; by < by1; ++by) {
+    for (int bx = sx * kSbBlk; bx < bx1; ++bx) {
+      const float4 b = ldg(d.tb, by * d.ntx_src + bx);
+      m.x = fminf(m.x, b.x);
+      m.y = fmaxf(m.y, b.y);
+      m.z = fminf(m.z, b.z);
+      m.w = fmaxf(m.w, b.w);
+    }
+  }
+  stg(d.sbb, sb, m);
+}
+
+hipError_t launch_superbounds(const EnvDesc* envs, int n_envs, int sb_max, hipStream_t s) {
+  if (n_envs <= 0 || sb_max <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_superbounds, dim3((sb_max + kBlock - 1) / kBlock, n_envs), dim3(kBlock), 0,
+                     s, envs);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep_b(const EnvDesc* envs, const int32_t* src_prefix, int n_envs,
                          int total_groups, hipStream_t s) {
   if (total_groups <= 0) return hipSuccess;

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
   __shared__ float4 s_cq[CQN];   // crossing queues of the waves (no refractory period)
   __shared__ int s_evn, s_req[4];
   __shared__ unsigned long long s_gbase;
-  __shared__ int s_item, s_rank, s_q, s_lcnt;
+  __shared__ int s_item, s_rank, s_q, s_lcnt, s_sbn;
   __shared__ unsigned long long s_lcnt2;   // two-splat warps: A's and B's candidate counts
   constexpr int AUXN = (MODE == MODE_STEP) ? NPX : 1;
   __shared__ float s_con[AUXN], s_coff[AUXN];
@@ -113,6 +113,7 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
       s_rank = r;
       s_q = q;
       s_lcnt = 0;
+      s_sbn = 0;
       if (!kGather) s_lcnt2 = 0ull;
     }
     __syncthreads();
@@ -181,7 +182,10 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
     bool overflow = false;
     if (K > 1) {
       if (kGather) {
-        nlist = build_candidates(d, dy, K, Tx0, Tx1, Ty0, Ty1, list, &s_lcnt, a.list_cap, win);
+        // the splat's per-wave slices are free until the splat: they hold
+        // the list of superblocks meanwhile (kBlock entries)
+        nlist = build_candidates(d, dy, K, Tx0, Tx1, Ty0, Ty1, list, &s_lcnt, a.list_cap, win,
+                                 reinterpret_cast<int*>(&s_wl[0][0]), &s_sbn);
         overflow = nlist > a.list_cap;
       } else {
         build_candidates_two(d, dy, K, Tx0, Tx1, Ty0, Ty1, list, &s_lcnt2, lcap, win, nlist,

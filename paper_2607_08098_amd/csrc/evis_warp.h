@@ -153,16 +153,23 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
       const bool bx = qx > fx0, by = qy > fy0;   // corners of strictly positive weight
       const uint32_t low = (DIR == DIR_A_TAGGED) ? ((uint32_t)src[c] | kATag) : (uint32_t)src[c];
       const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | low;
-      // All four corners of the cell from one address; a corner of zero
-      // weight gets the empty key, which changes nothing, so the four
-      // atomics need no branches.  y0 ZS + x0 is formed in float, exactly
-      // (|x0|, |y0| <= 2^12, so it is an integer below 2^24).
+      // All four corners of the cell from one address.  A corner of zero
+      // weight (an integer coordinate, rare) must not be written: the
+      // common case of four positive weights writes the one key four
+      // times, the rare case writes the other corners' empty key, which
+      // changes nothing.  y0 ZS + x0 is formed in float, exactly (|x0|,
+      // |y0| <= 2^12, so it is an integer below 2^24).
       constexpr int ZS = zrow<TW>();
       unsigned long long* zb = zs[t] + ((int)fmaf(fy0, (float)ZS, fx0) - corg);
       atomicMin(zb, key);
-      atomicMin(zb + 1, bx ? key : kEmptyKey);
-      atomicMin(zb + ZS, by ? key : kEmptyKey);
-      atomicMin(zb + ZS + 1, (bx && by) ? key : kEmptyKey);
+      if (bx && by) {
+        atomicMin(zb + 1, key);
+        atomicMin(zb + ZS, key);
+        atomicMin(zb + ZS + 1, key);
+      } else {
+        atomicMin(zb + 1, bx ? key : kEmptyKey);
+        atomicMin(zb + ZS, by ? key : kEmptyKey);
+      }
     }
   }
 }
@@ -227,14 +234,38 @@ __device__ __forceinline__ bool block_range(const EnvDesc& d, int bx, int by, in
   return substep_range(b, Sx0, Sx1, Sy0, Sy1, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi, BACK);
 }
 
+// Whether some source of superblock (sx, sy) can come within a pixel of
+// target tile [Tx0,Tx1]x[Ty0,Ty1] over the gap: the test block_range makes
+// first, on the superblock's extent and motion bounds.  Both only widen
+// from a block to its superblock, so a block that passes it lies in a
+// superblock that passes it.
+__device__ __forceinline__ bool superblock_reaches(const EnvDesc& d, int sx, int sy, int Tx0,
+                                                   int Tx1, int Ty0, int Ty1) {
+  const float4 b = ldg(d.sbb, sy * d.ntx_sb + sx);
+  if (!(b.x <= b.y) || !(b.z <= b.w)) return false;   // no finite source
+  constexpr int SP = kSbBlk * kSrcBlk;                 // pixels per superblock side
+  const int Sx0 = sx * SP, Sx1 = min(Sx0 + SP - 1, d.W - 1);
+  const int Sy0 = sy * SP, Sy1 = min(Sy0 + SP - 1, d.H - 1);
+  return !((float)Sx0 - fmaxf(b.y, 0.0f) >= (float)(Tx1 + 2) ||
+           (float)Sx1 - fminf(b.x, 0.0f) <= (float)(Tx0 - 2) ||
+           (float)Sy0 - fmaxf(b.w, 0.0f) >= (float)(Ty1 + 2) ||
+           (float)Sy1 - fminf(b.z, 0.0f) <= (float)(Ty0 - 2));
+}
+
 // Candidate source blocks of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
 // during which each can reach it, appended to the LDS list (at most cap
 // entries, see cand_entry).  *count must be zero on entry; returns the
 // number of candidates (uniform; more than cap means the list overflowed).
-// Holds a barrier.
+// The window of blocks follows from the env's largest motion; with the
+// superblock bounds (sb_list: LDS [kBlock], *sb_count zero on entry) only
+// the blocks of the window's superblocks that can reach the tile are
+// tested, which on a scene whose motion varies is a fraction of the
+// window.  The candidates are the same either way (their order in the
+// list is not).  Holds a barrier (two with superblocks).
 __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& dy, int K,
                                                 int Tx0, int Tx1, int Ty0, int Ty1,
-                                                uint32_t* list, int* count, int cap, Window& w) {
+                                                uint32_t* list, int* count, int cap, Window& w,
+                                                int* sb_list = nullptr, int* sb_count = nullptr) {
   const int tid = threadIdx.x;
   const int W = d.W, H = d.H;
   const double M = __longlong_as_double((long long)dy.msq_bits);
@@ -245,13 +276,30 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
   const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcBlk);
   w.nwx = wx1 - w.wx0 + 1;
   w.nwin = w.nwx * (wy1 - w.wy0 + 1);
-  for (int i = tid; i < w.nwin; i += kBlock) {
-    const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
+  auto test_block = [&](int bx, int by) {
     int jlo, jhi;
     if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi)) {
       const int slot = atomicAdd(count, 1);
       if (slot < cap) list[slot] = cand_entry(bx, by, jlo, jhi);
     }
+  };
+  const int sx0 = w.wx0 / kSbBlk, sx1 = wx1 / kSbBlk, sy0 = w.wy0 / kSbBlk, sy1 = wy1 / kSbBlk;
+  const int nsx = sx1 - sx0 + 1, nsb = nsx * (sy1 - sy0 + 1);
+  if (sb_list != nullptr && d.sbb != nullptr && nsb <= kBlock) {   // uniform
+    if (tid < nsb) {
+      const int sx = sx0 + tid % nsx, sy = sy0 + tid / nsx;
+      if (superblock_reaches(d, sx, sy, Tx0, Tx1, Ty0, Ty1)) sb_list[atomicAdd(sb_count, 1)] = sx | (sy << 16);
+    }
+    __syncthreads();
+    constexpr int NB = kSbBlk * kSbBlk;
+    const int n_items = __builtin_amdgcn_readfirstlane(*sb_count) * NB;
+    for (int i = tid; i < n_items; i += kBlock) {
+      const int e = sb_list[i / NB], bi = i % NB;
+      const int bx = (e & 0xFFFF) * kSbBlk + bi % kSbBlk, by = (e >> 16) * kSbBlk + bi / kSbBlk;
+      if (bx >= w.wx0 && bx <= wx1 && by >= w.wy0 && by <= wy1) test_block(bx, by);
+    }
+  } else {
+    for (int i = tid; i < w.nwin; i += kBlock) test_block(w.wx0 + i % w.nwx, w.wy0 + i / w.nwx);
   }
   __syncthreads();
   return __builtin_amdgcn_readfirstlane(*count);

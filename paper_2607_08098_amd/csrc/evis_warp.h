@@ -154,21 +154,22 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
       const uint32_t low = (DIR == DIR_A_TAGGED) ? ((uint32_t)src[c] | kATag) : (uint32_t)src[c];
       const unsigned long long key = ((unsigned long long)__float_as_uint(zt) << 32) | low;
       // All four corners of the cell from one address.  A corner of zero
-      // weight (an integer coordinate, rare) must not be written: the
-      // common case of four positive weights writes the one key four
-      // times, the rare case writes the other corners' empty key, which
-      // changes nothing.  y0 ZS + x0 is formed in float, exactly (|x0|,
-      // |y0| <= 2^12, so it is an integer below 2^24).
+      // weight (an integer coordinate, rare) must not be written: it gets
+      // the empty key, which changes nothing; the gather warp's splat
+      // writes the one key four times when all four weights are positive.
+      // y0 ZS + x0 is formed in float, exactly (|x0|, |y0| <= 2^12, so it
+      // is an integer below 2^24).
       constexpr int ZS = zrow<TW>();
       unsigned long long* zb = zs[t] + ((int)fmaf(fy0, (float)ZS, fx0) - corg);
       atomicMin(zb, key);
-      if (bx && by) {
+      if (DIR == DIR_A && bx && by) {   // (the two-splat warps measured no faster with it)
         atomicMin(zb + 1, key);
         atomicMin(zb + ZS, key);
         atomicMin(zb + ZS + 1, key);
       } else {
         atomicMin(zb + 1, bx ? key : kEmptyKey);
         atomicMin(zb + ZS, by ? key : kEmptyKey);
+        atomicMin(zb + ZS + 1, (bx && by) ? key : kEmptyKey);
       }
     }
   }
@@ -256,11 +257,11 @@ __device__ __forceinline__ bool superblock_reaches(const EnvDesc& d, int sx, int
 // during which each can reach it, appended to the LDS list (at most cap
 // entries, see cand_entry).  *count must be zero on entry; returns the
 // number of candidates (uniform; more than cap means the list overflowed).
-// The window of blocks follows from the env's largest motion; with the
-// superblock bounds (sb_list: LDS [kBlock], *sb_count zero on entry) only
-// the blocks of the window's superblocks that can reach the tile are
-// tested, which on a scene whose motion varies is a fraction of the
-// window.  The candidates are the same either way (their order in the
+// The window of blocks follows from the env's largest motion; when it
+// takes more than one pass, with the superblock bounds (sb_list: LDS
+// [kBlock], *sb_count zero on entry) only the blocks of the window's
+// superblocks that can reach the tile are tested, which on a scene whose
+// motion varies is a fraction of the window.  The candidates are the same either way (their order in the
 // list is not).  Holds a barrier (two with superblocks).
 __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& dy, int K,
                                                 int Tx0, int Tx1, int Ty0, int Ty1,
@@ -285,7 +286,9 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
   };
   const int sx0 = w.wx0 / kSbBlk, sx1 = wx1 / kSbBlk, sy0 = w.wy0 / kSbBlk, sy1 = wy1 / kSbBlk;
   const int nsx = sx1 - sx0 + 1, nsb = nsx * (sy1 - sy0 + 1);
-  if (sb_list != nullptr && d.sbb != nullptr && nsb <= kBlock) {   // uniform
+  // (a window the workgroup scans in one pass is left to the plain scan:
+  // the superblock pass would only add a barrier)
+  if (sb_list != nullptr && d.sbb != nullptr && w.nwin > kBlock && nsb <= kBlock) {   // uniform
     if (tid < nsb) {
       const int sx = sx0 + tid % nsx, sy = sy0 + tid / nsx;
       if (superblock_reaches(d, sx, sy, Tx0, Tx1, Ty0, Ty1)) sb_list[atomicAdd(sb_count, 1)] = sx | (sy << 16);

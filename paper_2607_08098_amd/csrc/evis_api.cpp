@@ -85,6 +85,7 @@ struct evis_ctx {
   DevBuf voxmax;      // per-plane maxima of evis_voxel_grid
   DevBuf evb;         // evis_generate_events_batch: EventArgs[n], then two int32 prefixes
   DevBuf evs;         // the sharded event stream of the wave-form event model
+  bool evs_table_clean = false;   // its chunk table is all unpublished
   std::vector<unsigned char> soft_shadow;
   // host staging of the descriptor block (pinned ring)
   void* stage[kStageSlots] = {};
@@ -186,9 +187,27 @@ void drop_graphs(evis_ctx* ctx) {
 // output of `capacity` events (grown as needed, never shrunk).
 int stream_state(evis_ctx* ctx, long long capacity, StreamState* st) {
   const size_t bytes = stream_state_layout(capacity, nullptr, nullptr);
-  const int rc = ensure(ctx, ctx->evs, bytes);
+  bool grew = false;
+  const int rc = ensure(ctx, ctx->evs, bytes, &grew);
   if (rc) return rc;
+  if (grew) ctx->evs_table_clean = false;
   stream_state_layout(capacity, ctx->evs.p, st);
+  return EVIS_OK;
+}
+
+// Set-up, event-model launch (the caller's `launch`), fixup and clean-up of
+// the sharded stream on stream s.  The table is cleared whole only when its
+// state is unknown (new buffer, or a sequence that did not finish).
+template <typename Launch>
+int with_stream(evis_ctx* ctx, const StreamState& st, unsigned long long* cursor, int reset,
+                evis_event* out, long long capacity, hipStream_t s, Launch launch) {
+  const bool clear = !ctx->evs_table_clean;
+  ctx->evs_table_clean = false;
+  EVIS_HIP(launch_stream_init(st, cursor, reset, capacity, clear, s), "k_stream_init");
+  EVIS_HIP(launch(), "k_events");
+  EVIS_HIP(launch_stream_fixup(st, out, capacity, cursor, s), "k_stream_fixup");
+  EVIS_HIP(launch_stream_clean(st, s), "k_stream_clean");
+  ctx->evs_table_clean = true;
   return EVIS_OK;
 }
 
@@ -970,13 +989,14 @@ int evis_generate_events_noise(evis_ctx* ctx, const float* L_seq, int32_t H, int
   unsigned long long* cursor = reinterpret_cast<unsigned long long*>(n_total);
   const int reset = (flags & EVIS_FLAG_RESET_CURSOR) ? 1 : 0;
   ProfScope ps(ctx, EVIS_KERNEL_EVENTS, s);
-  if (wave) EVIS_HIP(launch_stream_init(st, cursor, reset, capacity, s), "k_stream_init");
-  EVIS_HIP(launch_events(L_seq, H, W, K, t0_us, span, Dt, sensor->C_on, sensor->C_off,
+  auto launch = [&]() {
+    return launch_events(L_seq, H, W, K, t0_us, span, Dt, sensor->C_on, sensor->C_off,
                          sensor->theta_on, sensor->theta_off, sensor->refractory_us,
                          (uint32_t)env_id << 23, state->L_ref, state->t_last, out, capacity,
-                         cursor, reset, noisy ? &nc : nullptr, st, s),
-           "k_events");
-  if (wave) EVIS_HIP(launch_stream_fixup(st, out, capacity, cursor, s), "k_stream_fixup");
+                         cursor, reset, noisy ? &nc : nullptr, st, s);
+  };
+  if (wave) return with_stream(ctx, st, cursor, reset, out, capacity, s, launch);
+  EVIS_HIP(launch(), "k_events");
   return EVIS_OK;
 }
 
@@ -1064,10 +1084,10 @@ int evis_generate_events_batch(evis_ctx* ctx, const evis_frames* envs, int32_t n
   // the wave form through the sharded stream (which leaves the cursor at
   // its end), then the workgroup form at the cursor
   if (n_wave > 0) {
-    EVIS_HIP(launch_stream_init(st, cursor, reset, capacity, s), "k_stream_init");
-    EVIS_HIP(launch_events_batch(d_descs, d_prefix, n_wave, (int)blocks_wave, true, st, s),
-             "k_events_batch_wave");
-    EVIS_HIP(launch_stream_fixup(st, out, capacity, cursor, s), "k_stream_fixup");
+    rc = with_stream(ctx, st, cursor, reset, out, capacity, s, [&]() {
+      return launch_events_batch(d_descs, d_prefix, n_wave, (int)blocks_wave, true, st, s);
+    });
+    if (rc) return rc;
   } else if (reset) {
     EVIS_HIP(launch_zero_u64(cursor, s), "k_zero_u64");
   }

@@ -540,39 +540,54 @@ __global__ __launch_bounds__(kBlock) void k_events_batch(const EventArgs* __rest
 // The sharded stream of a call (evis_stream.h): set-up and fixup.
 // ---------------------------------------------------------------------------
 
-// Set-up: every stream empty, blocks 0 .. kAheadChunks - 1 of every stream
-// published (chunk s * kAheadChunks + k), the rest unpublished; the base is
-// the cursor (0 with reset).  gmax counts the chunks whose slots all have a
+// The chunk table is kept all unpublished between calls: the clean-up
+// kernel after each fixup resets the entries the call published, and a
+// table that may hold anything else (new, or after a call that did not
+// finish its launches) is cleared whole first.
+__global__ __launch_bounds__(kBlock) void k_stream_clear(const StreamState st) {
+  const long long n = (long long)kStreams * st.kmax;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride)
+    st.chunk_of[idx] = kChunkUnpublished;
+}
+
+// Set-up (one workgroup): every stream empty, blocks 0 .. kAheadChunks - 1
+// of every stream published (chunk s * kAheadChunks + k); the base is the
+// cursor (0 with reset).  gmax counts the chunks whose slots all have a
 // place: below `capacity` or within the spill buffer after it (the stream
 // of a call that fits the output needs at most T + kSpillEvents slots).
 __global__ __launch_bounds__(kBlock) void k_stream_init(const StreamState st,
                                                         unsigned long long* cursor, int reset,
                                                         long long capacity) {
   const long long base = reset ? 0 : (long long)*cursor;
-  // whole chunks only: every slot of chunk g < gmax lies below capacity + kSpillEvents
   const long long room = capacity > base ? capacity - base + kSpillEvents : 0;
-  const long long gm = room >> kStreamChunkLog;
-  const int gmax = (int)min(gm, (long long)0x7FFFFFFF);
-  const long long n = (long long)kStreams * st.kmax;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += stride) {
-    const int s = (int)(idx / st.kmax), k = (int)(idx % st.kmax);
-    int v = kChunkUnpublished;
-    if (k < kAheadChunks) {
-      const int g = s * kAheadChunks + k;
-      v = g < gmax ? g : kChunkDropped;
+  const int gmax = (int)min(room >> kStreamChunkLog, (long long)0x7FFFFFFF);
+  const int t = threadIdx.x;
+  if (t < kStreams * kAheadChunks) {
+    const int s = t / kAheadChunks, k = t % kAheadChunks;
+    const int g = s * kAheadChunks + k;
+    if (k < st.kmax) {
+      st.chunk_of[(long long)s * st.kmax + k] = g < gmax ? g : kChunkDropped;
       if (g < gmax) st.owner[g] = s | (k << 8);
     }
-    st.chunk_of[idx] = v;
   }
-  if (blockIdx.x == 0) {
-    if (threadIdx.x < kStreams) st.fill[threadIdx.x * kStreamLine] = 0ull;
-    if (threadIdx.x == 0) {
-      st.hdr->base = base;
-      st.hdr->nchunks = (unsigned int)(kStreams * kAheadChunks);
-      st.hdr->gmax = gmax;
-    }
+  if (t < kStreams) st.fill[t * kStreamLine] = 0ull;
+  if (t == 0) {
+    st.hdr->base = base;
+    st.hdr->nchunks = (unsigned int)(kStreams * kAheadChunks);
+    st.hdr->gmax = gmax;
   }
+}
+
+// Clean-up (after the fixup): stream s published blocks 0 .. e_s +
+// kAheadChunks - 1, e_s = ceil(fill_s / kStreamChunk) the blocks it entered.
+__global__ __launch_bounds__(kBlock) void k_stream_clean(const StreamState st) {
+  const int s = blockIdx.x;
+  const long long f = (long long)st.fill[s * kStreamLine];
+  const long long e = (f + kStreamChunk - 1) >> kStreamChunkLog;
+  const long long kend = min(e + kAheadChunks, (long long)st.kmax);
+  for (long long k = threadIdx.x; k < kend; k += blockDim.x)
+    st.chunk_of[(long long)s * st.kmax + k] = kChunkUnpublished;
 }
 
 // Fixup: move the events stored at or above L = min(base + T, capacity)
@@ -701,10 +716,18 @@ hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s) {
 }
 
 hipError_t launch_stream_init(const StreamState& st, unsigned long long* cursor, int reset,
-                              long long capacity, hipStream_t s) {
-  const long long n = (long long)kStreams * st.kmax;
-  hipLaunchKernelGGL(k_stream_init, dim3(grid_for(n, kBlock * 8)), dim3(kBlock), 0, s, st, cursor,
-                     reset, capacity);
+                              long long capacity, bool clear_table, hipStream_t s) {
+  static_assert(kStreams * kAheadChunks <= kBlock, "one workgroup publishes the first blocks");
+  if (clear_table) {
+    const long long n = (long long)kStreams * st.kmax;
+    hipLaunchKernelGGL(k_stream_clear, dim3(grid_for(n, kBlock * 8)), dim3(kBlock), 0, s, st);
+  }
+  hipLaunchKernelGGL(k_stream_init, dim3(1), dim3(kBlock), 0, s, st, cursor, reset, capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_clean(const StreamState& st, hipStream_t s) {
+  hipLaunchKernelGGL(k_stream_clean, dim3(kStreams), dim3(kBlock), 0, s, st);
   return hipGetLastError();
 }
 

@@ -148,7 +148,8 @@ hipError_t launch_state_init(const float* L_first, long long n, float* L_ref, in
 // The event model over one env's frames.  Without a refractory period and
 // noise it runs in the wave form, which writes through the call's sharded
 // stream `st` (set up by launch_stream_init before, finished by
-// launch_stream_fixup after); otherwise in the workgroup form, which
+// launch_stream_fixup and launch_stream_clean after); otherwise in the
+// workgroup form, which
 // appends at the cursor (reset first if asked).
 inline bool events_wave_form(int refr, bool noise) { return refr == 0 && !noise; }
 hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, int span,
@@ -160,7 +161,8 @@ hipError_t launch_events(const float* L_seq, int H, int W, int K, long long t0, 
                          const StreamState& st, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, hipStream_t s);   // a kernel, not a memset
 hipError_t launch_stream_init(const StreamState& st, unsigned long long* cursor, int reset,
-                              long long capacity, hipStream_t s);
+                              long long capacity, bool clear_table, hipStream_t s);
+hipError_t launch_stream_clean(const StreamState& st, hipStream_t s);   // after the fixup
 hipError_t launch_stream_fixup(const StreamState& st, evis_event* out, long long capacity,
                                unsigned long long* cursor, hipStream_t s);
 // The event model over caller frames (k_events): one env's arguments; the

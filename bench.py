@@ -83,6 +83,9 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="timed loop only (for profilers)")
     ap.add_argument("--variants", action="store_true",
                     help="timed loop and the variants only (for profilers)")
+    ap.add_argument("--only", type=str, default=None, choices=("events_batch", "small_motion"),
+                    help="timed loop and this one variant only (for profilers): the event model "
+                         "over every env's materialised samples, or the small-motion fused step")
     ap.add_argument("--warp-steps", type=int, default=10,
                     help="timed steps of each variant: two-splat warps, noise (0 skips them)")
     ap.add_argument("--disc-steps", type=int, default=200,
@@ -276,6 +279,9 @@ def cpu_baseline(specs):
 
 def main():
     args = parse()
+    if args.only:
+        args.variants = True
+    want = lambda name: args.only is None or args.only == name
     if args.traffic_from:
         traffic_from(args.traffic_from, args.tile_label or "32x16")
         return
@@ -427,13 +433,12 @@ def main():
 
     # the two-splat warps, and the gather warp with sensor noise, over the
     # first pairs of the same sequence and tile shape
-    warps = None
+    warps = {}
     n_var = max(0, min(args.warp_steps, S))
     var_pairs = timed_pairs[:n_var]
     Kv = Ks[:n_var]
     mpix_var = float((px[None, :] * Kv).sum()) / 1e6 / max(n_var, 1)
-    if n_var > 0:
-        warps = {}
+    if n_var > 0 and want("warps"):
         noise = dict(leak_rate_hz=0.1, shot_rate_hz=1.0, hot_rate_hz=100.0, hot_fraction=1e-3,
                      shot_L0=-7.0, shot_inv_range=0.1)
         for name, mode, nz in (("splat_b_primary", evis.EVIS_WARP_SPLAT | evis.EVIS_BLEND_B_PRIMARY,
@@ -467,7 +472,7 @@ def main():
 
     # defocus of every env's keyframe 1 (one batched launch, sigma 0.5 px):
     # HBM-bound, 8 algorithmic bytes per pixel (one read, one write)
-    if n_var > 0:
+    if n_var > 0 and want("defocus"):
         src = seq.I[1]
         blurred = torch.empty_like(src)
         views = [(seq.view(src, e), seq.view(blurred, e)) for e in range(n_envs)]
@@ -513,7 +518,7 @@ def main():
     # voxel grid (128 bins per polarity) of one 1280x720 env from the stream
     # of the first timed pair: HBM-bound, 8 algorithmic bytes per event read
     # and per voxel written
-    if n_var > 0:
+    if n_var > 0 and want("voxel"):
         seq.L_ref.copy_(R_start)
         n_total.zero_()
         step(timed_pairs[0])
@@ -544,7 +549,7 @@ def main():
     # 1280x720 env, the K + 1 samples of the first timed pair written by
     # evis_interpolate first), and the fused step with small motion (K <= 2,
     # one warped substep) over the timed pairs
-    if n_var > 0:
+    if n_var > 0 and want("generate_events"):
         ve = n_envs - 1
         vh, vw = seq.shapes[ve]
         i0 = timed_pairs[0]
@@ -576,6 +581,9 @@ def main():
                           frac=round(ggbs / HBM_PEAK_GBS, 4)))
         log(f"generate_events: {gms:.3f} ms, {ggbs:.0f} GB/s")
         del frames
+    if n_var > 0 and want("events_batch"):
+        i0 = timed_pairs[0]
+        vt0, vt1 = seq.times(i0)
         # the same form over every env's samples of that pair in one launch
         # (evis_generate_events_batch): Σ 4 (K + 1) px bytes of samples, the
         # reference read and written, 8 B per event
@@ -606,6 +614,7 @@ def main():
                           frac=round(bgbs / HBM_PEAK_GBS, 4)))
         log(f"generate_events batch of 64: {bms:.3f} ms, {bgbs:.0f} GB/s")
         del allf, items
+    if n_var > 0 and want("small_motion"):
         # small motion: the same scenes turned by at most 1 px per keyframe
         # at the image corners, motion noise N(0, 0.15^2) px, so the
         # adaptive K is at most 2 (the form whose bytes per pixel-substep
@@ -703,7 +712,7 @@ def main():
         per_env_plain=plain, per_env_fused=fused_per_env,
         batched_vs_plain=(round(value / plain["value"], 2) if plain else None),
         batched_vs_fused_per_env=(round(value / fused_per_env["value"], 2) if fused_per_env else None),
-        roofline=roof, cpu_baseline=cpu, variants=warps, disc512_sustained=disc,
+        roofline=roof, cpu_baseline=cpu, variants=warps or None, disc512_sustained=disc,
     )
     print(json.dumps(rec))
     ctx.close()

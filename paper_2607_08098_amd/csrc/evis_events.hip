@@ -771,17 +771,19 @@ __global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
   float* hb = smem + inW * inH;     // [inH][kDefTW]
   const int x0 = (lt % im.tiles_x) * kDefTW, y0 = (lt / im.tiles_x) * kDefTH;
   for (int k = threadIdx.x; k <= 2 * r; k += kBlock) s_w[k] = a.w[k];
-  // the apron tile, all threads at once, four loads in flight per thread;
-  // element i sits at (i % inW, i / inW), stepped by kBlock incrementally
+  // the apron tile, all threads at once, kDefLoads loads in flight per
+  // thread (one round trip for radii up to 4); element i sits at
+  // (i % inW, i / inW), stepped by kBlock incrementally
   {
+    constexpr int kDefLoads = 12;
     const int n = inW * inH;
     const int dx = kBlock % inW, dy = kBlock / inW;
     int lx = threadIdx.x % inW, ly = threadIdx.x / inW;
-    for (int i0 = threadIdx.x; i0 < n; i0 += 4 * kBlock) {
-      float v[4];
-      int idx[4];
+    for (int i0 = threadIdx.x; i0 < n; i0 += kDefLoads * kBlock) {
+      float v[kDefLoads];
+      int idx[kDefLoads];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kDefLoads; ++u) {
         idx[u] = i0 + u * kBlock;
         const int gx = min(max(x0 - r + lx, 0), W - 1);
         const int gy = min(max(y0 - r + ly, 0), H - 1);
@@ -794,7 +796,7 @@ __global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < kDefLoads; ++u)
         if (idx[u] < n) in[idx[u]] = v[u];
     }
   }

@@ -56,12 +56,14 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
   const int c0 = min(total, wid * chunk), c1 = min(total, c0 + chunk);
   constexpr int U = 2;   // groups in flight per wave
   const float inf = __int_as_float(0x7f800000);
-  // the env's largest |m|^2 seen by this wave, published when the env changes
+  // the env's largest |m|^2 seen by this lane; reduced over the wave and
+  // published when the env changes (wave-uniform calls)
   int run_env = -1;
   double run_msq = 0.0;
   auto publish = [&]() {
-    if (run_env >= 0 && run_msq > 0.0 && lane == 0)
-      atomicMax(&dyn[run_env].msq_bits, (unsigned long long)__double_as_longlong(run_msq));
+    const double m = wave_max_d(run_msq);
+    if (run_env >= 0 && m > 0.0 && lane == 0)
+      atomicMax(&dyn[run_env].msq_bits, (unsigned long long)__double_as_longlong(m));
   };
   // each wave walks a contiguous run of block groups (wave-uniform loop), U
   // groups at a time so that their loads overlap
@@ -121,7 +123,6 @@ __global__ __launch_bounds__(kBlock) void k_prep(const EnvDesc* __restrict__ env
       mxx = row16_max(mxx);
       mny = row16_min(mny);
       mxy = row16_max(mxy);
-      msq = wave_max_d(msq);
       if (r == 0 && has[u]) stg(d.tb, blk[u], make_float4(mnx, mxx, mny, mxy));
       if (e[u] != run_env) {   // wave-uniform
         publish();

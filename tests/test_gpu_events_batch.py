@@ -103,3 +103,68 @@ def test_generate_events_batch_errors_enqueue_nothing(torch, ctx):
         assert ei.value.code == code, bad
     torch.cuda.synchronize()
     assert int(n.item()) == 5
+
+
+def _items(torch, specs, t0=1000):
+    from paper_2607_08098_amd import evis
+    dev = "cuda"
+    items, want = [], []
+    for e, (H, W, K, seed, kind) in enumerate(specs):
+        frames, sensor, L_ref, t_last = make_case(H, W, K, seed, kind)
+        w, R, tl = o.emit_events(list(frames), t0, t0 + 16667, sensor, L_ref, t_last, env_id=20 + e)
+        want.append((w, R, tl))
+        d = dict(L_seq=torch.from_numpy(np.ascontiguousarray(frames)).to(dev), t0=t0, t1=t0 + 16667,
+                 env_id=20 + e, C_on=sensor.C_on, C_off=sensor.C_off,
+                 refractory_us=sensor.refractory_us, L_ref=torch.from_numpy(L_ref).to(dev))
+        if t_last is not None:
+            d["t_last"] = torch.from_numpy(t_last.copy()).to(dev)
+        if sensor.theta_on is not None:
+            d["theta_on"] = torch.from_numpy(sensor.theta_on).to(dev)
+            d["theta_off"] = torch.from_numpy(sensor.theta_off).to(dev)
+        items.append(d)
+    return items, want
+
+
+def test_generate_events_batch_overflow_appends_and_reset(torch, ctx):
+    """A batch appended after existing events (no reset): the union; the
+    same batch into a buffer too small for it: the count is whole, every
+    stored slot holds one of its events, the states still advance; a batch
+    of refractory envs only (no wave form) with the reset flag starts at 0;
+    K = 128, the largest substep count."""
+    from paper_2607_08098_amd import evis
+    specs = [(40, 70, 128, 811, None), (90, 70, 9, 812, "mismatch"), (33, 65, 7, 813, "refractory")]
+    items, want = _items(torch, specs)
+    total = sum(len(w[0]) for w in want)
+    out, n = evis.event_buffer(1 << 22)
+    say("batch appended after", 777, "events")
+    n.fill_(777)
+    evis.evis_generate_events_batch(ctx, items, out, n, flags=0)
+    torch.cuda.synchronize()
+    assert int(n.item()) == 777 + total
+    got = evis.decode_events(out[777:], torch.tensor([total], dtype=torch.int64))
+    assert U.same_multiset(got, np.concatenate([w[0] for w in want]))
+    for d, (w, R, tl) in zip(items, want):
+        assert np.array_equal(d["L_ref"].cpu().numpy().view(np.uint32), R.view(np.uint32))
+    # too small a buffer (fresh states)
+    items, want = _items(torch, specs)
+    cap = total // 2
+    out2, n2 = evis.event_buffer(cap)
+    say("batch into a buffer of", cap, "for", total)
+    evis.evis_generate_events_batch(ctx, items, out2, n2)
+    torch.cuda.synchronize()
+    assert int(n2.item()) == total
+    got = evis.decode_events(out2, n2)
+    assert len(got) == cap
+    wanted = set(map(tuple, np.concatenate([w[0] for w in want]).tolist()))
+    assert all(tuple(e) in wanted for e in got.tolist())
+    for d, (w, R, tl) in zip(items, want):
+        assert np.array_equal(d["L_ref"].cpu().numpy().view(np.uint32), R.view(np.uint32))
+    # refractory envs only, with reset
+    items, want = _items(torch, [(33, 65, 7, 814, "refractory"), (20, 20, 3, 815, "refractory")])
+    n.fill_(999)
+    say("batch of refractory envs with reset")
+    evis.evis_generate_events_batch(ctx, items, out, n)
+    torch.cuda.synchronize()
+    w_all = np.concatenate([w[0] for w in want])
+    assert int(n.item()) == len(w_all)
+    assert U.same_multiset(evis.decode_events(out, n), w_all)

@@ -43,14 +43,26 @@ __global__ __launch_bounds__(kBlock) void k_voxel_acc(const VoxelArgs a) {
 }
 
 // Per (polarity, bin) plane maximum: workgroup (chunk, plane) reduces a
-// chunk of the plane and raises the plane's maximum with one atomic.
+// chunk of the plane and raises the plane's maximum with one atomic.  When
+// the grid starts on 16 bytes and a plane is a whole number of 16-byte
+// groups (the chunks are, see launch_voxel) the chunk is read 16 bytes per
+// lane, four loads in flight.
 __global__ __launch_bounds__(kBlock) void k_voxel_max(const uint32_t* __restrict__ acc, long long plane,
                                                       long long chunk, uint32_t* maxbuf) {
   __shared__ uint32_t s_max[kWavesPerBlock];
   const uint32_t* pl = acc + (long long)blockIdx.y * plane;
   const long long i0 = (long long)blockIdx.x * chunk, i1 = min(plane, i0 + chunk);
   uint32_t m = 0u;
-  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) m = max(m, pl[i]);
+  if ((plane & 3) == 0 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0) {   // uniform
+    const uint4* p4 = reinterpret_cast<const uint4*>(pl);
+#pragma unroll 4
+    for (long long i = (i0 >> 2) + threadIdx.x; i < (i1 >> 2); i += kBlock) {
+      const uint4 v = p4[i];
+      m = max(m, max(max(v.x, v.y), max(v.z, v.w)));
+    }
+  } else {
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) m = max(m, pl[i]);
+  }
   for (int off = kWave / 2; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, kWave));
   if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = m;
   __syncthreads();
@@ -62,7 +74,8 @@ __global__ __launch_bounds__(kBlock) void k_voxel_max(const uint32_t* __restrict
 }
 
 // Each voxel divided by its plane's maximum, in place (uint32 sums in,
-// float32 out); workgroup (chunk, plane) as for the maxima.
+// float32 out); workgroup (chunk, plane) as for the maxima, 16 bytes per
+// lane when the plane allows.
 __global__ __launch_bounds__(kBlock) void k_voxel_div(uint32_t* __restrict__ acc, long long plane,
                                                       long long chunk, const uint32_t* maxbuf) {
   uint32_t* pl = acc + (long long)blockIdx.y * plane;
@@ -70,9 +83,20 @@ __global__ __launch_bounds__(kBlock) void k_voxel_div(uint32_t* __restrict__ acc
   const uint32_t mx = maxbuf[blockIdx.y];
   const float fm = (float)mx;
   const long long i0 = (long long)blockIdx.x * chunk, i1 = min(plane, i0 + chunk);
-  for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
-    const uint32_t v = pl[i];
-    out[i] = mx ? (float)v / fm : 0.0f;
+  if ((plane & 3) == 0 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0) {   // uniform
+    uint4* p4 = reinterpret_cast<uint4*>(pl);
+    float4* o4 = reinterpret_cast<float4*>(pl);
+#pragma unroll 4
+    for (long long i = (i0 >> 2) + threadIdx.x; i < (i1 >> 2); i += kBlock) {
+      const uint4 v = p4[i];
+      o4[i] = mx ? make_float4((float)v.x / fm, (float)v.y / fm, (float)v.z / fm, (float)v.w / fm)
+                 : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  } else {
+    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) {
+      const uint32_t v = pl[i];
+      out[i] = mx ? (float)v / fm : 0.0f;
+    }
   }
 }
 
@@ -90,8 +114,9 @@ hipError_t launch_voxel(const VoxelArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_voxel_acc, dim3(acc_blocks), dim3(kBlock), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // enough workgroups to fill the chip: chunks of at least 16 K voxels
-  const long long chunk = std::max<long long>(16384, (plane + 7) / 8);
+  // enough workgroups to fill the chip: chunks of at least 16 K voxels, a
+  // multiple of 4 (whole 16-byte groups)
+  const long long chunk = (std::max<long long>(16384, (plane + 7) / 8) + 3) & ~3LL;
   const int nchunks = (int)((plane + chunk - 1) / chunk);
   hipLaunchKernelGGL(k_voxel_max, dim3(nchunks, 2 * a.bins), dim3(kBlock), 0, s, a.acc, plane, chunk,
                      a.maxbuf);

@@ -96,6 +96,17 @@ __device__ __forceinline__ T ldg(const T* p, int idx) {
   return p[idx];
 #endif
 }
+// The same with a byte offset (a uniform base plus one 32-bit offset per
+// lane, no 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ T ldg_bytes(const T* p, uint32_t byte_off) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef const __attribute__((address_space(1))) char* gp;
+  return *(const __attribute__((address_space(1))) T*)((gp)p + byte_off);
+#else
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + byte_off);
+#endif
+}
 template <typename T>
 __device__ __forceinline__ void stg(T* p, int idx, T v) {
 #if defined(__HIP_DEVICE_COMPILE__)

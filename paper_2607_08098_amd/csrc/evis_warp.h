@@ -116,8 +116,9 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
   float4 rec[kChunk];   // A: (m_A.x, m_A.y, Z_A, Zend - Z_A); B: (-m_B.x, -m_B.y, Zstart, Z_B - Zstart)
   int src[kChunk];      // source index, -1 outside the image or for an empty slot
   int sx[kChunk], sy[kChunk];
-  // All loads first, unconditionally (a lane without a source reads record
-  // 0), so that they are in flight together.
+  // All loads first, unconditionally (a lane without a source reads a
+  // record of its block, or of block 0), so that they are in flight
+  // together.
 #pragma unroll
   for (int c = 0; c < kChunk; ++c) {
     const uint32_t e = blk[c];
@@ -128,7 +129,10 @@ __device__ __forceinline__ void splat_chunk(const EnvDesc& d, const uint32_t (&b
     // 24-bit products (full-rate v_mul_u32_u24): rows, columns and block
     // counts are below 2^12
     src[c] = ok ? (int)__umul24((unsigned)sy[c], (unsigned)d.W) + sx[c] : -1;
-    rec[c] = ldg(recs, ok ? ((int)__umul24((unsigned)by, (unsigned)d.ntx_src) + bx) * kBlkPx + r : 0);
+    // every candidate entry names a block of the env (an empty slot block
+    // 0), so the record is read unconditionally: one 32-bit byte offset
+    rec[c] = ldg_bytes(recs, ((__umul24((unsigned)by, (unsigned)d.ntx_src) + (unsigned)bx) *
+                              (unsigned)(kBlkPx * sizeof(float4))) + (unsigned)r * (unsigned)sizeof(float4));
   }
   // image pixel (x, y) has z-buffer cell y ZS + x - corg (the apron's first
   // cell is pixel (Tx0 - 1, Ty0 - 1))

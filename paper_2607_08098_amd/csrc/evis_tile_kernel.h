@@ -195,9 +195,12 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
     }
 
     // Static tile: every source that can reach it does not move, it does not
-    // move in B and L_A == L_B on it, so every sub-frame equals L_A.
+    // move in B and L_A == L_B on it, so every sub-frame equals L_A.  (The
+    // test costs a round of loads and a barrier; with one or two warped
+    // substeps it is not worth them, and the full path gives the same
+    // sub-frames.)
     bool is_static = false;
-    if (MODE == MODE_STEP && kGather && a.static_tiles && K > 1 && !overflow) {
+    if (MODE == MODE_STEP && kGather && a.static_tiles && K > 3 && !overflow) {
       bool okst = true;
       for (int e2 = tid; e2 < nlist; e2 += kBlock) {
         const uint32_t ent = list[e2];

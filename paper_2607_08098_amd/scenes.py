@@ -493,3 +493,21 @@ class PlaneScene:
         m_next = np.stack([xx - nxt[0], yy - nxt[1]], -1).astype(F32) if k + 1 < len(self.cam) else None
         m_prev = np.stack([prv[0] - xx, prv[1] - yy], -1).astype(F32) if k > 0 else None
         return img.astype(F32), m_next, m_prev, np.where(np.isfinite(Z), Z, 8.0).astype(F32)
+
+
+def render_keyframes(scene: "PlaneScene", ks, threads: int = 16) -> list:
+    """scene.keyframe(k) for every k of ks, on `threads` Python threads.
+
+    The ray casts are small matrix products.  Multithreaded OpenBLAS called
+    from several Python threads at once has returned different motion
+    fields from one call to the next, so the threads run with BLAS held to
+    one thread each (a product's elements are the same dot products at any
+    thread count, so the frames equal those of a sequential rendering)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ks = list(ks)
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:   # without it: one at a time
+        return [scene.keyframe(k) for k in ks]
+    with threadpool_limits(1), ThreadPoolExecutor(max(1, threads)) as pool:
+        return list(pool.map(scene.keyframe, ks))

@@ -303,10 +303,11 @@ def test_planes_chained_mismatch_refractory(torch, ctx, golden):
     g = case_digests(golden, "planes640")
     H, W, n_pairs = F.PLANES_H, F.PLANES_W, F.PLANES_PAIRS
     assert len(g["pairs"]) == n_pairs
-    say("planes 640x480: render", n_pairs + 1, "keyframes")
+    say("planes 640x480: render", n_pairs + 1, "keyframes; tuning",
+        evis.evis_get_tuning(ctx).as_dict())
     sc = scenes.PlaneScene(H, W, F.PLANES_SEED, n_pairs)
+    kf = scenes.render_keyframes(sc, range(n_pairs + 1), threads=16)
     with ThreadPoolExecutor(16) as pool:
-        kf = list(pool.map(lambda k: sc.keyframe(k), range(n_pairs + 1)))
         L = list(pool.map(lambda k: F.log_intensity(k[0]), kf))
     on, off = F.planes_thresholds()
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()

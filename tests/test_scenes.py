@@ -33,3 +33,17 @@ def test_generators_are_seeded():
     d1 = scenes.disc_pair(26, 34, 11, step=3)
     d2 = scenes.disc_pair(26, 34, 11, step=3)
     assert np.array_equal(d1["I_B"], d2["I_B"])
+
+
+def test_threaded_plane_keyframes_equal_sequential():
+    """render_keyframes on several threads returns the frames of one-at-a-time
+    rendering, bit for bit (multithreaded BLAS entered from several Python
+    threads at once has not)."""
+    sc = scenes.PlaneScene(480, 640, 2000, 40)   # full size: BLAS runs threaded
+    ks = list(range(20, 36))
+    ref = [sc.keyframe(k) for k in ks]
+    for _ in range(2):
+        got = scenes.render_keyframes(sc, ks, threads=16)
+        for a, b in zip(ref, got):
+            for x, y in zip(a, b):
+                assert (x is None and y is None) or np.array_equal(x.view(np.uint32), y.view(np.uint32))

@@ -105,6 +105,29 @@ def test_defocus_batch(torch, ctx):
             assert ok, (x.shape, info)
 
 
+@pytest.mark.parametrize("sigma", [0.5, 2.0])
+def test_defocus_batch_full_frames(torch, ctx, sigma):
+    """The benchmark's 64 images in one launch (24 x 346x260, 24 x 640x480,
+    16 x 1280x720: 12256 tiles, dealt to the XCDs in runs of consecutive
+    tiles that cross image boundaries; sigma 2 needs more than one round of
+    apron loads per thread), every image against the oracle."""
+    from paper_2607_08098_amd import evis
+    rng = np.random.default_rng(11)
+    shapes = [(260, 346)] * 24 + [(480, 640)] * 24 + [(720, 1280)] * 16
+    xs = [(10.0 ** rng.uniform(-2, 2, size=s)).astype(F32) for s in shapes]
+    pairs = [(torch.from_numpy(x).cuda(), None) for x in xs]
+    pairs = [(xd, torch.empty_like(xd)) for xd, _ in pairs]
+    say("defocus batch of 64 full frames, sigma", sigma)
+    evis.evis_defocus_batch(ctx, pairs, sigma)
+    torch.cuda.synchronize()
+    r = o.defocus_radius(sigma)
+    for x, (_, od) in zip(xs, pairs):
+        got = od.cpu().numpy().astype(np.float64)
+        want = o.defocus(x.astype(np.float64), sigma)
+        ok, info = within_bound(got, want, x, r)
+        assert ok, (x.shape, sigma, info)
+
+
 def test_defocus_argument_errors(torch, ctx):
     from paper_2607_08098_amd import evis
     x = torch.ones(8, 9, device="cuda")

@@ -121,6 +121,27 @@ def test_voxel_grid_matches_oracle(torch, ctx, bins, window):
     assert undetermined <= max(1, (2 * 2 * bins) // 100), undetermined
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_voxel_grid_unaligned_output(torch, ctx, shift):
+    """A grid that starts `shift` words past a 16-byte boundary (the zero
+    fill's word head and tail, the per-plane passes' word paths) equals the
+    grid written to an aligned buffer, bit for bit, and no word outside it
+    is written."""
+    from paper_2607_08098_amd import evis
+    out, n = stream_of_two_envs(torch, ctx)
+    for env, (H, W) in ((3, (60, 80)), (4, (45, 70))):
+        for bins in (5, 128):
+            say("voxel grid unaligned", shift, env, bins)
+            ref = evis.evis_voxel_grid(ctx, out, n, env, H, W, 100000, 116667, bins)
+            m = 2 * bins * H * W
+            big = torch.full((m + 8,), -7.0, dtype=torch.float32, device="cuda")
+            view = big[shift:shift + m].view(2, bins, H, W)
+            evis.evis_voxel_grid(ctx, out, n, env, H, W, 100000, 116667, bins, out=view)
+            torch.cuda.synchronize()
+            assert torch.equal(view, ref)
+            assert bool((big[:shift] == -7.0).all()) and bool((big[shift + m:] == -7.0).all())
+
+
 def test_voxel_grid_full_voxel_limit(torch, ctx):
     """65535 events on one bin centre of one voxel (the most a voxel holds
     at full weight before its uint32 sum wraps), plus a few elsewhere: the

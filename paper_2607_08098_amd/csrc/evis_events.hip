@@ -752,10 +752,16 @@ int defocus_tiles(int H, int W, int* tiles_x) {
   return *tiles_x * ((H + kDefTH - 1) / kDefTH);
 }
 
+// R > 0: the radius, fixed at compile time (taps unrolled, weights from the
+// kernel arguments in scalar registers); R = 0: any radius, a.r, weights
+// from LDS.  Pixel (x, y), channel c is element (y W + x) C + c, below
+// 2^26 (H, W <= 4096, C <= 3): 32-bit indices and 24-bit products.
+template <int R>
 __global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
   extern __shared__ float smem[];
-  __shared__ float s_w[2 * kDefocusMaxR + 1];
-  const int r = a.r, C = a.C, c = blockIdx.y;
+  __shared__ float s_w[R > 0 ? 1 : 2 * kDefocusMaxR + 1];
+  const int r = R > 0 ? R : a.r;
+  const int C = a.C, c = blockIdx.y;
   // Workgroups go to the XCDs in turn (workgroup b to XCD b % kXcd), and
   // each XCD has its own L2: workgroup b takes tile (b % kXcd) * per +
   // b / kXcd, so that each XCD works through one run of consecutive tiles
@@ -780,61 +786,88 @@ __global__ __launch_bounds__(kBlock) void k_defocus(const DefocusArgs a) {
   float* in = smem;                 // [inH][inW]
   float* hb = smem + inW * inH;     // [inH][kDefTW]
   const int x0 = (lt % im.tiles_x) * kDefTW, y0 = (lt / im.tiles_x) * kDefTH;
-  for (int k = threadIdx.x; k <= 2 * r; k += kBlock) s_w[k] = a.w[k];
-  // the apron tile, all threads at once, kDefLoads loads in flight per
-  // thread (one round trip for radii up to 4); element i sits at
-  // (i % inW, i / inW), stepped by kBlock incrementally
-  {
-    constexpr int kDefLoads = 12;
-    const int n = inW * inH;
-    const int dx = kBlock % inW, dy = kBlock / inW;
-    int lx = threadIdx.x % inW, ly = threadIdx.x / inW;
-    for (int i0 = threadIdx.x; i0 < n; i0 += kDefLoads * kBlock) {
-      float v[kDefLoads];
-      int idx[kDefLoads];
+  const unsigned rowC = (unsigned)(W * C);   // elements per image row
+  if (R == 0)
+    for (int k = threadIdx.x; k <= 2 * r; k += kBlock) s_w[k] = a.w[k];
+  auto wt = [&](int k) { return R > 0 ? a.w[k] : s_w[k]; };
+  // Lane l of every wave owns column l of the tile (kDefTW = kWave): its
+  // apron columns l and, for l < 2r, kDefTW + l, and output column l.
+  static_assert(kDefTW == kWave && kDefTH == kWavesPerBlock * 8, "defocus tile: one column per lane");
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const bool two = lane < 2 * r;   // 2r <= 60 < 64
+  const unsigned ca = __umul24((unsigned)min(max(x0 - r + lane, 0), W - 1), (unsigned)C) + (unsigned)c;
+  const unsigned cb = __umul24((unsigned)min(max(x0 - r + kDefTW + lane, 0), W - 1), (unsigned)C) + (unsigned)c;
+  // The apron: wave w loads rows w, w + 4, ... (a row's source row and
+  // offset are uniform), kDefRows rows per pass with all loads in flight
+  // (one pass for radii up to 4).
+  constexpr int kDefRows = 10;
+  for (int row0 = wave; row0 < inH; row0 += kDefRows * kWavesPerBlock) {
+    float va[kDefRows], vb[kDefRows];
 #pragma unroll
-      for (int u = 0; u < kDefLoads; ++u) {
-        idx[u] = i0 + u * kBlock;
-        const int gx = min(max(x0 - r + lx, 0), W - 1);
-        const int gy = min(max(y0 - r + ly, 0), H - 1);
-        v[u] = (idx[u] < n) ? im.x[((long long)gy * W + gx) * C + c] : 0.0f;
-        lx += dx;
-        ly += dy;
-        if (lx >= inW) {
-          lx -= inW;
-          ++ly;
-        }
+    for (int u = 0; u < kDefRows; ++u) {
+      const int row = row0 + u * kWavesPerBlock;
+      const unsigned base = __umul24((unsigned)min(max(y0 - r + row, 0), H - 1), rowC);
+      va[u] = vb[u] = 0.0f;
+      if (row < inH) {   // uniform
+        va[u] = ldg(im.x, (int)(base + ca));
+        if (two) vb[u] = ldg(im.x, (int)(base + cb));
       }
+    }
 #pragma unroll
-      for (int u = 0; u < kDefLoads; ++u)
-        if (idx[u] < n) in[idx[u]] = v[u];
+    for (int u = 0; u < kDefRows; ++u) {
+      const int row = row0 + u * kWavesPerBlock;
+      if (row < inH) {
+        in[row * inW + lane] = va[u];
+        if (two) in[row * inW + kDefTW + lane] = vb[u];
+      }
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kDefTW * inH; i += kBlock) {
-    const int col = i % kDefTW, row = i / kDefTW;
-    const float* src = in + row * inW + col;
+  // horizontal pass: every apron row, wave w rows w, w + 4, ...
+  for (int row = wave; row < inH; row += kWavesPerBlock) {
+    const float* src = in + row * inW + lane;
     float acc = 0.0f;
-    for (int k = 0; k <= 2 * r; ++k) acc = acc + s_w[k] * src[k];
-    hb[i] = acc;
+    if constexpr (R > 0) {
+#pragma unroll
+      for (int k = 0; k <= 2 * R; ++k) acc = acc + wt(k) * src[k];
+    } else {
+      for (int k = 0; k <= 2 * r; ++k) acc = acc + wt(k) * src[k];
+    }
+    hb[row * kDefTW + lane] = acc;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kDefTW * kDefTH; i += kBlock) {
-    const int col = i % kDefTW, row = i / kDefTW;
-    const int gx = x0 + col, gy = y0 + row;
-    if (gx >= W || gy >= H) continue;
-    const float* src = hb + row * kDefTW + col;
+  // vertical pass: wave w output rows 8w .. 8w + 7 (uniform row tests)
+  const int gx = x0 + lane;
+  const unsigned cx = __umul24((unsigned)gx, (unsigned)C) + (unsigned)c;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int row = wave * 8 + j, gy = y0 + row;
+    if (gy >= H) break;   // uniform
+    const float* src = hb + row * kDefTW + lane;
     float acc = 0.0f;
-    for (int k = 0; k <= 2 * r; ++k) acc = acc + s_w[k] * src[k * kDefTW];
-    im.out[((long long)gy * W + gx) * C + c] = acc;
+    if constexpr (R > 0) {
+#pragma unroll
+      for (int k = 0; k <= 2 * R; ++k) acc = acc + wt(k) * src[k * kDefTW];
+    } else {
+      for (int k = 0; k <= 2 * r; ++k) acc = acc + wt(k) * src[k * kDefTW];
+    }
+    if (gx < W) stg(im.out, (int)(__umul24((unsigned)gy, rowC) + cx), acc);
   }
 }
 
 hipError_t launch_defocus(const DefocusArgs& a, hipStream_t s) {
   const int inW = kDefTW + 2 * a.r, inH = kDefTH + 2 * a.r;
   const size_t lds = (size_t)(inW * inH + kDefTW * inH) * sizeof(float);
-  const int grid = (a.tile_prefix[a.n] + kXcd - 1) / kXcd * kXcd;   // see k_defocus
-  hipLaunchKernelGGL(k_defocus, dim3(grid, a.C), dim3(kBlock), lds, s, a);
+  const dim3 grid((a.tile_prefix[a.n] + kXcd - 1) / kXcd * kXcd, a.C);   // see k_defocus
+  switch (a.r) {   // sigma <= 2 (the usual range) unrolled
+    case 1: hipLaunchKernelGGL(k_defocus<1>, grid, dim3(kBlock), lds, s, a); break;
+    case 2: hipLaunchKernelGGL(k_defocus<2>, grid, dim3(kBlock), lds, s, a); break;
+    case 3: hipLaunchKernelGGL(k_defocus<3>, grid, dim3(kBlock), lds, s, a); break;
+    case 4: hipLaunchKernelGGL(k_defocus<4>, grid, dim3(kBlock), lds, s, a); break;
+    case 5: hipLaunchKernelGGL(k_defocus<5>, grid, dim3(kBlock), lds, s, a); break;
+    case 6: hipLaunchKernelGGL(k_defocus<6>, grid, dim3(kBlock), lds, s, a); break;
+    default: hipLaunchKernelGGL(k_defocus<0>, grid, dim3(kBlock), lds, s, a); break;
+  }
   return hipGetLastError();
 }
 

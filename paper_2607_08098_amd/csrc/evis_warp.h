@@ -257,6 +257,22 @@ __device__ __forceinline__ bool superblock_reaches(const EnvDesc& d, int sx, int
            (float)Sy1 - fminf(b.z, 0.0f) <= (float)(Ty0 - 2));
 }
 
+// The window of source blocks that can reach target tile [Tx0,Tx1]x[Ty0,Ty1]
+// (the env's largest motion around it); its last block column and row in
+// wx1, wy1.
+__device__ __forceinline__ void candidate_window(const EnvDesc& d, const EnvDyn& dy, int Tx0,
+                                                 int Tx1, int Ty0, int Ty1, Window& w, int& wx1,
+                                                 int& wy1) {
+  const double M = __longlong_as_double((long long)dy.msq_bits);
+  const int Rw = (M > 1.0e12) ? (1 << 20) : ((int)ceil(sqrt(M)) + 3);
+  w.wx0 = max(0, Tx0 - Rw) / kSrcBlk;
+  w.wy0 = max(0, Ty0 - Rw) / kSrcBlk;
+  wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, d.W - 1) / kSrcBlk);
+  wy1 = min(d.nty_src - 1, min(Ty1 + Rw, d.H - 1) / kSrcBlk);
+  w.nwx = wx1 - w.wx0 + 1;
+  w.nwin = w.nwx * (wy1 - w.wy0 + 1);
+}
+
 // Candidate source blocks of target tile [Tx0,Tx1]x[Ty0,Ty1] and the substeps
 // during which each can reach it, appended to the LDS list (at most cap
 // entries, see cand_entry).  *count must be zero on entry; returns the
@@ -272,15 +288,8 @@ __device__ __forceinline__ int build_candidates(const EnvDesc& d, const EnvDyn& 
                                                 uint32_t* list, int* count, int cap, Window& w,
                                                 int* sb_list = nullptr, int* sb_count = nullptr) {
   const int tid = threadIdx.x;
-  const int W = d.W, H = d.H;
-  const double M = __longlong_as_double((long long)dy.msq_bits);
-  const int Rw = (M > 1.0e12) ? (1 << 20) : ((int)ceil(sqrt(M)) + 3);
-  w.wx0 = max(0, Tx0 - Rw) / kSrcBlk;
-  w.wy0 = max(0, Ty0 - Rw) / kSrcBlk;
-  const int wx1 = min(d.ntx_src - 1, min(Tx1 + Rw, W - 1) / kSrcBlk);
-  const int wy1 = min(d.nty_src - 1, min(Ty1 + Rw, H - 1) / kSrcBlk);
-  w.nwx = wx1 - w.wx0 + 1;
-  w.nwin = w.nwx * (wy1 - w.wy0 + 1);
+  int wx1, wy1;
+  candidate_window(d, dy, Tx0, Tx1, Ty0, Ty1, w, wx1, wy1);
   auto test_block = [&](int bx, int by) {
     int jlo, jhi;
     if (block_range(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi)) {
@@ -394,18 +403,21 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
       }
     }
   } else {
-    // Window scan: the candidate list did not fit.  Four blocks per pass.
-    for (int i0 = wave * 4; i0 < w.nwin; i0 += 4 * kWavesPerBlock) {
-      const int i = i0 + g;
+    // Window scan (the candidate list did not fit, or was not built): each
+    // pass of a wave tests and splats 4 kChunk blocks of the window.
+    for (int i0 = wave * 4 * kChunk; i0 < w.nwin; i0 += 4 * kChunk * kWavesPerBlock) {
       uint32_t blk[kChunk];
 #pragma unroll
-      for (int c = 0; c < kChunk; ++c) blk[c] = 0u;
-      if (i < w.nwin) {
-        const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
-        int jlo, jhi;
-        if (block_range<DIR == DIR_B>(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && jz >= jlo &&
-            j <= jhi)
-          blk[0] = cand_entry(bx, by, jlo, jhi);
+      for (int c = 0; c < kChunk; ++c) {
+        const int i = i0 + c * 4 + g;
+        blk[c] = 0u;
+        if (i < w.nwin) {
+          const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
+          int jlo, jhi;
+          if (block_range<DIR == DIR_B>(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && jz >= jlo &&
+              j <= jhi)
+            blk[c] = cand_entry(bx, by, jlo, jhi);
+        }
       }
       splat_chunk<TW, NF, DIR>(d, blk, fs, nf, Tx0, Tx1, Ty0, Ty1, zs);
     }

@@ -310,6 +310,28 @@ def test_step_config1(torch, ctx):
     assert got[1] > 1000
 
 
+@pytest.mark.parametrize("shape,seed,flow,omega", [((96, 130), 31, "rotate", 12.0),
+                                                   ((37, 53), 32, "translate", None),
+                                                   ((200, 260), 33, "rotate", 40.0)])
+def test_one_warped_substep(torch, ctx, shape, seed, flow, omega):
+    """K = 2 (one warped substep, the small-motion case): the sub-frames and
+    the fused step's events and reference level against the oracle, bit
+    for bit, on ragged multi-tile frames, one with motion of tens of
+    pixels."""
+    H, W = shape
+    kw = dict(flow=flow, omega=omega) if flow == "rotate" else dict(flow=flow)
+    pair = U.oracle_pair(U.blob_scene(H, W, seed, **kw))
+    say("one warped substep", shape, flow, omega)
+    want_L, want_h = o.interpolate(pair, 2, 0, 3)
+    got_L, got_h = run_interp(torch, ctx, pair, 2, 0, 3, o.BLEND_TIME)
+    check_interp(got_L, got_h, want_L, want_h, (shape, "K=2"))
+    s = o.Sensor(C_on=0.1, C_off=0.1, K=2)
+    args = ([pair], [s], [pair.L_A.copy()], [None], [3])
+    got = run_step(torch, ctx, *args)
+    check_step(got, oracle_steps(*args))
+    assert got[1] > 100
+
+
 def test_step_mixed_small_batch(torch, ctx):
     """Envs of uneven size, K, blend mode, mismatch and refractory in one launch."""
     from paper_2607_08098_amd import scenes

@@ -590,13 +590,16 @@ def main():
         # (evis_generate_events_batch): Σ 4 (K + 1) px bytes of samples, the
         # reference read and written, 8 B per event
         Kp = Ks[0]
-        offs = np.concatenate([[0], np.cumsum((Kp + 1) * px)])
+        # each env's samples start on 256 bytes, as separate allocations
+        # would (packed back to back, most planes would straddle lines)
+        sizes = (Kp + 1) * px
+        offs = np.concatenate([[0], np.cumsum((sizes + 63) // 64 * 64)])
         allf = torch.empty(int(offs[-1]), dtype=torch.float32, device="cuda")
         dicts = seq.env_dicts(i0, sensor)
         items = []
         for e, d in enumerate(dicts):
             H, W = seq.shapes[e]
-            fr = allf[int(offs[e]):int(offs[e + 1])].view(int(Kp[e]) + 1, H, W)
+            fr = allf[int(offs[e]):int(offs[e]) + int(sizes[e])].view(int(Kp[e]) + 1, H, W)
             evis.evis_interpolate(ctx, d, int(Kp[e]), 0, int(Kp[e]) + 1, evis.EVIS_BLEND_TIME,
                                   L_out=fr, want_holes=False)
             items.append(dict(L_seq=fr, t0=vt0, t1=vt1, env_id=e, C_on=0.2, C_off=0.2,
@@ -607,10 +610,10 @@ def main():
         bstep(i0)
         bms, bl, bev = replay_timed(bstep, [i0] * args.warp_steps, kind=evis.EVIS_KERNEL_EVENTS)
         bev /= max(bl, 1)
-        bbytes = 4.0 * float(offs[-1]) + 8.0 * float(px.sum()) + 8.0 * bev
+        bbytes = 4.0 * float(sizes.sum()) + 8.0 * float(px.sum()) + 8.0 * bev
         bgbs = bbytes / (bms / 1e3) / 1e9
         warps["generate_events_batch64"] = dict(
-            kernel_ms=round(bms, 4), samples_GB=round(4.0 * float(offs[-1]) / 1e9, 3),
+            kernel_ms=round(bms, 4), samples_GB=round(4.0 * float(sizes.sum()) / 1e9, 3),
             events=round(bev),
             roofline=dict(bound="hbm", achieved=round(bgbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(bgbs / HBM_PEAK_GBS, 4)))

@@ -3,8 +3,8 @@
 // spread over two neighbouring time bins by linear interpolation, in 16-bit
 // fixed point so that the sums are integers (uint32 atomics, exact and
 // independent of order), then each (polarity, bin) plane is divided by its
-// maximum.  HBM-bound: one pass over the event stream, a fill, a read for
-// the plane maxima and a read-write pass over the grid.
+// maximum.  HBM-bound: a fill, one pass over the event stream (which also
+// finds the plane maxima) and a read-write pass over the grid.
 #include "evis_internal.h"
 
 namespace evis {
@@ -16,7 +16,14 @@ __global__ __launch_bounds__(kBlock) void k_voxel_fill(uint32_t* __restrict__ ac
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) acc[i] = 0u;
 }
 
+// The accumulation also finds each plane's maximum: a voxel's sums only
+// grow, so the largest sum an add returns is the plane's final maximum.
+// Each workgroup keeps its planes' maxima in LDS and raises the global
+// ones once at its end.
 __global__ __launch_bounds__(kBlock) void k_voxel_acc(const VoxelArgs a) {
+  extern __shared__ uint32_t s_pmax[];   // [2 * bins]
+  for (int i = threadIdx.x; i < 2 * a.bins; i += kBlock) s_pmax[i] = 0u;
+  __syncthreads();
   const long long n = min((long long)*a.n_events, a.capacity);
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long plane = (long long)a.H * a.W;
@@ -36,46 +43,21 @@ __global__ __launch_bounds__(kBlock) void k_voxel_acc(const VoxelArgs a) {
     } else {
       q1 = (uint32_t)floorf((tau - (float)b) * 65536.0f);
     }
-    uint32_t* base = a.acc + ((long long)(p * a.bins + b) * plane + (long long)y * a.W + x);
-    atomicAdd(base, kVoxelOne - q1);
-    if (q1) atomicAdd(base + plane, q1);
+    const int pl = p * a.bins + b;
+    uint32_t* base = a.acc + ((long long)pl * plane + (long long)y * a.W + x);
+    const uint32_t w0 = kVoxelOne - q1;
+    atomicMax(&s_pmax[pl], atomicAdd(base, w0) + w0);
+    if (q1) atomicMax(&s_pmax[pl + 1], atomicAdd(base + plane, q1) + q1);
   }
-}
-
-// Per (polarity, bin) plane maximum: workgroup (chunk, plane) reduces a
-// chunk of the plane and raises the plane's maximum with one atomic.  When
-// the grid starts on 16 bytes and a plane is a whole number of 16-byte
-// groups (the chunks are, see launch_voxel) the chunk is read 16 bytes per
-// lane, four loads in flight.
-__global__ __launch_bounds__(kBlock) void k_voxel_max(const uint32_t* __restrict__ acc, long long plane,
-                                                      long long chunk, uint32_t* maxbuf) {
-  __shared__ uint32_t s_max[kWavesPerBlock];
-  const uint32_t* pl = acc + (long long)blockIdx.y * plane;
-  const long long i0 = (long long)blockIdx.x * chunk, i1 = min(plane, i0 + chunk);
-  uint32_t m = 0u;
-  if ((plane & 3) == 0 && (reinterpret_cast<uintptr_t>(acc) & 15) == 0) {   // uniform
-    const uint4* p4 = reinterpret_cast<const uint4*>(pl);
-#pragma unroll 4
-    for (long long i = (i0 >> 2) + threadIdx.x; i < (i1 >> 2); i += kBlock) {
-      const uint4 v = p4[i];
-      m = max(m, max(max(v.x, v.y), max(v.z, v.w)));
-    }
-  } else {
-    for (long long i = i0 + threadIdx.x; i < i1; i += kBlock) m = max(m, pl[i]);
-  }
-  for (int off = kWave / 2; off >= 1; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) s_max[threadIdx.x / kWave] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t mx = 0u;
-    for (int k = 0; k < kWavesPerBlock; ++k) mx = max(mx, s_max[k]);
-    if (mx) atomicMax(maxbuf + blockIdx.y, mx);
-  }
+  for (int i = threadIdx.x; i < 2 * a.bins; i += kBlock)
+    if (s_pmax[i]) atomicMax(a.maxbuf + i, s_pmax[i]);
 }
 
 // Each voxel divided by its plane's maximum, in place (uint32 sums in,
-// float32 out); workgroup (chunk, plane) as for the maxima, 16 bytes per
-// lane when the plane allows.
+// float32 out); workgroup (chunk, plane) reads a chunk of a plane, 16
+// bytes per lane when the grid starts on 16 bytes and a plane is a whole
+// number of 16-byte groups (the chunks are, see launch_voxel).
 __global__ __launch_bounds__(kBlock) void k_voxel_div(uint32_t* __restrict__ acc, long long plane,
                                                       long long chunk, const uint32_t* maxbuf) {
   uint32_t* pl = acc + (long long)blockIdx.y * plane;
@@ -111,17 +93,13 @@ hipError_t launch_voxel(const VoxelArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int acc_blocks = (int)std::max<long long>(1, std::min<long long>((a.capacity + kBlock - 1) / kBlock, 256LL * 8));
-  hipLaunchKernelGGL(k_voxel_acc, dim3(acc_blocks), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL(k_voxel_acc, dim3(acc_blocks), dim3(kBlock), 2 * a.bins * sizeof(uint32_t), s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // enough workgroups to fill the chip: chunks of at least 16 K voxels, a
   // multiple of 4 (whole 16-byte groups)
   const long long chunk = (std::max<long long>(16384, (plane + 7) / 8) + 3) & ~3LL;
   const int nchunks = (int)((plane + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_voxel_max, dim3(nchunks, 2 * a.bins), dim3(kBlock), 0, s, a.acc, plane, chunk,
-                     a.maxbuf);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_voxel_div, dim3(nchunks, 2 * a.bins), dim3(kBlock), 0, s, a.acc, plane, chunk,
                      a.maxbuf);
   return hipGetLastError();

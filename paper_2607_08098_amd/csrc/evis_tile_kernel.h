@@ -372,8 +372,10 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
           const int nf = (j + 1 <= j_int_last) ? 2 : 1;
           const float fs[2] = {f, (float)(j + 1) / (float)K};
           unsigned long long* const zs[2] = {zb, zbuf + ((j + 1) & 3) * ZN};
-          splat_candidates<TW, 2>(d, list, nlist, overflow, win, K, j, nf, fs, Tx0, Tx1, Ty0,
-                                  Ty1, s_wl[wave], zs);
+          // (three blocks per lane group per window-scan pass in the plain
+          // step; the noise kernel, at its register limit, scans one)
+          splat_candidates<TW, 2, DIR_A, (NOISE == 0 ? kChunk : 1)>(
+              d, list, nlist, overflow, win, K, j, nf, fs, Tx0, Tx1, Ty0, Ty1, s_wl[wave], zs);
           __syncthreads();
           if (MODE == MODE_STEP) sink_check(sh, so, sr);
         }

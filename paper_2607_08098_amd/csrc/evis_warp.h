@@ -370,7 +370,7 @@ __device__ __forceinline__ void build_candidates_two(const EnvDesc& d, const Env
 // 64-entry LDS slice `wl` and splats them four blocks (one per lane group)
 // per slot.  Entry e sits at list[lbase + lstep * e] (lstep = -1 for the
 // backward splat's entries at the back of a shared list).
-template <int TW, int NF, int DIR = DIR_A>
+template <int TW, int NF, int DIR = DIR_A, int SCAN = 1>
 __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_t* list, int nlist,
                                                  bool overflow, const Window& w, int K, int j,
                                                  int nf, const float (&fs)[NF], int Tx0, int Tx1,
@@ -403,15 +403,18 @@ __device__ __forceinline__ void splat_candidates(const EnvDesc& d, const uint32_
       }
     }
   } else {
-    // Window scan (the candidate list did not fit, or was not built): each
-    // pass of a wave tests and splats 4 kChunk blocks of the window.
-    for (int i0 = wave * 4 * kChunk; i0 < w.nwin; i0 += 4 * kChunk * kWavesPerBlock) {
+    // Window scan (the candidate list did not fit): each pass of a wave
+    // tests and splats 4 SCAN blocks of the window (SCAN <= kChunk slots of
+    // the chunk; more slots take more registers, which the kernels at
+    // their register limit pay for in spills).
+    static_assert(SCAN >= 1 && SCAN <= kChunk, "window scan slots");
+    for (int i0 = wave * 4 * SCAN; i0 < w.nwin; i0 += 4 * SCAN * kWavesPerBlock) {
       uint32_t blk[kChunk];
 #pragma unroll
       for (int c = 0; c < kChunk; ++c) {
         const int i = i0 + c * 4 + g;
         blk[c] = 0u;
-        if (i < w.nwin) {
+        if (c < SCAN && i < w.nwin) {
           const int bx = w.wx0 + i % w.nwx, by = w.wy0 + i / w.nwx;
           int jlo, jhi;
           if (block_range<DIR == DIR_B>(d, bx, by, Tx0, Tx1, Ty0, Ty1, K, jlo, jhi) && jz >= jlo &&

@@ -444,7 +444,7 @@ int evis_soft_count_backward(evis_ctx *ctx, const evis_soft_env *envs, int32_t n
  * the fraction q floored to 16 bits, 1 - q and q summed as uint32 fixed
  * point (exact and independent of event order), one float32 division per
  * voxel.  Limit: a voxel holds at most 65535 full-weight events per call
- * (beyond that its uint32 sum wraps).
+ * (beyond that its uint32 sum wraps and the grid is not defined).
  * out is [2][bins][H][W] float32, polarity 0 (OFF) first; it is also the
  * accumulator.  2 <= bins <= EVIS_MAX_VOXEL_BINS. */
 #define EVIS_MAX_VOXEL_BINS 1024

@@ -84,10 +84,10 @@ def parse():
     ap.add_argument("--variants", action="store_true",
                     help="timed loop and the variants only (for profilers)")
     ap.add_argument("--only", type=str, default=None,
-                    choices=("events_batch", "small_motion", "defocus", "voxel"),
+                    choices=("generate_events", "events_batch", "small_motion", "defocus", "voxel"),
                     help="timed loop and this one variant only (for profilers): the event model "
-                         "over every env's materialised samples, the small-motion fused step, the "
-                         "batched defocus or the voxel grid")
+                         "over one env's or every env's materialised samples, the small-motion "
+                         "fused step, the batched defocus or the voxel grid")
     ap.add_argument("--warp-steps", type=int, default=10,
                     help="timed steps of each variant: two-splat warps, noise (0 skips them)")
     ap.add_argument("--disc-steps", type=int, default=200,

@@ -295,7 +295,39 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
       pending = false;
     };
 
-    const int j_int_last = min(j_last, K - 1);   // last interior substep to build
+    // A static tile's samples are all L_A (and L_B = L_A): once a substep
+    // leaves every pixel within its thresholds of the reference, no later
+    // substep can emit (the reference moves only with a crossing), so the
+    // interior substeps stop there and the last one (which drains the
+    // crossing queue) follows.  Noise draws per substep: the noise kernel
+    // runs them all.
+    bool static_done = false;
+    if (MODE == MODE_STEP && NOISE == 0 && is_static) {   // uniform
+      uint32_t hb0[PPT];
+      float Lj[PPT];
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) hb0[k] = 0u;
+      for (int j = 1; j <= K - 1; ++j) {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) Lj[k] = LAq[k];
+        consume(j, Lj, hb0);
+        int quiet = 1;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          if ((okbits >> k) & 1u) {
+            const float dd = LAq[k] - R[k];
+            const float c = aux.c(k, dd > 0.0f);
+            if (fabsf(dd) >= c && c > 0.0f) quiet = 0;
+          }
+        }
+        if (__syncthreads_and(quiet) != 0) break;   // uniform
+      }
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) Lj[k] = LAq[k];
+      consume(K, Lj, hb0);
+      static_done = true;
+    }
+    const int j_int_last = static_done ? 0 : min(j_last, K - 1);   // last interior substep to build
     for (int j = j_first; j <= j_int_last; ++j) {
       const float f = (float)j / (float)K;
       const float g = 1.0f - f;
@@ -420,7 +452,7 @@ __global__ __launch_bounds__(kBlock, (tile_waves<TW, TH>())) void k_tile(const T
       pending = true;
     }
     if (pending) finish_pending();
-    if (j_last == K) {
+    if (j_last == K && !static_done) {
       float Lj[PPT];
       uint32_t hb[PPT];
 #pragma unroll

@@ -1,6 +1,7 @@
 """Frames that do not change: zero motion and L_B = L_A, so every tile of the
-fused step takes the static-tile path (K = 8 fixed; the path is tried for
-K > 3).  Every sample of such a tile is L_A, so once a substep leaves each
+fused step's gather warp takes the static-tile path (K = 8 fixed; the path
+is tried for K > 3); the two-splat warps, which run the full path, on the
+same frames.  Every sample of such a tile is L_A, so once a substep leaves each
 pixel within its thresholds of the reference no later substep can emit,
 and the kernel stops the tile's substeps there.  Against the oracle's full
 step: events as a multiset, reference level and last-event times bit for
@@ -45,8 +46,9 @@ def static_pair(H, W, seed):
     return o.Pair(L, L.copy(), m, m.copy(), Z, Z.copy(), 1000, 17667)
 
 
+@pytest.mark.parametrize("warp", [0, o.WARP_SPLAT, o.WARP_JOINT])
 @pytest.mark.parametrize("case", ["quiet", "offset", "offset_refractory", "capped"])
-def test_static_tiles(torch, ctx, case):
+def test_static_tiles(torch, ctx, case, warp):
     from paper_2607_08098_amd import evis
     H, W, K = 70, 100, 8
     pair = static_pair(H, W, 40)
@@ -64,16 +66,16 @@ def test_static_tiles(torch, ctx, case):
         limit = evis.EVIS_MAX_CROSSINGS
         R0[5, 7] = F32(pair.L_A[5, 7] - F32(20000.0))    # 100000 crossings at C = 0.2
         R0[40, 90] = F32(pair.L_A[40, 90] + F32(14000.0))
-    s = o.Sensor(C_on=0.2, C_off=0.2, K=K, refractory_us=refr)
+    s = o.Sensor(C_on=0.2, C_off=0.2, K=K, refractory_us=refr, blend_mode=warp)
     want, R, tl, Kw = o.step(pair, s, R0.copy(), None if tl0 is None else tl0.copy(), 6,
                              count_limit=limit)
     d = U.device_pair(pair, torch)
-    d.update(C_on=0.2, C_off=0.2, refractory_us=refr, K=K, K_max=64, blend_mode=0, env_id=6)
+    d.update(C_on=0.2, C_off=0.2, refractory_us=refr, K=K, K_max=64, blend_mode=warp, env_id=6)
     d["L_ref"] = torch.from_numpy(R0.copy()).cuda()
     d["t_last"] = None if tl0 is None else torch.from_numpy(tl0.copy()).cuda()
     out, n = evis.event_buffer(1 << 22)
     K_used = torch.zeros(1, dtype=torch.int32, device="cuda")
-    say("static tiles", case, "oracle events", len(want))
+    say("static tiles", case, hex(warp), "oracle events", len(want))
     evis.evis_step_batch(ctx, [d], out, n, K_used)
     torch.cuda.synchronize()
     ev = evis.decode_events(out, n)

@@ -84,10 +84,12 @@ def parse():
     ap.add_argument("--variants", action="store_true",
                     help="timed loop and the variants only (for profilers)")
     ap.add_argument("--only", type=str, default=None,
-                    choices=("generate_events", "events_batch", "small_motion", "defocus", "voxel"),
+                    choices=("generate_events", "events_batch", "small_motion", "defocus", "voxel",
+                             "disc512"),
                     help="timed loop and this one variant only (for profilers): the event model "
                          "over one env's or every env's materialised samples, the small-motion "
-                         "fused step, the batched defocus or the voxel grid")
+                         "fused step, the batched defocus or the voxel grid; disc512: the "
+                         "512-disc batch alone (--disc-steps pairs)")
     ap.add_argument("--warp-steps", type=int, default=10,
                     help="timed steps of each variant: two-splat warps, noise (0 skips them)")
     ap.add_argument("--disc-steps", type=int, default=200,
@@ -310,6 +312,11 @@ def main():
         copy_calibration()
         return
     ctx = evis.Context(0)
+    if args.only == "disc512":   # the 512-disc batch alone (for profilers)
+        tw, th = (int(v) for v in (args.tile or "32x16").lower().split("x"))
+        evis.evis_set_tuning(ctx, tile_w=tw, tile_h=th)
+        print(json.dumps(disc_sustained(ctx, max(1, args.disc_steps))))
+        return
     t = time.time()
     W0, S = max(1, args.warmup), args.steps
     n_kf = W0 + S + 1
